@@ -1,0 +1,245 @@
+"""FP64 CPU oracle for McMurchie-Davidson 3-/4-centre Coulomb integrals.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the GPU library (``paper_2405_01834_amd``) and the GPU library never
+imports it.
+
+This module is a thin ctypes wrapper around ``liboracle.so`` (built from
+``oracle.c`` by :func:`build`); every function of the method lives in the C
+source, which cites the equations of Sec. 2 of the paper that it follows.
+
+Basis arrays use the same plain convention as the GPU boundary: ``l[nshell]``,
+``nprim[nshell]``, concatenated ``exps`` / ``coefs`` and ``centers[nshell, 3]``
+in bohr.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+ORACLE_LMAX = 6  # public shells; derivatives use l+1 internally
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (OpenMP, -O2)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-fopenmp", "-std=c11", "-shared", "-fPIC", "-o", _SO + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd, cwd=_HERE)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_SO)
+        _setup(_lib)
+    return _lib
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def _setup(L):
+    L.oracle_boys.argtypes = [ctypes.c_int, ctypes.c_double, _dp]
+    L.oracle_E2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double, _dp]
+    L.oracle_E1.argtypes = [ctypes.c_int, ctypes.c_double, _dp]
+    L.oracle_R.argtypes = [ctypes.c_int, ctypes.c_double, _dp, ctypes.c_double, _dp]
+    L.oracle_solid.argtypes = [ctypes.c_int, _dp]
+    L.oracle_norm_coefs.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp]
+    basis = [ctypes.c_int, _ip, _ip, _dp, _dp, _dp, ctypes.c_int]
+    L.oracle_eri4_cart.argtypes = basis + [ctypes.c_int] * 4 + [_dp]
+    L.oracle_eri4_deriv.argtypes = basis + [ctypes.c_int] * 4 + [_dp]
+    L.oracle_eri4.argtypes = basis + [ctypes.c_int, _ip, ctypes.c_int, _ip, _dp, ctypes.c_int]
+    L.oracle_eri3.argtypes = [ctypes.c_int, _ip, _ip, _dp, _dp, _dp, ctypes.c_int, _ip, _ip, _dp, _dp, _dp,
+                              ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int, _ip, _dp, ctypes.c_int]
+    L.oracle_schwarz.argtypes = basis + [ctypes.c_int, _ip, _dp, ctypes.c_int]
+    L.oracle_kbuild.argtypes = basis + [_dp, ctypes.c_double, _dp, ctypes.c_int]
+    L.oracle_exchange_grad.argtypes = basis + [_ip, ctypes.c_int, _dp, ctypes.c_double, _dp, ctypes.c_int]
+    for name in ("oracle_eri4_cart", "oracle_eri4_deriv", "oracle_eri4", "oracle_eri3", "oracle_schwarz",
+                 "oracle_kbuild", "oracle_exchange_grad"):
+        getattr(L, name).restype = ctypes.c_int
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_ip)
+
+
+def nsph(l):
+    return 2 * l + 1
+
+
+def ncart(l):
+    return (l + 1) * (l + 2) // 2
+
+
+class Basis:
+    """Plain container for a shell list (host arrays)."""
+
+    def __init__(self, l, nprim, exps, coefs, centers, normalize=1):
+        self.l = np.ascontiguousarray(l, dtype=np.int32)
+        self.nprim = np.ascontiguousarray(nprim, dtype=np.int32)
+        self.exps = np.ascontiguousarray(exps, dtype=np.float64)
+        self.coefs = np.ascontiguousarray(coefs, dtype=np.float64)
+        self.centers = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+        self.normalize = int(normalize)
+        assert self.l.shape == self.nprim.shape == (self.centers.shape[0],)
+        assert self.exps.shape == self.coefs.shape == (int(self.nprim.sum()),)
+
+    @property
+    def nshell(self):
+        return int(self.l.shape[0])
+
+    def args(self):
+        return (self.nshell, self.l.ctypes.data_as(_ip), self.nprim.ctypes.data_as(_ip),
+                self.exps.ctypes.data_as(_dp), self.coefs.ctypes.data_as(_dp),
+                self.centers.ctypes.data_as(_dp), self.normalize)
+
+    def nao(self):
+        return int(np.sum(2 * self.l + 1))
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"{what} failed with code {rc}")
+
+
+def boys(mmax: int, T: float) -> np.ndarray:
+    F = np.zeros(mmax + 1)
+    lib().oracle_boys(mmax, float(T), F.ctypes.data_as(_dp))
+    return F
+
+
+def E2(la, lb, za, zb, Ax, Bx) -> np.ndarray:
+    E = np.zeros((la + 1, lb + 1, la + lb + 1))
+    lib().oracle_E2(la, lb, za, zb, Ax, Bx, E.ctypes.data_as(_dp))
+    return E
+
+
+def E1(la, za) -> np.ndarray:
+    E = np.zeros((la + 1, la + 1))
+    lib().oracle_E1(la, za, E.ctypes.data_as(_dp))
+    return E
+
+
+def R(L, rho, PQ, pref=1.0) -> np.ndarray:
+    out = np.zeros((L + 1, L + 1, L + 1))
+    pq, pqp = _d(PQ)
+    lib().oracle_R(L, rho, pqp, pref, out.ctypes.data_as(_dp))
+    return out
+
+
+def solid(l) -> np.ndarray:
+    C = np.zeros((nsph(l), ncart(l)))
+    lib().oracle_solid(l, C.ctypes.data_as(_dp))
+    return C
+
+
+def cart_list(l):
+    return [(lx, ly, l - lx - ly) for lx in range(l, -1, -1) for ly in range(l - lx, -1, -1)]
+
+
+def norm_coefs(l, exps, coefs, normalize=1) -> np.ndarray:
+    z, zp = _d(exps)
+    c, cp = _d(coefs)
+    out = np.zeros(len(z))
+    lib().oracle_norm_coefs(l, len(z), zp, cp, normalize, out.ctypes.data_as(_dp))
+    return out
+
+
+def eri4_cart(basis: Basis, i, j, k, m) -> np.ndarray:
+    ls = [int(basis.l[x]) for x in (i, j, k, m)]
+    out = np.zeros([ncart(x) for x in ls])
+    _check(lib().oracle_eri4_cart(*basis.args(), i, j, k, m, out.ctypes.data_as(_dp)), "oracle_eri4_cart")
+    return out
+
+
+def eri4_deriv(basis: Basis, i, j, k, m) -> np.ndarray:
+    """out[centre, xyz, ma, mb, mc, md]."""
+    ls = [int(basis.l[x]) for x in (i, j, k, m)]
+    out = np.zeros([4, 3] + [nsph(x) for x in ls])
+    _check(lib().oracle_eri4_deriv(*basis.args(), i, j, k, m, out.ctypes.data_as(_dp)), "oracle_eri4_deriv")
+    return out
+
+
+def eri4(basis: Basis, bra, ket, nthreads=0) -> np.ndarray:
+    """Class batch, returned as V[ij, ab, cd, kl] (numpy shape (nbra, Nab, Ncd, nket), Fortran order)."""
+    bra, brap = _i(np.asarray(bra).reshape(-1, 2))
+    ket, ketp = _i(np.asarray(ket).reshape(-1, 2))
+    la, lb = int(basis.l[bra[0, 0]]), int(basis.l[bra[0, 1]])
+    lc, ld = int(basis.l[ket[0, 0]]), int(basis.l[ket[0, 1]])
+    nab, ncd = nsph(la) * nsph(lb), nsph(lc) * nsph(ld)
+    V = np.zeros(len(bra) * nab * ncd * len(ket))
+    _check(lib().oracle_eri4(*basis.args(), len(bra), brap, len(ket), ketp, V.ctypes.data_as(_dp), nthreads),
+           "oracle_eri4")
+    return V.reshape((len(bra), nab, ncd, len(ket)), order="F")
+
+
+def eri4_shellset(basis: Basis, i, j, k, m) -> np.ndarray:
+    """One shell quartet as [ma, mb, mc, md]."""
+    V = eri4(basis, [[i, j]], [[k, m]], nthreads=1)
+    ls = [int(basis.l[x]) for x in (i, j, k, m)]
+    return V[0, :, :, 0].reshape([nsph(x) for x in ls])
+
+
+def eri3(basis: Basis, aux: Basis, pairs, auxidx, nthreads=0) -> np.ndarray:
+    """(ab|P) batch as V[ij, ab, mP, k] (shape (npair, Nab, NP, naux), Fortran order)."""
+    pairs, pp = _i(np.asarray(pairs).reshape(-1, 2))
+    auxidx, ap = _i(np.asarray(auxidx).reshape(-1))
+    la, lb = int(basis.l[pairs[0, 0]]), int(basis.l[pairs[0, 1]])
+    lc = int(aux.l[auxidx[0]])
+    nab, nc = nsph(la) * nsph(lb), nsph(lc)
+    V = np.zeros(len(pairs) * nab * nc * len(auxidx))
+    assert basis.normalize == aux.normalize
+    a = aux.args()
+    _check(lib().oracle_eri3(*basis.args()[:6], a[0], a[1], a[2], a[3], a[4], a[5], basis.normalize, len(pairs), pp,
+                             len(auxidx), ap, V.ctypes.data_as(_dp), nthreads), "oracle_eri3")
+    return V.reshape((len(pairs), nab, nc, len(auxidx)), order="F")
+
+
+def schwarz(basis: Basis, pairs, nthreads=0) -> np.ndarray:
+    pairs, pp = _i(np.asarray(pairs).reshape(-1, 2))
+    Q = np.zeros(len(pairs))
+    _check(lib().oracle_schwarz(*basis.args(), len(pairs), pp, Q.ctypes.data_as(_dp), nthreads), "oracle_schwarz")
+    return Q
+
+
+def kbuild(basis: Basis, D, tau=1e-12, nthreads=0) -> np.ndarray:
+    nao = basis.nao()
+    D, Dp = _d(D)
+    assert D.shape == (nao, nao)
+    K = np.zeros((nao, nao))
+    _check(lib().oracle_kbuild(*basis.args(), Dp, float(tau), K.ctypes.data_as(_dp), nthreads), "oracle_kbuild")
+    return K
+
+
+def exchange_grad(basis: Basis, atom_of_shell, natom, D, tau=1e-12, nthreads=0) -> np.ndarray:
+    nao = basis.nao()
+    D, Dp = _d(D)
+    assert D.shape == (nao, nao)
+    aos, aop = _i(atom_of_shell)
+    g = np.zeros((natom, 3))
+    _check(lib().oracle_exchange_grad(*basis.args(), aop, int(natom), Dp, float(tau), g.ctypes.data_as(_dp),
+                                      nthreads), "oracle_exchange_grad")
+    return g
