@@ -1,0 +1,124 @@
+/*
+ * mderi.h -- C ABI of libmderi, an MI355X (gfx950) implementation of the
+ * McMurchie-Davidson (MD) evaluation of 3-centre (ab|P) and 4-centre (ab|cd)
+ * two-electron Coulomb integrals over contracted real solid-harmonic
+ * Gaussians (Asadchev & Valeev, "3-center and 4-center 2-particle Gaussian AO
+ * integrals on modern accelerated processors").
+ *
+ * General rules for every entry point:
+ *  - extern "C"; only plain integers, doubles and pointers cross the ABI.
+ *  - Pointers named *_host are host memory and are read (or copied) before
+ *    the call returns; pointers named *_dev are device memory owned by the
+ *    caller; the library never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    device work of a call is enqueued on that stream and the call returns
+ *    without waiting for it, except where stated.
+ *  - A context owns per-device workspace (pair data, scratch), the Boys
+ *    interpolation table and the constant tables; calls that share a context
+ *    must be issued from one host thread at a time and on one stream at a
+ *    time (workspace is reused in stream order).
+ *  - Validation happens before anything is enqueued: on any error nothing is
+ *    enqueued, the status is returned and mderi_last_error() describes it.
+ *    HIP launch failures return MDERI_EDEVICE.
+ *
+ * Basis convention (Sec. 2 "Formalism"): a shell is (l, K, exponents[K],
+ * coefficients[K], centre[3] in bohr).  With normalize=1 the coefficients
+ * multiply unit-normalised primitive x^l Gaussians and the contracted shell
+ * is rescaled to unit norm; with normalize=0 they multiply bare primitives
+ * x^a y^b z^c exp(-zeta r^2).  Real solid harmonics are ordered m = -l..l
+ * and carry the norm of x^l on the sphere (p shells come out as y, z, x).
+ */
+#ifndef MDERI_H
+#define MDERI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MDERI_OK = 0,
+  MDERI_EINVAL = -1,       /* bad argument (range, null pointer, mixed classes, ...) */
+  MDERI_ENOMEM = -2,       /* device workspace could not be allocated */
+  MDERI_EUNSUPPORTED = -3, /* valid request outside what is built (l, K, class) */
+  MDERI_EDEVICE = -4,      /* HIP runtime / launch failure */
+  MDERI_ESIZE = -5         /* output buffer too small */
+} mderi_status;
+
+#define MDERI_LMAX 6  /* largest shell angular momentum */
+#define MDERI_KMAX 16 /* largest number of primitives per shell */
+
+typedef struct mderi_ctx *mderi_ctx_t;
+typedef struct mderi_basis *mderi_basis_t;
+
+/* Options shared by the compute calls; NULL means defaults. */
+typedef struct {
+  int precision;      /* 0 = FP64 (only value supported by the FP64 entry points) */
+  double schwarz_tau; /* screening threshold for the K build (default 1e-12) */
+  int reserved[4];
+} mderi_opts;
+
+/* Creates a context on HIP device `device`: uploads the Boys-function
+ * interpolation table and the constant Hermite / solid-harmonic tables.
+ * *out receives the handle. */
+mderi_status mderi_create(int device, mderi_ctx_t *out);
+
+/* Releases the context and all library-owned device memory.  NULL is a no-op. */
+void mderi_destroy(mderi_ctx_t ctx);
+
+/* Text of the last failure on the calling host thread ("" if none). */
+const char *mderi_last_error(void);
+
+/* Copies a shell list to the device (Sec. 2; see the basis convention
+ * above).  Arrays: l_host[nshell] (0..MDERI_LMAX), nprim_host[nshell]
+ * (1..MDERI_KMAX), exps_host / coefs_host concatenated over shells
+ * (sum(nprim) entries, exponents finite and > 0), centers_host[nshell][3].
+ * atom_host[nshell] maps shells to atoms (may be NULL: shell i -> atom i).
+ * Host arrays are copied before return; the call synchronises the device. */
+mderi_status mderi_basis_upload(mderi_ctx_t ctx, int nshell, const int *l_host, const int *nprim_host,
+                                const double *exps_host, const double *coefs_host, const double *centers_host,
+                                const int *atom_host, int normalize, mderi_basis_t *out);
+
+/* Releases a basis.  NULL is a no-op. */
+void mderi_basis_free(mderi_basis_t basis);
+
+/* Number of shells / AOs of a basis (AOs: sum of 2l+1 in shell order). */
+int mderi_basis_nshell(mderi_basis_t basis);
+int mderi_basis_nao(mderi_basis_t basis);
+
+/*
+ * Class batch of 4-centre integrals (Sec. 3 "MD Algorithm Variants": output
+ * layout V[ij,ab,cd,kl], column-major, ij fastest).
+ *
+ * bra_host[nbra][2] and ket_host[nket][2] are int32 shell-index pairs.  All
+ * bra pairs must share (l_a, l_b) and all ket pairs (l_c, l_d); contraction
+ * degrees may differ from pair to pair.  The call evaluates every quartet
+ * (ij, kl) of the two lists -- pair data and the Hermite->solid transform
+ * matrices H of Eqs. (solid2herm-2) included -- and writes
+ *     V_dev[ij + nbra*(ab + Nab*(cd + Ncd*kl))],
+ * ab = m_a*N(l_b) + m_b, cd = m_c*N(l_d) + m_d (0-based component indices,
+ * N(l) = 2l+1).  V_elems is the capacity of V_dev in doubles and must be at
+ * least nbra*Nab*Ncd*nket.  Contracted over all primitive quartets in FP64.
+ */
+mderi_status mderi_eri4(mderi_ctx_t ctx, mderi_basis_t basis, int nbra, const int32_t *bra_host, int nket,
+                        const int32_t *ket_host, double *V_dev, size_t V_elems, const mderi_opts *opts,
+                        void *stream);
+
+/*
+ * Schwarz factors Q_ij = sqrt(max_ab |(ab|ab)|) of shell pairs, from the
+ * diagonal quartets (ij|ij) evaluated by the same MD path as mderi_eri4.
+ * Screening (not defined in the paper beyond the remark in Sec. 3 that
+ * screening makes pair lists sparse) keeps a pair when Q_ij * Q_max >= tau
+ * and a quartet when Q_ij * Q_kl >= tau.
+ * pairs_host[npair][2] are int32 shell indices of any mix of classes;
+ * Q_dev[npair] (device, doubles) receives the factors in input order.
+ */
+mderi_status mderi_schwarz(mderi_ctx_t ctx, mderi_basis_t basis, int npair, const int32_t *pairs_host, double *Q_dev,
+                           void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

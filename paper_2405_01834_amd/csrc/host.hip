@@ -1,0 +1,602 @@
+// host.hip -- the C ABI of libmderi: contexts, basis upload, validation,
+// class-batch planning and kernel dispatch.  Constant tables (Boys grid,
+// Hermite order, Cartesian->solid coefficients) are generated here on the
+// host from their mathematical definitions and uploaded once per context.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace mderi;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static mderi_status fail(mderi_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(MDERI_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" const char *mderi_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// constant tables
+// ---------------------------------------------------------------------------
+namespace {
+
+// Hermite functions (t,u,v) ordered by total degree, then t descending,
+// then u descending.
+std::vector<uint32_t> hermite_order() {
+  std::vector<uint32_t> h;
+  h.reserve(kNtilMax);
+  for (int n = 0; n <= kLtotMax; ++n)
+    for (int t = n; t >= 0; --t)
+      for (int u = n - t; u >= 0; --u) h.push_back(pack3(t, u, n - t - u));
+  return h;
+}
+
+// Real regular solid harmonics S_lm (S_00 = 1, same norm on the sphere as
+// x^l) from the standard recurrences
+//   S_{l+1,l+1}  = sqrt(2^{d(l,0)} (2l+1)/(2l+2)) (x S_{ll} - (1-d(l,0)) y S_{l,-l})
+//   S_{l+1,-l-1} = sqrt(2^{d(l,0)} (2l+1)/(2l+2)) (y S_{ll} + (1-d(l,0)) x S_{l,-l})
+//   S_{l+1,m}    = ((2l+1) z S_{lm} - sqrt((l+m)(l-m)) r^2 S_{l-1,m}) / sqrt((l+m+1)(l-m+1))
+// Polynomials are dense coefficient arrays over monomials x^a y^b z^c of
+// one degree, indexed by (a, b).
+struct Poly {
+  int deg = 0;
+  std::vector<long double> c;  // [(deg+1)*(deg+1)], entry a*(deg+1)+b, c = deg-a-b
+  explicit Poly(int d = 0) : deg(d), c((size_t)(d + 1) * (d + 1), 0.0L) {}
+  long double &at(int a, int b) { return c[(size_t)a * (deg + 1) + b]; }
+  long double get(int a, int b) const { return c[(size_t)a * (deg + 1) + b]; }
+};
+Poly mul_xyz(const Poly &p, int axis) {
+  Poly r(p.deg + 1);
+  for (int a = 0; a <= p.deg; ++a)
+    for (int b = 0; a + b <= p.deg; ++b) {
+      const long double v = p.get(a, b);
+      if (v == 0.0L) continue;
+      if (axis == 0) r.at(a + 1, b) += v;
+      else if (axis == 1) r.at(a, b + 1) += v;
+      else r.at(a, b) += v;
+    }
+  return r;
+}
+Poly mul_r2(const Poly &p) {
+  Poly r(p.deg + 2);
+  for (int a = 0; a <= p.deg; ++a)
+    for (int b = 0; a + b <= p.deg; ++b) {
+      const long double v = p.get(a, b);
+      if (v == 0.0L) continue;
+      r.at(a + 2, b) += v;
+      r.at(a, b + 2) += v;
+      r.at(a, b) += v;
+    }
+  return r;
+}
+Poly axpby(long double x, const Poly &p, long double y, const Poly &q) {
+  Poly r(p.deg);
+  for (size_t i = 0; i < r.c.size(); ++i) r.c[i] = x * p.c[i] + y * q.c[i];
+  return r;
+}
+
+// S[l][m+l] for l <= lmax
+std::vector<std::vector<Poly>> solid_harmonics(int lmax) {
+  std::vector<std::vector<Poly>> S(lmax + 1);
+  S[0].push_back(Poly(0));
+  S[0][0].at(0, 0) = 1.0L;
+  for (int l = 0; l < lmax; ++l) {
+    std::vector<Poly> nx(2 * l + 3, Poly(l + 1));
+    const long double f = sqrtl((l == 0 ? 2.0L : 1.0L) * (2 * l + 1) / (2.0L * l + 2.0L));
+    const Poly &Sll = S[l][2 * l], &Slml = S[l][0];
+    if (l == 0) {
+      nx[2 * l + 2] = axpby(f, mul_xyz(Sll, 0), 0.0L, mul_xyz(Sll, 0));
+      nx[0] = axpby(f, mul_xyz(Sll, 1), 0.0L, mul_xyz(Sll, 1));
+    } else {
+      nx[2 * l + 2] = axpby(f, mul_xyz(Sll, 0), -f, mul_xyz(Slml, 1));
+      nx[0] = axpby(f, mul_xyz(Sll, 1), f, mul_xyz(Slml, 0));
+    }
+    for (int m = -l; m <= l; ++m) {
+      Poly zs = mul_xyz(S[l][m + l], 2);
+      Poly t(l + 1);
+      if (l >= 1 && m >= -(l - 1) && m <= l - 1) t = mul_r2(S[l - 1][m + l - 1]);
+      const long double den = sqrtl((long double)(l + m + 1) * (l - m + 1));
+      const long double s = sqrtl((long double)(l + m) * (l - m));
+      nx[m + l + 1] = axpby((2 * l + 1) / den, zs, -s / den, t);
+    }
+    S[l + 1] = nx;
+  }
+  return S;
+}
+
+// Boys table F_m(T_i) in long double: positive-term series for the largest
+// m, F_m(T) = e^{-T} sum_k (2T)^k / [(2m+1)(2m+3)...(2m+2k+1)], then the
+// downward recursion F_m = (2T F_{m+1} + e^{-T}) / (2m+1).
+std::vector<double> boys_table() {
+  std::vector<double> tab((size_t)kBoysNgrid * kBoysM);
+  const int M = kBoysM - 1;
+  for (int i = 0; i < kBoysNgrid; ++i) {
+    const long double T = (long double)i / kBoysGridPerUnit;
+    const long double et = expl(-T);
+    long double term = 1.0L / (2 * M + 1), sum = term;
+    for (int k = 1; k < 10000; ++k) {
+      term *= 2.0L * T / (2 * M + 2 * k + 1);
+      sum += term;
+      if (k > T && term < 1e-24L * sum) break;
+    }
+    long double f = et * sum;
+    tab[(size_t)i * kBoysM + M] = (double)f;
+    for (int m = M - 1; m >= 0; --m) {
+      f = (2.0L * T * f + et) / (2 * m + 1);
+      tab[(size_t)i * kBoysM + m] = (double)f;
+    }
+  }
+  return tab;
+}
+
+double dfact_odd(int n) {
+  double r = 1.0;
+  for (int i = n; i > 1; i -= 2) r *= i;
+  return r;
+}
+
+template <class T>
+hipError_t upload(T **dst, const std::vector<T> &src) {
+  hipError_t e = hipMalloc((void **)dst, sizeof(T) * (src.empty() ? 1 : src.size()));
+  if (e != hipSuccess) return e;
+  if (src.empty()) return hipSuccess;
+  return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+enum WsSlot {
+  WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_COUNT
+};
+
+struct mderi_ctx {
+  int device = 0;
+  Tables tab;
+  void *ws[WS_COUNT] = {};
+  size_t ws_cap[WS_COUNT] = {};
+  // pinned staging for per-call host->device uploads, guarded by an event
+  char *stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
+};
+
+struct mderi_basis {
+  mderi_ctx *ctx = nullptr;
+  int nshell = 0, nao = 0;
+  std::vector<int> l, K, poff, atom;
+  DevBasis dev;
+};
+
+static mderi_status ws_get(mderi_ctx *c, int slot, size_t bytes, void **out) {
+  if (bytes == 0) bytes = 16;
+  if (c->ws_cap[slot] < bytes) {
+    if (c->ws[slot]) {
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipFree(c->ws[slot]));
+      c->ws[slot] = nullptr;
+      c->ws_cap[slot] = 0;
+    }
+    const size_t cap = bytes + bytes / 4;
+    if (hipMalloc(&c->ws[slot], cap) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MDERI_ENOMEM, "device workspace of %zu bytes could not be allocated", cap);
+    }
+    c->ws_cap[slot] = cap;
+  }
+  *out = c->ws[slot];
+  return MDERI_OK;
+}
+
+// Copies `n` host bytes to device `dst` on `s` through the pinned staging
+// buffer (reused only after the previous copy has completed).
+static mderi_status stage_copy(mderi_ctx *c, void *dst, const void *src, size_t n, hipStream_t s, size_t *used) {
+  if (*used + n > c->stage_cap) return fail(MDERI_EINVAL, "internal: staging overflow");
+  memcpy(c->stage + *used, src, n);
+  HIP_TRY(hipMemcpyAsync(dst, c->stage + *used, n, hipMemcpyHostToDevice, s));
+  *used += (n + 255) & ~(size_t)255;
+  return MDERI_OK;
+}
+
+static mderi_status stage_begin(mderi_ctx *c, size_t need) {
+  if (c->stage_pending) {
+    HIP_TRY(hipEventSynchronize(c->stage_done));
+    c->stage_pending = false;
+  }
+  if (need > c->stage_cap) {
+    if (c->stage) HIP_TRY(hipHostFree(c->stage));
+    c->stage = nullptr;
+    const size_t cap = need + need / 2 + 4096;
+    HIP_TRY(hipHostMalloc((void **)&c->stage, cap, hipHostMallocDefault));
+    c->stage_cap = cap;
+  }
+  return MDERI_OK;
+}
+
+static mderi_status stage_end(mderi_ctx *c, hipStream_t s) {
+  HIP_TRY(hipEventRecord(c->stage_done, s));
+  c->stage_pending = true;
+  return MDERI_OK;
+}
+
+extern "C" mderi_status mderi_create(int device, mderi_ctx_t *out) {
+  if (!out) return fail(MDERI_EINVAL, "mderi_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(MDERI_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(MDERI_EINVAL, "device %d out of range [0,%d)", device, ndev);
+  HIP_TRY(hipSetDevice(device));
+  mderi_ctx *c = new mderi_ctx;
+  c->device = device;
+
+  std::vector<uint32_t> herm = hermite_order();
+  std::vector<double> boys = boys_table();
+  auto S = solid_harmonics(kLshell);
+  // nonzeros of slot s = l*(2*kLshell+1) + (m+l) occupy [sstart[s], sstart[s+1])
+  std::vector<int> sstart(kSolidSlots, 0);
+  std::vector<double> scoef;
+  std::vector<uint32_t> scart;
+  for (int sl = 0; sl < kSolidSlots - 1; ++sl) {
+    sstart[sl] = (int)scoef.size();
+    const int l = sl / (2 * kLshell + 1), mm = sl % (2 * kLshell + 1);
+    if (mm > 2 * l) continue;
+    long double mx = 0.0L;
+    for (auto &pl : S[l])
+      for (long double v : pl.c) mx = fmaxl(mx, fabsl(v));
+    const Poly &p = S[l][mm];
+    for (int a = l; a >= 0; --a)
+      for (int bb = l - a; bb >= 0; --bb) {
+        const long double v = p.get(a, bb);
+        if (fabsl(v) > 1e-13L * mx) {
+          scoef.push_back((double)v);
+          scart.push_back(pack3(a, bb, l - a - bb));
+        }
+      }
+  }
+  sstart[kSolidSlots - 1] = (int)scoef.size();
+  hipError_t e;
+  if ((e = upload(&c->tab.herm, herm)) != hipSuccess || (e = upload(&c->tab.boys, boys)) != hipSuccess ||
+      (e = upload(&c->tab.solid_start, sstart)) != hipSuccess || (e = upload(&c->tab.solid_coef, scoef)) != hipSuccess ||
+      (e = upload(&c->tab.solid_cart, scart)) != hipSuccess) {
+    mderi_destroy(c);
+    return fail(MDERI_EDEVICE, "table upload failed: %s", hipGetErrorString(e));
+  }
+  if ((e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming)) != hipSuccess) {
+    mderi_destroy(c);
+    return fail(MDERI_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  g_err.clear();
+  return MDERI_OK;
+}
+
+extern "C" void mderi_destroy(mderi_ctx_t c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(c->tab.boys);
+  (void)hipFree(c->tab.herm);
+  (void)hipFree(c->tab.solid_start);
+  (void)hipFree(c->tab.solid_coef);
+  (void)hipFree(c->tab.solid_cart);
+  for (int i = 0; i < WS_COUNT; ++i) (void)hipFree(c->ws[i]);
+  if (c->stage) (void)hipHostFree(c->stage);
+  if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  delete c;
+}
+
+// ---------------------------------------------------------------------------
+// basis
+// ---------------------------------------------------------------------------
+extern "C" mderi_status mderi_basis_upload(mderi_ctx_t c, int nshell, const int *l, const int *nprim,
+                                           const double *exps, const double *coefs, const double *centers,
+                                           const int *atom, int normalize, mderi_basis_t *out) {
+  if (!c || !out) return fail(MDERI_EINVAL, "mderi_basis_upload: NULL context or out");
+  *out = nullptr;
+  if (nshell <= 0) return fail(MDERI_EINVAL, "nshell must be positive (got %d)", nshell);
+  if (!l || !nprim || !exps || !coefs || !centers) return fail(MDERI_EINVAL, "mderi_basis_upload: NULL array");
+  mderi_basis *b = new mderi_basis;
+  b->ctx = c;
+  b->nshell = nshell;
+  b->l.assign(l, l + nshell);
+  b->K.assign(nprim, nprim + nshell);
+  b->poff.resize(nshell);
+  b->atom.resize(nshell);
+  int np = 0;
+  for (int i = 0; i < nshell; ++i) {
+    if (l[i] < 0 || l[i] > kLmax) {
+      delete b;
+      return fail(MDERI_EUNSUPPORTED, "shell %d: l=%d outside [0,%d]", i, l[i], kLmax);
+    }
+    if (nprim[i] < 1 || nprim[i] > MDERI_KMAX) {
+      delete b;
+      return fail(MDERI_EUNSUPPORTED, "shell %d: %d primitives outside [1,%d]", i, nprim[i], MDERI_KMAX);
+    }
+    b->poff[i] = np;
+    np += nprim[i];
+    b->nao += 2 * l[i] + 1;
+    b->atom[i] = atom ? atom[i] : i;
+    for (int x = 0; x < 3; ++x)
+      if (!std::isfinite(centers[3 * i + x])) {
+        delete b;
+        return fail(MDERI_EINVAL, "shell %d: non-finite centre", i);
+      }
+  }
+  std::vector<double> cn(np), ex(exps, exps + np);
+  for (int i = 0; i < nshell; ++i) {
+    const int L = l[i], K = nprim[i], o = b->poff[i];
+    for (int k = 0; k < K; ++k)
+      if (!(std::isfinite(exps[o + k]) && exps[o + k] > 0.0) || !std::isfinite(coefs[o + k])) {
+        delete b;
+        return fail(MDERI_EINVAL, "shell %d primitive %d: exponent must be finite and > 0, coefficient finite", i, k);
+      }
+    if (!normalize) {
+      for (int k = 0; k < K; ++k) cn[o + k] = coefs[o + k];
+      continue;
+    }
+    // unit-normalised primitives x^l e^{-z r^2}: (2z/pi)^{3/4} (4z)^{l/2} / sqrt((2l-1)!!),
+    // then the contraction rescaled to unit norm; two such primitives on one
+    // centre overlap by (2 sqrt(z z') / (z + z'))^{l + 3/2}.
+    double norm2 = 0.0;
+    for (int k = 0; k < K; ++k)
+      for (int kk = 0; kk < K; ++kk) {
+        const double zk = exps[o + k], zkk = exps[o + kk];
+        norm2 += coefs[o + k] * coefs[o + kk] * std::pow(2.0 * std::sqrt(zk * zkk) / (zk + zkk), L + 1.5);
+      }
+    if (!(norm2 > 0.0)) {
+      delete b;
+      return fail(MDERI_EINVAL, "shell %d: contraction has zero norm", i);
+    }
+    const double inv = 1.0 / std::sqrt(norm2);
+    for (int k = 0; k < K; ++k) {
+      const double z = exps[o + k];
+      cn[o + k] = inv * coefs[o + k] * std::pow(2.0 * z / M_PI, 0.75) * std::pow(4.0 * z, 0.5 * L) /
+                  std::sqrt(dfact_odd(2 * L - 1));
+    }
+  }
+  hipError_t e = hipSetDevice(c->device);
+  std::vector<double> cen(centers, centers + 3 * nshell);
+  b->dev.nshell = nshell;
+  b->dev.nprim = np;
+  if (e == hipSuccess) e = upload(&b->dev.l, b->l);
+  if (e == hipSuccess) e = upload(&b->dev.K, b->K);
+  if (e == hipSuccess) e = upload(&b->dev.poff, b->poff);
+  if (e == hipSuccess) e = upload(&b->dev.atom, b->atom);
+  if (e == hipSuccess) e = upload(&b->dev.centers, cen);
+  if (e == hipSuccess) e = upload(&b->dev.exps, ex);
+  if (e == hipSuccess) e = upload(&b->dev.coefs, cn);
+  if (e != hipSuccess) {
+    mderi_basis_free(b);
+    return fail(MDERI_EDEVICE, "basis upload: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return MDERI_OK;
+}
+
+extern "C" void mderi_basis_free(mderi_basis_t b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(b->dev.l);
+  (void)hipFree(b->dev.K);
+  (void)hipFree(b->dev.poff);
+  (void)hipFree(b->dev.atom);
+  (void)hipFree(b->dev.centers);
+  (void)hipFree(b->dev.exps);
+  (void)hipFree(b->dev.coefs);
+  delete b;
+}
+
+extern "C" int mderi_basis_nshell(mderi_basis_t b) { return b ? b->nshell : 0; }
+extern "C" int mderi_basis_nao(mderi_basis_t b) { return b ? b->nao : 0; }
+
+// ---------------------------------------------------------------------------
+// class batches
+// ---------------------------------------------------------------------------
+namespace {
+
+// Validates a pair list of one class and expands it into primitive pairs.
+mderi_status expand_pairs(const mderi_basis *b, int n, const int32_t *pairs, const char *what, int *la, int *lb,
+                          std::vector<PrimPair> &pp, std::vector<int> &off) {
+  if (n <= 0) return fail(MDERI_EINVAL, "%s: need at least one pair (got %d)", what, n);
+  if (!pairs) return fail(MDERI_EINVAL, "%s: NULL pair list", what);
+  pp.clear();
+  off.assign(1, 0);
+  for (int i = 0; i < n; ++i) {
+    const int s0 = pairs[2 * i], s1 = pairs[2 * i + 1];
+    if (s0 < 0 || s0 >= b->nshell || s1 < 0 || s1 >= b->nshell)
+      return fail(MDERI_EINVAL, "%s: pair %d = (%d,%d) out of range [0,%d)", what, i, s0, s1, b->nshell);
+    if (i == 0) {
+      *la = b->l[s0];
+      *lb = b->l[s1];
+    } else if (b->l[s0] != *la || b->l[s1] != *lb) {
+      return fail(MDERI_EINVAL, "%s: pair %d has class (%d,%d) but the batch is (%d,%d)", what, i, b->l[s0],
+                  b->l[s1], *la, *lb);
+    }
+    for (int ka = 0; ka < b->K[s0]; ++ka)
+      for (int kb = 0; kb < b->K[s1]; ++kb) pp.push_back(PrimPair{s0, s1, b->poff[s0] + ka, b->poff[s1] + kb});
+    off.push_back((int)pp.size());
+  }
+  return MDERI_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Enqueues pair data (bra and ket) and the fused kernel for one class batch.
+// diag != 0 evaluates only (ij|ij) (bra list == ket list) and writes the
+// diagonal [ij][ab] to V.
+mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb, int lc, int ld,
+                             const std::vector<PrimPair> &ppb, const std::vector<int> &offb,
+                             const std::vector<PrimPair> &ppk, const std::vector<int> &offk, int diag, double *V,
+                             const std::vector<int> *extra_idx, void **d_extra_idx, hipStream_t s) {
+  const int nbra = (int)offb.size() - 1, nket = (int)offk.size() - 1;
+  const int Lb = la + lb, Lk = lc + ld, L = Lb + Lk;
+  const int Nb = nsph(la) * nsph(lb), Nk = nsph(lc) * nsph(ld);
+  const int Nhb = ntil(Lb), Nhk = ntil(Lk);
+  int npt = 0, nat = 0;
+  if (!eri4_pick_tiles(round16(Nhb) / 16, round16(Nb) / 16, &npt, &nat) || round16(Nk) / 16 > 6)
+    return fail(MDERI_EUNSUPPORTED, "class (%d%d|%d%d) is beyond the fused kernel's tiles", la, lb, lc, ld);
+  const int Nhb_pad = 16 * npt, Nb_pad = 16 * nat, Nhk_pad = round16(Nhk), Nk_pad = round16(Nk);
+  mderi_status st;
+  void *d_ppb, *d_ppk, *d_offb, *d_offk, *d_Gb, *d_Gk, *d_Hb, *d_Hk;
+  if ((st = ws_get(c, WS_PP_BRA, sizeof(PrimPair) * ppb.size(), &d_ppb)) ||
+      (st = ws_get(c, WS_PP_KET, sizeof(PrimPair) * ppk.size(), &d_ppk)) ||
+      (st = ws_get(c, WS_OFF_BRA, sizeof(int) * offb.size(), &d_offb)) ||
+      (st = ws_get(c, WS_OFF_KET, sizeof(int) * offk.size(), &d_offk)) ||
+      (st = ws_get(c, WS_G_BRA, sizeof(double) * 4 * ppb.size(), &d_Gb)) ||
+      (st = ws_get(c, WS_G_KET, sizeof(double) * 4 * ppk.size(), &d_Gk)) ||
+      (st = ws_get(c, WS_H_BRA, sizeof(double) * (size_t)Nhb_pad * Nb_pad * ppb.size(), &d_Hb)) ||
+      (st = ws_get(c, WS_H_KET, sizeof(double) * (size_t)Nhk_pad * Nk_pad * ppk.size(), &d_Hk)))
+    return st;
+  if (extra_idx && (st = ws_get(c, WS_IDX, sizeof(int) * extra_idx->size(), d_extra_idx))) return st;
+  const size_t stage_need = sizeof(PrimPair) * (ppb.size() + ppk.size()) + sizeof(int) * (offb.size() + offk.size()) +
+                            (extra_idx ? sizeof(int) * extra_idx->size() : 0) + 5 * 256;
+  if ((st = stage_begin(c, stage_need))) return st;
+  size_t used = 0;
+  if ((st = stage_copy(c, d_ppb, ppb.data(), sizeof(PrimPair) * ppb.size(), s, &used)) ||
+      (st = stage_copy(c, d_ppk, ppk.data(), sizeof(PrimPair) * ppk.size(), s, &used)) ||
+      (st = stage_copy(c, d_offb, offb.data(), sizeof(int) * offb.size(), s, &used)) ||
+      (st = stage_copy(c, d_offk, offk.data(), sizeof(int) * offk.size(), s, &used)))
+    return st;
+  if (extra_idx && (st = stage_copy(c, *d_extra_idx, extra_idx->data(), sizeof(int) * extra_idx->size(), s, &used)))
+    return st;
+  if ((st = stage_end(c, s))) return st;
+
+  PairArgs pa{};
+  pa.basis = b->dev;
+  pa.tab = c->tab;
+  pa.npp = (int)ppb.size();
+  pa.pp = (const PrimPair *)d_ppb;
+  pa.la = la;
+  pa.lb = lb;
+  pa.Nh = Nhb;
+  pa.N = Nb;
+  pa.Nh_pad = Nhb_pad;
+  pa.N_pad = Nb_pad;
+  pa.ket_sign = 0;
+  pa.G = (double *)d_Gb;
+  pa.H = (double *)d_Hb;
+  HIP_TRY(launch_pairs(pa, s));
+  pa.npp = (int)ppk.size();
+  pa.pp = (const PrimPair *)d_ppk;
+  pa.la = lc;
+  pa.lb = ld;
+  pa.Nh = Nhk;
+  pa.N = Nk;
+  pa.Nh_pad = Nhk_pad;
+  pa.N_pad = Nk_pad;
+  pa.ket_sign = 1;
+  pa.G = (double *)d_Gk;
+  pa.H = (double *)d_Hk;
+  HIP_TRY(launch_pairs(pa, s));
+
+  Eri4Args ea{};
+  ea.nbra = nbra;
+  ea.nket = nket;
+  ea.L = L;
+  ea.Nhb = Nhb;
+  ea.Nhk = Nhk;
+  ea.Nb = Nb;
+  ea.Nk = Nk;
+  ea.Nhb_pad = Nhb_pad;
+  ea.Nhk_pad = Nhk_pad;
+  ea.Nb_pad = Nb_pad;
+  ea.Nk_pad = Nk_pad;
+  ea.npt = npt;
+  ea.nat = nat;
+  ea.levn = rr_level_stride(L);
+  ea.diag = diag;
+  ea.bra_off = (const int *)d_offb;
+  ea.ket_off = (const int *)d_offk;
+  ea.bra_G = (const double *)d_Gb;
+  ea.ket_G = (const double *)d_Gk;
+  ea.bra_H = (const double *)d_Hb;
+  ea.ket_H = (const double *)d_Hk;
+  ea.tab = c->tab;
+  ea.V = V;
+  HIP_TRY(launch_eri4(ea, s));
+  return MDERI_OK;
+}
+
+}  // namespace
+
+extern "C" mderi_status mderi_eri4(mderi_ctx_t c, mderi_basis_t b, int nbra, const int32_t *bra, int nket,
+                                   const int32_t *ket, double *V, size_t V_elems, const mderi_opts *opts,
+                                   void *stream) {
+  if (!c || !b) return fail(MDERI_EINVAL, "mderi_eri4: NULL context or basis");
+  if (b->ctx != c) return fail(MDERI_EINVAL, "mderi_eri4: basis belongs to another context");
+  if (opts && opts->precision != 0) return fail(MDERI_EUNSUPPORTED, "mderi_eri4: precision %d", opts->precision);
+  int la, lb, lc, ld;
+  std::vector<PrimPair> ppb, ppk;
+  std::vector<int> offb, offk;
+  mderi_status st;
+  if ((st = expand_pairs(b, nbra, bra, "bra", &la, &lb, ppb, offb)) != MDERI_OK) return st;
+  if ((st = expand_pairs(b, nket, ket, "ket", &lc, &ld, ppk, offk)) != MDERI_OK) return st;
+  const size_t need = (size_t)nbra * nsph(la) * nsph(lb) * nsph(lc) * nsph(ld) * nket;
+  if (!V) return fail(MDERI_EINVAL, "mderi_eri4: NULL output");
+  if (V_elems < need) return fail(MDERI_ESIZE, "mderi_eri4: output holds %zu doubles, needs %zu", V_elems, need);
+  HIP_TRY(hipSetDevice(c->device));
+  return run_class_batch(c, b, la, lb, lc, ld, ppb, offb, ppk, offk, 0, V, nullptr, nullptr, (hipStream_t)stream);
+}
+
+extern "C" mderi_status mderi_schwarz(mderi_ctx_t c, mderi_basis_t b, int npair, const int32_t *pairs, double *Q,
+                                      void *stream) {
+  if (!c || !b) return fail(MDERI_EINVAL, "mderi_schwarz: NULL context or basis");
+  if (b->ctx != c) return fail(MDERI_EINVAL, "mderi_schwarz: basis belongs to another context");
+  if (npair <= 0 || !pairs) return fail(MDERI_EINVAL, "mderi_schwarz: need a non-empty pair list");
+  if (!Q) return fail(MDERI_EINVAL, "mderi_schwarz: NULL output");
+  for (int i = 0; i < npair; ++i)
+    if (pairs[2 * i] < 0 || pairs[2 * i] >= b->nshell || pairs[2 * i + 1] < 0 || pairs[2 * i + 1] >= b->nshell)
+      return fail(MDERI_EINVAL, "mderi_schwarz: pair %d = (%d,%d) out of range", i, pairs[2 * i], pairs[2 * i + 1]);
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  // group by class (la, lb)
+  std::vector<std::vector<int>> groups((kLmax + 1) * (kLmax + 1));
+  for (int i = 0; i < npair; ++i) groups[b->l[pairs[2 * i]] * (kLmax + 1) + b->l[pairs[2 * i + 1]]].push_back(i);
+  mderi_status st;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const std::vector<int> &grp = groups[gi];
+    if (grp.empty()) continue;
+    std::vector<int32_t> sub(2 * grp.size());
+    for (size_t k = 0; k < grp.size(); ++k) {
+      sub[2 * k] = pairs[2 * grp[k]];
+      sub[2 * k + 1] = pairs[2 * grp[k] + 1];
+    }
+    int la, lb;
+    std::vector<PrimPair> pp;
+    std::vector<int> off;
+    if ((st = expand_pairs(b, (int)grp.size(), sub.data(), "pairs", &la, &lb, pp, off)) != MDERI_OK) return st;
+    const int Nab = nsph(la) * nsph(lb);
+    void *d_diag, *d_idx = nullptr;
+    if ((st = ws_get(c, WS_DIAG, sizeof(double) * grp.size() * Nab, &d_diag))) return st;
+    if ((st = run_class_batch(c, b, la, lb, la, lb, pp, off, pp, off, 1, (double *)d_diag, &grp, &d_idx, s)))
+      return st;
+    HIP_TRY(launch_schwarz_reduce((int)grp.size(), Nab, (const double *)d_diag, (const int *)d_idx, Q, s));
+  }
+  return MDERI_OK;
+}

@@ -1,0 +1,108 @@
+// internal.h -- definitions shared by the host code and the HIP kernels of
+// libmderi (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mderi.h"
+
+namespace mderi {
+
+constexpr int kLmax = MDERI_LMAX;       // largest shell l
+constexpr int kLshell = kLmax + 1;      // l+1 shells appear in derivatives
+constexpr int kLtotMax = 4 * kLshell;   // largest total L = la+lb+lc+ld
+constexpr int kNtilMax = (kLtotMax + 1) * (kLtotMax + 2) * (kLtotMax + 3) / 6;
+
+// Boys-function interpolation table: F_m(T_i), T_i = i/16 for i = 0..640
+// (T <= 40), m = 0..33, stored row-major [i][m].  Evaluated on the host in
+// long double from the positive-term series of F_mmax and downward
+// recursion; see boys_table() in host.hip.
+constexpr int kBoysM = 34;
+constexpr int kBoysGridPerUnit = 16;
+constexpr double kBoysTmax = 40.0;
+constexpr int kBoysNgrid = 641;
+constexpr int kBoysTaylor = 8;  // Taylor terms around the nearest grid point
+
+// Number of Hermite functions of total degree <= l.
+__host__ __device__ constexpr int ntil(int l) { return (l + 1) * (l + 2) * (l + 3) / 6; }
+// Number of solid harmonics of one shell.
+__host__ __device__ constexpr int nsph(int l) { return 2 * l + 1; }
+__host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+__host__ __device__ constexpr int round16(int n) { return (n + 15) & ~15; }
+
+// Packed Hermite / Cartesian triple.
+__host__ __device__ inline uint32_t pack3(int t, int u, int v) {
+  return (uint32_t)t | ((uint32_t)u << 8) | ((uint32_t)v << 16);
+}
+
+// Constant device tables owned by a context.
+struct Tables {
+  double *boys = nullptr;        // [kBoysNgrid][kBoysM]
+  uint32_t *herm = nullptr;      // [kNtilMax] (t,u,v), ordered by degree, then t desc, then u desc
+  int *solid_start = nullptr;    // [(kLshell+1)*(2*kLshell+1) + 1]: nonzeros of (l, m) start at
+                                 //   solid_start[l*(2*kLshell+1) + (m+l)]
+  double *solid_coef = nullptr;  // nonzero Cartesian->solid coefficients
+  uint32_t *solid_cart = nullptr;// matching Cartesian exponents (packed)
+};
+__host__ __device__ inline int solid_slot(int l, int m) { return l * (2 * kLshell + 1) + (m + l); }
+constexpr int kSolidSlots = (kLshell + 1) * (2 * kLshell + 1) + 1;
+
+// Primitive-pair descriptor built on the host for a class batch.
+struct PrimPair {
+  int sa, sb;  // shell indices
+  int pa, pb;  // global primitive indices (into the basis exponent / coefficient arrays)
+};
+
+// Device copy of a basis.
+struct DevBasis {
+  int nshell = 0, nprim = 0;
+  int *l = nullptr, *K = nullptr, *poff = nullptr, *atom = nullptr;
+  double *centers = nullptr;  // [nshell][3]
+  double *exps = nullptr;     // [nprim]
+  double *coefs = nullptr;    // [nprim], normalised contraction coefficients
+};
+
+// Arguments of the pair-data kernel (Sec. 3: pair data G and transform
+// matrices H, stored contiguously per (pair, primitive)).
+struct PairArgs {
+  int npp;
+  const PrimPair *pp;
+  DevBasis basis;
+  int la, lb;
+  int Nh, N, Nh_pad, N_pad;
+  int ket_sign;  // fold (-1)^{|q|} of Eq. (pq) into a ket transform matrix
+  Tables tab;
+  double *G;  // [npp][4] : zeta_p, P_x, P_y, P_z
+  double *H;  // [npp][Nh_pad][N_pad]
+};
+
+// Arguments of the fused 4-centre kernel.
+struct Eri4Args {
+  int nbra, nket;
+  int L, Nhb, Nhk, Nb, Nk;
+  int Nhb_pad, Nhk_pad, Nb_pad, Nk_pad;
+  int npt, nat;  // register tile: bra p tiles and ab tiles (Nhb_pad = 16 npt, Nb_pad = 16 nat)
+  int levn;      // stride of one R-recursion level buffer (doubles)
+  int diag;      // Schwarz mode: quartets (ij|ij) only, V receives the diagonal [ij][ab]
+  const int *bra_off, *ket_off;  // [n+1] primitive-pair offsets per shell pair
+  const double *bra_G, *ket_G;
+  const double *bra_H, *ket_H;
+  Tables tab;
+  double *V;
+};
+
+// Launchers (defined in the .hip files).
+hipError_t launch_pairs(const PairArgs &a, hipStream_t s);
+hipError_t launch_eri4(const Eri4Args &a, hipStream_t s);
+// Q[idx[n]] = sqrt(max_ab |D[n][ab]|) for n < npair (Schwarz factors).
+hipError_t launch_schwarz_reduce(int npair, int Nab, const double *D, const int *idx, double *Q, hipStream_t s);
+// Chooses the register tile (p tiles, ab tiles) of the 4-centre kernel for a
+// bra side needing npt x nat tiles; false if none is built.
+bool eri4_pick_tiles(int npt, int nat, int *NPT, int *NAT);
+// LDS bytes needed by the 4-centre kernel for total angular momentum L.
+size_t eri4_lds_bytes(int L, int Nhk_pad, int levn);
+// Stride of a level buffer of the R recursion.
+int rr_level_stride(int L);
+
+}  // namespace mderi

@@ -1,0 +1,105 @@
+// pairs.hip -- primitive-pair data G and Hermite->solid transform matrices H
+// for one class batch of shell pairs.
+//
+// For each primitive pair of shells (a, b) with exponents za, zb:
+//   zeta_p = za + zb, P = (za A + zb B) / zeta_p                  (Sec. 2)
+//   E^t_{ij} per axis by Eqs. (E2rr1)-(E2-abp), E^0_00 = exp(-mu X_AB^2)
+//   H[p][ab] = c_a c_b sum_{a,b Cartesian} C_{l_a m_a}^a C_{l_b m_b}^b
+//              E^{t}_{a_x b_x} E^{u}_{a_y b_y} E^{v}_{a_z b_z}   Eq. (solid2herm-2)
+// with p = (t,u,v) in the global Hermite order.  For a ket pair the sign
+// (-1)^{|q|} of Eq. (pq) is folded into H.  Rows p >= Nh and columns
+// ab >= N are zero padding up to multiples of 16 (the matrix-core tiles).
+#include "device_common.h"
+
+namespace mderi {
+
+namespace {
+
+constexpr int kPairThreads = 256;
+constexpr int kEmaxA = kLshell + 1;            // la+1
+constexpr int kEmaxT = 2 * kLshell + 2;        // la+lb+2 (one spare for t+1 reads)
+
+__global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
+  const int pp = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ double E[3][kEmaxA][kEmaxA][kEmaxT];
+  __shared__ double sc[2];
+
+  const PrimPair d = a.pp[pp];
+  const double za = a.basis.exps[d.pa], zb = a.basis.exps[d.pb];
+  const double *A = a.basis.centers + 3 * d.sa;
+  const double *B = a.basis.centers + 3 * d.sb;
+  const double p = za + zb;
+  const double mu = za * zb / p;
+  const int la = a.la, lb = a.lb;
+
+  for (int e = tid; e < 3 * kEmaxA * kEmaxA * kEmaxT; e += kPairThreads) (&E[0][0][0][0])[e] = 0.0;
+  __syncthreads();
+  if (tid < 3) {
+    const int x = tid;
+    const double Px = (za * A[x] + zb * B[x]) / p;
+    const double XPA = Px - A[x], XPB = Px - B[x], XAB = A[x] - B[x];
+    const double o2p = 0.5 / p;
+    double(*Ex)[kEmaxA][kEmaxT] = E[x];
+    Ex[0][0][0] = exp(-mu * XAB * XAB);  // Eq. (E2-000)
+    for (int i = 0; i < la; ++i)         // Eq. (E2rr1), b = 0
+      for (int t = 0; t <= i + 1; ++t)
+        Ex[i + 1][0][t] = (t > 0 ? o2p * Ex[i][0][t - 1] : 0.0) + XPA * Ex[i][0][t] + (t + 1) * Ex[i][0][t + 1];
+    for (int i = 0; i <= la; ++i)  // Eq. (E2rr2)
+      for (int j = 0; j < lb; ++j)
+        for (int t = 0; t <= i + j + 1; ++t)
+          Ex[i][j + 1][t] = (t > 0 ? o2p * Ex[i][j][t - 1] : 0.0) + XPB * Ex[i][j][t] + (t + 1) * Ex[i][j][t + 1];
+    if (x == 0) {
+      sc[0] = a.basis.coefs[d.pa] * a.basis.coefs[d.pb];
+    }
+  }
+  if (tid == 0) {
+    double *G = a.G + 4 * (size_t)pp;
+    G[0] = p;
+    G[1] = (za * A[0] + zb * B[0]) / p;
+    G[2] = (za * A[1] + zb * B[1]) / p;
+    G[3] = (za * A[2] + zb * B[2]) / p;
+  }
+  __syncthreads();
+  const double cab = sc[0];
+  const int Nbb = nsph(lb);
+  double *H = a.H + (size_t)pp * a.Nh_pad * a.N_pad;
+  const int total = a.Nh_pad * a.N_pad;
+  for (int e = tid; e < total; e += kPairThreads) {
+    const int ph = e / a.N_pad;
+    const int ab = e - ph * a.N_pad;
+    double h = 0.0;
+    if (ph < a.Nh && ab < a.N) {
+      const uint32_t hp = a.tab.herm[ph];
+      const int t = hp & 0xff, u = (hp >> 8) & 0xff, v = (hp >> 16) & 0xff;
+      const int ma = ab / Nbb - la, mb = ab % Nbb - lb;
+      const int s0 = a.tab.solid_start[solid_slot(la, ma)], s1 = a.tab.solid_start[solid_slot(la, ma) + 1];
+      const int r0 = a.tab.solid_start[solid_slot(lb, mb)], r1 = a.tab.solid_start[solid_slot(lb, mb) + 1];
+      for (int s = s0; s < s1; ++s) {
+        const uint32_t ca = a.tab.solid_cart[s];
+        const int ax = ca & 0xff, ay = (ca >> 8) & 0xff, az = (ca >> 16) & 0xff;
+        double inner = 0.0;
+        for (int r = r0; r < r1; ++r) {
+          const uint32_t cb = a.tab.solid_cart[r];
+          const int bx = cb & 0xff, by = (cb >> 8) & 0xff, bz = (cb >> 16) & 0xff;
+          if (t <= ax + bx && u <= ay + by && v <= az + bz)
+            inner += a.tab.solid_coef[r] * E[0][ax][bx][t] * E[1][ay][by][u] * E[2][az][bz][v];
+        }
+        h += a.tab.solid_coef[s] * inner;
+      }
+      h *= cab;
+      if (a.ket_sign && ((t + u + v) & 1)) h = -h;
+    }
+    H[e] = h;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_pairs(const PairArgs &a, hipStream_t s) {
+  if (a.npp <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pair_kernel, dim3(a.npp), dim3(kPairThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace mderi

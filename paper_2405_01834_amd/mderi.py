@@ -1,0 +1,182 @@
+"""ctypes binding of libmderi (see include/mderi.h for the contract)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmderi.so")
+
+_lib = None
+
+MDERI_LMAX = 6
+MDERI_KMAX = 16
+
+
+class MderiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libmderi status {status}: {msg}")
+        self.status = status
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("schwarz_tau", ctypes.c_double), ("reserved", ctypes.c_int * 4)]
+
+
+_vp = ctypes.c_void_p
+_ip = ctypes.POINTER(ctypes.c_int)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def load_library():
+    """Loads libmderi.so (built by paper_2405_01834_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise MderiError(-3, f"{_LIB_PATH} is not built (run paper_2405_01834_amd/build.py)")
+    L = ctypes.CDLL(_LIB_PATH)
+    L.mderi_create.argtypes = [ctypes.c_int, ctypes.POINTER(_vp)]
+    L.mderi_create.restype = ctypes.c_int
+    L.mderi_destroy.argtypes = [_vp]
+    L.mderi_destroy.restype = None
+    L.mderi_last_error.argtypes = []
+    L.mderi_last_error.restype = ctypes.c_char_p
+    L.mderi_basis_upload.argtypes = [_vp, ctypes.c_int, _ip, _ip, _dp, _dp, _dp, _ip, ctypes.c_int, ctypes.POINTER(_vp)]
+    L.mderi_basis_upload.restype = ctypes.c_int
+    L.mderi_basis_free.argtypes = [_vp]
+    L.mderi_basis_free.restype = None
+    L.mderi_basis_nshell.argtypes = [_vp]
+    L.mderi_basis_nshell.restype = ctypes.c_int
+    L.mderi_basis_nao.argtypes = [_vp]
+    L.mderi_basis_nao.restype = ctypes.c_int
+    L.mderi_eri4.argtypes = [_vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
+                             ctypes.POINTER(Opts), _vp]
+    L.mderi_eri4.restype = ctypes.c_int
+    L.mderi_schwarz.argtypes = [_vp, _vp, ctypes.c_int, _ip, _vp, _vp]
+    L.mderi_schwarz.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != 0:
+        raise MderiError(st, load_library().mderi_last_error().decode())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+def nsph(l):
+    return 2 * l + 1
+
+
+class Context:
+    """Owns a libmderi context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise MderiError(-4, "no GPU visible to torch; libmderi has no CPU path")
+        self.device = device
+        torch.cuda.set_device(device)
+        L = load_library()
+        h = _vp()
+        _check(L.mderi_create(device, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().mderi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def basis(self, l, nprim, exps, coefs, centers, atom=None, normalize=1) -> "Basis":
+        return Basis(self, l, nprim, exps, coefs, centers, atom, normalize)
+
+    def eri4(self, basis: "Basis", bra, ket, out=None, stream=None):
+        """Class batch (ab|cd) -> torch float64 tensor V[ij, ab, cd, kl] (shape
+        (nbra, Nab, Ncd, nket), a Fortran-order view of the flat output)."""
+        import torch
+        bra = np.ascontiguousarray(np.asarray(bra, dtype=np.int32).reshape(-1, 2))
+        ket = np.ascontiguousarray(np.asarray(ket, dtype=np.int32).reshape(-1, 2))
+        nab, ncd = basis.pair_dim(bra), basis.pair_dim(ket)
+        if nab is None or ncd is None:  # let the library report the bad index
+            _check(load_library().mderi_eri4(self._h, basis._h, len(bra), bra.ctypes.data_as(_ip), len(ket),
+                                             ket.ctypes.data_as(_ip), None, 0, None, _stream_handle(stream)))
+        n = len(bra) * nab * ncd * len(ket)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=f"cuda:{self.device}")
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        _check(load_library().mderi_eri4(self._h, basis._h, len(bra), bra.ctypes.data_as(_ip), len(ket),
+                                         ket.ctypes.data_as(_ip), _vp(out.data_ptr()), out.numel(), None,
+                                         _stream_handle(stream)))
+        return out[:n].view(len(ket), ncd, nab, len(bra)).permute(3, 2, 1, 0)
+
+
+    def schwarz(self, basis: "Basis", pairs, stream=None):
+        """Schwarz factors Q_ij = sqrt(max |(ab|ab)|) -> torch float64 tensor [npair]."""
+        import torch
+        pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        Q = torch.empty(max(len(pairs), 1), dtype=torch.float64, device=f"cuda:{self.device}")
+        _check(load_library().mderi_schwarz(self._h, basis._h, len(pairs), pairs.ctypes.data_as(_ip),
+                                            _vp(Q.data_ptr()), _stream_handle(stream)))
+        return Q[:len(pairs)]
+
+
+class Basis:
+    """A shell list uploaded to the device (see include/mderi.h)."""
+
+    def __init__(self, ctx: Context, l, nprim, exps, coefs, centers, atom=None, normalize=1):
+        self.ctx = ctx
+        self.l = np.ascontiguousarray(l, dtype=np.int32)
+        self.nprim = np.ascontiguousarray(nprim, dtype=np.int32)
+        self.exps = np.ascontiguousarray(exps, dtype=np.float64)
+        self.coefs = np.ascontiguousarray(coefs, dtype=np.float64)
+        self.centers = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+        self.atom = None if atom is None else np.ascontiguousarray(atom, dtype=np.int32)
+        h = _vp()
+        _check(load_library().mderi_basis_upload(
+            ctx._h, len(self.l), self.l.ctypes.data_as(_ip), self.nprim.ctypes.data_as(_ip),
+            self.exps.ctypes.data_as(_dp), self.coefs.ctypes.data_as(_dp), self.centers.ctypes.data_as(_dp),
+            None if self.atom is None else self.atom.ctypes.data_as(_ip), int(normalize), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def nshell(self):
+        return len(self.l)
+
+    def pair_dim(self, pairs):
+        """N(l_a) N(l_b) of the first pair, or None if it indexes outside the basis."""
+        if len(pairs) == 0 or pairs.min() < 0 or pairs.max() >= len(self.l):
+            return None
+        return nsph(int(self.l[pairs[0, 0]])) * nsph(int(self.l[pairs[0, 1]]))
+
+    def nao(self):
+        return int(load_library().mderi_basis_nao(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().mderi_basis_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

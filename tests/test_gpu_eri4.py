@@ -1,0 +1,111 @@
+"""GPU parity of the 4-centre class batches (Eqs. (ket-from-hermite),
+(bra-from-hermite) on the matrix cores) against the FP64 CPU oracle, element
+by element: |gpu - ref| <= 1e-14 + 1e-12 |ref|."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_01834_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-12, 1e-14
+
+
+@pytest.fixture(scope="module")
+def ctx(need_gpu):
+    from paper_2405_01834_amd import Context
+    return Context(0)
+
+
+def _both(ctx, sh, bra, ket, normalize=1):
+    import torch
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, normalize=normalize)
+    V = ctx.eri4(b, bra, ket)
+    torch.cuda.synchronize()
+    got = V.cpu().numpy()
+    ob = oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, normalize)
+    ref = oracle.eri4(ob, bra, ket)
+    return got, ref
+
+
+def _assert_close(got, ref, what):
+    err = np.abs(got - ref)
+    bad = err > ATOL + RTOL * np.abs(ref)
+    assert not bad.any(), (f"{what}: {bad.sum()} of {bad.size} outside tolerance; max abs err {err.max():.3e}, "
+                           f"max |ref| {np.abs(ref).max():.3e}")
+
+
+def test_pp_quartets_full(ctx):
+    """[pp|pp], K=1, 16 bra x 32 ket pairs (512 quartets), all elements."""
+    sh, bra, ket = inputs.pp_quartets(seed=0)
+    got, ref = _both(ctx, sh, bra, ket)
+    _assert_close(got, ref, "[pp|pp]")
+
+
+CLASSES = [
+    ((0, 0, 0, 0), 1), ((1, 0, 0, 0), 2), ((0, 0, 1, 0), 1), ((1, 1, 1, 1), 2), ((2, 0, 1, 1), 1),
+    ((2, 1, 2, 0), 2), ((2, 2, 2, 2), 1), ((2, 2, 2, 2), 3), ((3, 1, 2, 2), 1), ((3, 3, 3, 3), 1),
+    ((3, 3, 3, 3), 2), ((4, 0, 4, 1), 1), ((4, 2, 3, 2), 1), ((4, 3, 1, 1), 2), ((4, 4, 4, 4), 1),
+    ((4, 4, 4, 4), 3), ((0, 0, 4, 4), 1), ((4, 4, 0, 0), 2),
+]
+
+
+@pytest.mark.parametrize("cls,K", CLASSES)
+def test_class_batch_parity(ctx, cls, K):
+    la, lb, lc, ld = cls
+    nbra, nket = (3, 5) if max(cls) < 4 or K == 1 else (2, 2)
+    sh_b, bra = inputs.near_pairs(100 + 7 * sum(cls) + K, la, lb, K, nbra, box=6.0)
+    sh_k, ket = inputs.near_pairs(200 + 7 * sum(cls) + K, lc, ld, K, nket, box=6.0)
+    sh = sh_b.concat(sh_k)
+    ket = ket + sh_b.n
+    got, ref = _both(ctx, sh, bra, ket)
+    _assert_close(got, ref, f"{cls} K={K}")
+
+
+def test_mixed_contraction_degrees(ctx):
+    """Pairs of one class may have different primitive counts."""
+    rng = np.random.default_rng(5)
+    sh = inputs.random_shells(rng, [2, 1, 2, 1, 3, 0, 3, 0], [1, 3, 2, 1, 2, 2, 1, 3], 5.0, 0.1, 20.0)
+    got, ref = _both(ctx, sh, [[0, 1], [2, 3]], [[4, 5], [6, 7]])
+    _assert_close(got, ref, "mixed K")
+
+
+def test_unnormalised_basis(ctx):
+    rng = np.random.default_rng(6)
+    sh = inputs.random_shells(rng, [1, 2, 2, 1], [2, 1, 1, 2], 4.0, 0.2, 5.0)
+    got, ref = _both(ctx, sh, [[0, 1]], [[2, 3]], normalize=0)
+    _assert_close(got, ref, "raw")
+
+
+def test_validation_errors(ctx):
+    from paper_2405_01834_amd import MderiError
+    sh, bra, ket = inputs.pp_quartets(seed=0, nbra=2, nket=2)
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    with pytest.raises(MderiError):  # out-of-range shell index
+        ctx.eri4(b, [[0, 99]], ket)
+    sh2 = sh.concat(inputs.random_shells(np.random.default_rng(1), [2, 2], 1, 3.0, 0.5, 2.0))
+    b2 = ctx.basis(sh2.l, sh2.nprim, sh2.exps, sh2.coefs, sh2.centers)
+    with pytest.raises(MderiError):  # mixed classes in one batch
+        ctx.eri4(b2, [[0, 1], [sh.n, sh.n + 1]], ket)
+    with pytest.raises(MderiError):  # output too small
+        import torch
+        ctx.eri4(b, bra, ket, out=torch.empty(3, dtype=torch.float64, device="cuda"))
+    with pytest.raises(MderiError):  # non-positive exponent
+        ctx.basis([0], [1], [-1.0], [1.0], [[0, 0, 0]])
+    with pytest.raises(MderiError):  # l beyond the built maximum
+        ctx.basis([7], [1], [1.0], [1.0], [[0, 0, 0]])
+
+
+def test_schwarz_factors_mixed_classes(ctx):
+    """Q_ij = sqrt(max_ab |(ab|ab)|) for a list mixing classes, in input order."""
+    import torch
+    rng = np.random.default_rng(17)
+    ls = [0, 1, 2, 3, 4, 2, 1, 4, 3, 0, 2, 2]
+    sh = inputs.random_shells(rng, ls, [1, 2, 1, 3, 1, 2, 1, 2, 1, 3, 1, 1], 6.0, 0.1, 30.0)
+    pairs = np.array([[0, 1], [2, 3], [4, 4], [5, 6], [7, 8], [9, 10], [11, 2], [3, 3], [1, 0], [8, 7]], np.int32)
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    Q = ctx.schwarz(b, pairs)
+    torch.cuda.synchronize()
+    ref = oracle.schwarz(oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, 1), pairs)
+    np.testing.assert_allclose(Q.cpu().numpy(), ref, rtol=1e-12, atol=1e-14)
