@@ -1,7 +1,7 @@
 // device_common.h -- device building blocks shared by the MD kernels:
 // the Boys function (Eq. (boys)), the auxiliary integrals [0]^(m) (Eq. (0m))
-// and the Hermite recursion (Eq. (r)) into a workgroup's LDS, and the FP64
-// matrix-core product used by the Hermite->solid transforms.
+// and the Hermite recursion (Eq. (r)) into LDS, and the FP64 matrix-core
+// product used by the Hermite->solid transforms.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -52,57 +52,82 @@ __device__ __forceinline__ double boys_m(int m, double T, const double *__restri
 // t descending then u descending.
 __device__ __forceinline__ int deg_index(int n, int t, int u) { return ((n - t) * (n - t + 1) >> 1) + (n - t - u); }
 
+// Makes this wave's LDS writes visible to its other lanes before they read.
+__device__ __forceinline__ void lds_wave_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Builds [r]^(0) for all |r| <= L (Eqs. (0m) and (r)) in the LDS cube
-// cube[t*(L+1)^2 + u*(L+1) + v], cooperatively over the workgroup.
+// cube[t*S1 + u*S2 + v] (S2 > L, S1 > L*S2) with a single wave (lanes 0..63)
+// and wave-local synchronisation, so the other waves of the workgroup keep
+// issuing matrix-core work meanwhile.
 //   p, P: bra Hermite exponent and centre; q, Q: ket.
+//   herm: LDS copy of the Hermite order (degree-major, t then u descending).
 //   lev:  3 rotating level buffers of `levn` doubles each; level n holds
 //         [r]^(m) for |r| = n, m = 0..L-n at [m * T_n + deg_index].
-// Starts and ends with all threads past a barrier.
-__device__ __forceinline__ void build_R(int L, double p, const double *P, double q, const double *Q, double *cube,
-                                        double *lev, int levn, const Tables &tab, int tid, int nthr) {
+// A lane owns whole Hermite functions of a level and runs their m chain, so
+// no index division is needed.
+__device__ __forceinline__ void build_R_wave(int L, double p, const double *P, double q, const double *Q,
+                                             double *cube, int S1, int S2, double *lev, int levn,
+                                             const uint32_t *herm, const double *boys, int lane) {
   const double pq = p + q;
   const double rho = p * q / pq;
   const double X = P[0] - Q[0], Y = P[1] - Q[1], Z = P[2] - Q[2];
   const double T = rho * (X * X + Y * Y + Z * Z);
-  const int L1 = L + 1;
-  const int S1 = L1 * L1;
-  if (tid <= L) {
-    // Eq. (0m): [0]^(m) = (-2 rho)^m 2 pi^{5/2} / (p q sqrt(p+q)) F_m(T)
-    double f = 2.0 * 17.493418327624862 / (p * q * sqrt(pq));  // 17.49.. = pi^{5/2}
+  if (lane <= L) {
+    double f = 2.0 * 17.493418327624862 / (p * q * sqrt(pq));  // Eq. (0m), 17.49.. = pi^{5/2}
     const double m2r = -2.0 * rho;
-    for (int j = 0; j < tid; ++j) f *= m2r;
-    lev[tid] = f * boys_m(tid, T, tab.boys);
+    for (int j = 0; j < lane; ++j) f *= m2r;
+    const double v0 = f * boys_m(lane, T, boys);
+    lev[lane] = v0;
+    if (lane == 0) cube[0] = v0;
   }
-  __syncthreads();
-  if (tid == 0) cube[0] = lev[0];
+  lds_wave_sync();
   for (int n = 1; n <= L; ++n) {
     double *cur = lev + (n % 3) * levn;
     const double *pr1 = lev + ((n - 1) % 3) * levn;
     const double *pr2 = lev + ((n + 1) % 3) * levn;  // level n-2
     const int Tn = (n + 1) * (n + 2) / 2, Tn1 = n * (n + 1) / 2, Tn2 = (n - 1) * n / 2;
-    const int cnt = (L - n + 1) * Tn;
-    const uint32_t *hdeg = tab.herm + (n * (n + 1) * (n + 2)) / 6;
-    for (int e = tid; e < cnt; e += nthr) {
-      const int m = e / Tn;
-      const int i = e - m * Tn;
+    const int M = L - n;  // m = 0..M at this level
+    const uint32_t *hdeg = herm + (n * (n + 1) * (n + 2)) / 6;
+    for (int i = lane; i < Tn; i += 64) {
       const uint32_t h = hdeg[i];
       const int t = h & 0xff, u = (h >> 8) & 0xff, v = (h >> 16) & 0xff;
-      double val;
-      // Eq. (r): [r+1_i]^(m) = r_i [r-1_i]^(m+1) + (P_i - Q_i) [r]^(m+1)
+      // Eq. (r): [r+1_i]^(m) = r_i [r-1_i]^(m+1) + (P_i - Q_i) [r]^(m+1),
+      // raising the first non-zero direction of r
+      double xi, ri;
+      int i1, i2;
       if (t > 0) {
-        val = X * pr1[(m + 1) * Tn1 + deg_index(n - 1, t - 1, u)];
-        if (t > 1) val += (t - 1) * pr2[(m + 1) * Tn2 + deg_index(n - 2, t - 2, u)];
+        xi = X;
+        ri = t - 1;
+        i1 = deg_index(n - 1, t - 1, u);
+        i2 = t > 1 ? deg_index(n - 2, t - 2, u) : -1;
       } else if (u > 0) {
-        val = Y * pr1[(m + 1) * Tn1 + deg_index(n - 1, 0, u - 1)];
-        if (u > 1) val += (u - 1) * pr2[(m + 1) * Tn2 + deg_index(n - 2, 0, u - 2)];
+        xi = Y;
+        ri = u - 1;
+        i1 = deg_index(n - 1, 0, u - 1);
+        i2 = u > 1 ? deg_index(n - 2, 0, u - 2) : -1;
       } else {
-        val = Z * pr1[(m + 1) * Tn1 + deg_index(n - 1, 0, 0)];
-        if (v > 1) val += (v - 1) * pr2[(m + 1) * Tn2 + deg_index(n - 2, 0, 0)];
+        xi = Z;
+        ri = v - 1;
+        i1 = deg_index(n - 1, 0, 0);
+        i2 = v > 1 ? deg_index(n - 2, 0, 0) : -1;
       }
-      cur[e] = val;
-      if (m == 0) cube[t * S1 + u * L1 + v] = val;
+      const double *a1 = pr1 + Tn1 + i1;  // m+1 = 1 at m = 0
+      const double *a2 = pr2 + Tn2 + (i2 < 0 ? 0 : i2);
+      double *o = cur + i;
+      double val = xi * a1[0];
+      if (i2 >= 0) val += ri * a2[0];
+      o[0] = val;
+      cube[t * S1 + u * S2 + v] = val;
+      for (int m = 1; m <= M; ++m) {
+        double w = xi * a1[m * Tn1];
+        if (i2 >= 0) w += ri * a2[m * Tn2];
+        o[m * Tn] = w;
+      }
     }
-    __syncthreads();
+    lds_wave_sync();
   }
 }
 

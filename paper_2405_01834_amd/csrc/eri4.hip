@@ -1,140 +1,216 @@
 // eri4.hip -- fused 4-centre MD kernel on the FP64 matrix cores.
 //
-// One workgroup evaluates one shell quartet (ij, kl); wave w owns the 16
-// ket components cd in [16w, 16w+16) for every bra component ab.  For each
-// bra primitive pair:
+// One workgroup evaluates one shell quartet (ij, kl).  It runs
+//   * one producer wave that builds [r]^(0) (Eqs. (0m), (r)) for the primitive
+//     quartets one after another into a double-buffered LDS cube, one quartet
+//     ahead of the consumers, and
+//   * nct * nps consumer waves: wave (ct, ph) owns the 16 ket components
+//     cd in [16 ct, 16 ct + 16) and the bra Hermite rows p of part ph.
+// For each bra primitive pair a consumer computes
 //   X[p][cd]  = sum_{ket prims} sum_q [p|q] H_ket[q][cd]        Eq. (ket-from-hermite)
 //   V[ab][cd] += sum_p H_bra[p][ab] X[p][cd]                      Eq. (bra-from-hermite)
 // with [p|q] = (-1)^{|q|} [p+q]^(0) (Eq. (pq); the sign lives in H_ket)
-// gathered straight from the LDS copy of [r]^(0) (Eqs. (0m), (r)) as the A
-// operand of a 16x16x4 FP64 MFMA, so the Ñ_bra x Ñ_ket matrix [p|q] is never
-// stored.  X stays in registers: the accumulator tile of the ket step is
-// exactly the B operand of the bra step (rows 4r..4r+3 of a 16-row tile sit
-// in register r), so the two transforms are chained without leaving the
-// wave.  Output goes to V[ij,ab,cd,kl] (Sec. 3), ij fastest.
+// gathered straight from the LDS cube as the A operand of a 16x16x4 FP64
+// MFMA, so the Ñ_bra x Ñ_ket matrix [p|q] is never stored.  X stays in
+// registers: the accumulator tile of the ket step is exactly the B operand of
+// the bra step (rows 4r..4r+3 of a 16-row tile sit in register r), so the two
+// transforms are chained without leaving the wave.  The bra step runs one
+// 16-row ab tile at a time and adds it into an LDS copy of V[ab][cd]
+// (FP64 LDS atomics, since the nps row parts share columns), which is written
+// to V[ij,ab,cd,kl] (Sec. 3, ij fastest) at the end.
 #include "device_common.h"
 
 namespace mderi {
 
 namespace {
 
-constexpr int kMaxWaves = 6;
+constexpr int kMaxWaves = 16;
 
-template <int NPT, int NAT>
+template <int NPT>
 __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
   extern __shared__ double smem[];
   const int L = a.L;
-  const int L1 = L + 1, S1 = L1 * L1;
-  double *cube = smem;
-  double *lev = cube + S1 * L1;
-  int *offq = (int *)(lev + 3 * a.levn);
+  const int S1 = a.S1, S2 = a.S2;
+  const int cube_sz = a.cube_sz;
+  double *cube0 = smem;
+  double *cube1 = a.dbuf ? smem + cube_sz : smem;
+  double *lev = smem + (a.dbuf ? 2 : 1) * cube_sz;
+  double *gsh = lev + 3 * a.levn;             // G of this quartet's bra then ket primitive pairs
+  double *vsh = gsh + 4 * a.maxpp;            // V[ab][cd] of this quartet (Nb x Nk)
+  uint32_t *hsh = (uint32_t *)(vsh + a.Nb * a.Nk);  // Hermite order, |r| <= L
+  int *offq = (int *)(hsh + ntil(L));
 
   const long G = a.diag ? (long)a.nbra : (long)a.nbra * a.nket;
   const long v = xcd_remap(blockIdx.x, G);
   const int ij = (int)(v % a.nbra), kl = a.diag ? ij : (int)(v / a.nbra);
 
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, c = lane & 15;
-
-  for (int q = tid; q < a.Nhk_pad; q += nthr) {
-    int o = 0;
-    if (q < a.Nhk) {
-      const uint32_t h = a.tab.herm[q];
-      o = (int)(h & 0xff) * S1 + (int)((h >> 8) & 0xff) * L1 + (int)((h >> 16) & 0xff);
-    }
-    offq[q] = o;
-  }
-  int offp[NPT];
-#pragma unroll
-  for (int pt = 0; pt < NPT; ++pt) {
-    const int p = pt * 16 + c;
-    int o = 0;
-    if (p < a.Nhb) {
-      const uint32_t h = a.tab.herm[p];
-      o = (int)(h & 0xff) * S1 + (int)((h >> 8) & 0xff) * L1 + (int)((h >> 16) & 0xff);
-    }
-    offp[pt] = o;
-  }
-
-  d4 vacc[NAT];
-#pragma unroll
-  for (int at = 0; at < NAT; ++at) vacc[at] = d4{0.0, 0.0, 0.0, 0.0};
+  const int ncons = a.nct * a.nps;
 
   const int bp0 = a.bra_off[ij], bp1 = a.bra_off[ij + 1];
   const int kp0 = a.ket_off[kl], kp1 = a.ket_off[kl + 1];
-  const int nks = a.Nhk_pad >> 2;
-  const int col = wave * 16 + c;  // this lane's ket column cd
+  const int nbp = bp1 - bp0, nkp = kp1 - kp0;
+  const int nsteps = nbp * nkp;
 
-  for (int bp = bp0; bp < bp1; ++bp) {
-    d4 xacc[NPT];
-#pragma unroll
-    for (int pt = 0; pt < NPT; ++pt) xacc[pt] = d4{0.0, 0.0, 0.0, 0.0};
-    const double pz = a.bra_G[4 * (size_t)bp];
-    const double P[3] = {a.bra_G[4 * (size_t)bp + 1], a.bra_G[4 * (size_t)bp + 2], a.bra_G[4 * (size_t)bp + 3]};
-
-    for (int kp = kp0; kp < kp1; ++kp) {
-      const double qz = a.ket_G[4 * (size_t)kp];
-      const double Q[3] = {a.ket_G[4 * (size_t)kp + 1], a.ket_G[4 * (size_t)kp + 2], a.ket_G[4 * (size_t)kp + 3]};
-      __syncthreads();  // previous [r] consumed by every wave
-      build_R(L, pz, P, qz, Q, cube, lev, a.levn, a.tab, tid, nthr);
-
-      // ket transform: X[p][cd] += sum_q [p+q] H_ket[q][cd]
-      const double *Hk = a.ket_H + (size_t)kp * a.Nhk_pad * a.Nk_pad + col;
-      double bnext = Hk[(size_t)g * a.Nk_pad];
-#pragma unroll 1
-      for (int ks = 0; ks < nks; ++ks) {
-        const double bcur = bnext;
-        if (ks + 1 < nks) bnext = Hk[(size_t)(4 * (ks + 1) + g) * a.Nk_pad];
-        const int oq = offq[4 * ks + g];
-#pragma unroll
-        for (int pt = 0; pt < NPT; ++pt) xacc[pt] = mfma16x16x4(cube[offp[pt] + oq], bcur, xacc[pt]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
+  for (int e = tid; e < 4 * nbp; e += blockDim.x) gsh[e] = a.bra_G[4 * (size_t)bp0 + e];
+  for (int e = tid; e < 4 * nkp; e += blockDim.x) gsh[4 * nbp + e] = a.ket_G[4 * (size_t)kp0 + e];
+  for (int e = tid; e < ntil(L); e += blockDim.x) hsh[e] = a.tab.herm[e];
+  for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) vsh[e] = 0.0;
+  for (int q = tid; q < a.Nhk_pad; q += blockDim.x) {
+    int o = 0;
+    if (q < a.Nhk) {
+      const uint32_t h = a.tab.herm[q];
+      o = (int)(h & 0xff) * S1 + (int)((h >> 8) & 0xff) * S2 + (int)((h >> 16) & 0xff);
     }
+    offq[q] = o;
+  }
+  __syncthreads();
 
-    // bra transform: V[ab][cd] += sum_p H_bra[p][ab] X[p][cd]
-    const double *Hb = a.bra_H + (size_t)bp * a.Nhb_pad * a.Nb_pad + c;
+  if (wave == ncons) {
+    // ---------------- producer: [r] one primitive quartet ahead ----------------
+    auto build = [&](int n, double *cube) {
+      const int ib = n / nkp, ik = n - ib * nkp;
+      const double *Gb = gsh + 4 * ib;
+      const double *Gk = gsh + 4 * (nbp + ik);
+      const double P[3] = {Gb[1], Gb[2], Gb[3]};
+      const double Q[3] = {Gk[1], Gk[2], Gk[3]};
+      build_R_wave(L, Gb[0], P, Gk[0], Q, cube, S1, S2, lev, a.levn, hsh, a.tab.boys, lane);
+    };
+    if (nsteps > 0) build(0, cube0);
+    for (int n = 0; n < nsteps; ++n) {
+      if (!a.dbuf && n > 0) {
+        __syncthreads();  // consumers are done with the single cube
+        build(n, cube0);
+      }
+      __syncthreads();  // [r] of step n published
+      if (a.dbuf && n + 1 < nsteps) build(n + 1, ((n + 1) & 1) ? cube1 : cube0);
+    }
+  } else {
+    // ---------------- consumers ----------------
+    const int ct = wave % a.nct, ph = wave / a.nct;
+    const int col = ct * 16 + c;  // this lane's ket column cd
+    int offp[NPT];
 #pragma unroll
     for (int pt = 0; pt < NPT; ++pt) {
+      // rows are permuted per class so the 16 rows of a tile sit in distinct LDS banks
+      const uint32_t h = a.border[(ph * NPT + pt) * 16 + c];
+      offp[pt] = (int)(h & 0xff) * S1 + (int)((h >> 8) & 0xff) * S2 + (int)((h >> 16) & 0xff);
+    }
+    const int nks = a.Nhk_pad >> 2;  // even: Nhk_pad is a multiple of 8
+    const int klo = g * a.Nk_pad + col, kstep = 4 * a.Nk_pad;
+    const int blo = g * a.Nb_pad + c;
+    const int nat = a.Nb_pad >> 4;
+    d4 xacc[NPT];
+    for (int n = 0; n < nsteps; ++n) {
+      if (!a.dbuf && n > 0) __syncthreads();
+      __syncthreads();
+      const double *cube = (a.dbuf && (n & 1)) ? cube1 : cube0;
+      const int ib = n / nkp, ik = n - ib * nkp;
+      if (ik == 0) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double *row = Hb + (size_t)(pt * 16 + 4 * r + g) * a.Nb_pad;
+        for (int pt = 0; pt < NPT; ++pt) xacc[pt] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+      // ket transform: X[p][cd] += sum_q [p+q] H_ket[q][cd]; the LDS gathers
+      // and the H_ket load of k-step ks+1 are issued before the MFMAs of ks
+      const double *Hk = a.ket_H + (size_t)(kp0 + ik) * a.Nhk_pad * a.Nk_pad;
+      // Two register sets ping-pong: the LDS gathers and the H_ket load of
+      // k-step ks+1 are issued before the MFMAs of ks (scheduling barriers
+      // keep that order); prefetch indices are clamped so every load is
+      // unconditional.  nks is even (Nhk_pad is a multiple of 8).
+      double aA[NPT], aB[NPT];
+      double bA, bB;
+      {
+        const int oq = offq[g];
 #pragma unroll
-        for (int at = 0; at < NAT; ++at) vacc[at] = mfma16x16x4(row[at * 16], xacc[pt][r], vacc[at]);
+        for (int pt = 0; pt < NPT; ++pt) aA[pt] = cube[offp[pt] + oq];
+        bA = Hk[klo];
+      }
+#pragma unroll 1
+      for (int ks = 0; ks < nks; ks += 2) {
+        {
+          const int oq = offq[4 * (ks + 1) + g];
+#pragma unroll
+          for (int pt = 0; pt < NPT; ++pt) aB[pt] = cube[offp[pt] + oq];
+          bB = Hk[(size_t)(ks + 1) * kstep + klo];
+        }
         __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int pt = 0; pt < NPT; ++pt) xacc[pt] = mfma16x16x4(aA[pt], bA, xacc[pt]);
+        __builtin_amdgcn_sched_barrier(0);
+        {
+          const int ks2 = min(ks + 2, nks - 1);
+          const int oq = offq[4 * ks2 + g];
+#pragma unroll
+          for (int pt = 0; pt < NPT; ++pt) aA[pt] = cube[offp[pt] + oq];
+          bA = Hk[(size_t)ks2 * kstep + klo];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int pt = 0; pt < NPT; ++pt) xacc[pt] = mfma16x16x4(aB[pt], bB, xacc[pt]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (ik == nkp - 1) {
+        // bra transform: V[ab][cd] += sum_p H_bra[p][ab] X[p][cd], one ab tile
+        // at a time (two accumulators), summed into the LDS copy of V
+        const double *Hb = a.bra_H + (size_t)(bp0 + ib) * a.Nhb_pad * a.Nb_pad + (size_t)ph * NPT * 16 * a.Nb_pad;
+#pragma unroll 1
+        for (int at = 0; at < nat; ++at) {
+          const double *Ht = Hb + at * 16 + blo;
+          d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = d4{0.0, 0.0, 0.0, 0.0};
+          double h[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) h[r] = Ht[(4 * r) * a.Nb_pad];
+#pragma unroll
+          for (int pt = 0; pt < NPT; ++pt) {
+            double hn[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) hn[r] = (pt + 1 < NPT) ? Ht[((pt + 1) * 16 + 4 * r) * a.Nb_pad] : 0.0;
+            acc0 = mfma16x16x4(h[0], xacc[pt][0], acc0);
+            acc1 = mfma16x16x4(h[1], xacc[pt][1], acc1);
+            acc0 = mfma16x16x4(h[2], xacc[pt][2], acc0);
+            acc1 = mfma16x16x4(h[3], xacc[pt][3], acc1);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h[r] = hn[r];
+          }
+          if (col < a.Nk) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int ab = at * 16 + 4 * r + g;
+              if (ab < a.Nb) atomicAdd(&vsh[ab * a.Nk + col], acc0[r] + acc1[r]);
+            }
+          }
+        }
       }
     }
   }
+  __syncthreads();  // V complete in LDS
 
   if (a.diag) {
-#pragma unroll
-    for (int at = 0; at < NAT; ++at)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ab = at * 16 + 4 * r + g;
-        if (ab == col && ab < a.Nb) a.V[(size_t)ij * a.Nb + ab] = vacc[at][r];
-      }
+    for (int ab = tid; ab < a.Nb; ab += blockDim.x) a.V[(size_t)ij * a.Nb + ab] = vsh[ab * a.Nk + ab];
     return;
   }
-  if (col < a.Nk) {
-    const size_t base = (size_t)ij + (size_t)a.nbra * (size_t)a.Nb * ((size_t)col + (size_t)a.Nk * kl);
-#pragma unroll
-    for (int at = 0; at < NAT; ++at)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ab = at * 16 + 4 * r + g;
-        if (ab < a.Nb) a.V[base + (size_t)a.nbra * ab] = vacc[at][r];
-      }
+  const size_t base = (size_t)ij + (size_t)a.nbra * (size_t)a.Nb * (size_t)a.Nk * kl;
+  for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) {
+    const int cd = e / a.Nb, ab = e - cd * a.Nb;
+    a.V[base + (size_t)a.nbra * ((size_t)ab + (size_t)a.Nb * cd)] = vsh[ab * a.Nk + cd];
   }
 }
 
-template <int NPT, int NAT>
+template <int NPT>
 hipError_t launch_t(const Eri4Args &a, hipStream_t s) {
-  const int waves = a.Nk_pad / 16;
-  const size_t lds = eri4_lds_bytes(a.L, a.Nhk_pad, a.levn);
+  const int waves = a.nct * a.nps + 1;
+  const size_t lds = eri4_lds_bytes(a);
   const long G = a.diag ? (long)a.nbra : (long)a.nbra * a.nket;
-  hipLaunchKernelGGL((eri4_kernel<NPT, NAT>), dim3((unsigned)G), dim3(64 * waves), lds, s, a);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)eri4_kernel<NPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((eri4_kernel<NPT>), dim3((unsigned)G), dim3(64 * waves), lds, s, a);
   return hipGetLastError();
 }
 
@@ -146,6 +222,9 @@ __global__ void schwarz_reduce_kernel(int npair, int Nab, const double *__restri
   for (int ab = 0; ab < Nab; ++ab) mx = fmax(mx, fabs(D[(size_t)n * Nab + ab]));
   Q[idx[n]] = sqrt(mx);
 }
+
+// p tiles per consumer wave that are built.
+const int kTiles[] = {1, 2, 3, 4, 6};
 
 }  // namespace
 
@@ -164,35 +243,50 @@ int rr_level_stride(int L) {
   return mx;
 }
 
-size_t eri4_lds_bytes(int L, int Nhk_pad, int levn) {
-  const size_t L1 = (size_t)L + 1;
-  return sizeof(double) * (L1 * L1 * L1 + 3 * (size_t)levn) + sizeof(int) * (size_t)Nhk_pad;
+static size_t cube_region(int cube_sz, int ncube) { return sizeof(double) * (size_t)cube_sz * ncube; }
+
+static size_t side_bytes(int L, int levn, int maxpp, int Nhk_pad, int Nb, int Nk) {
+  return sizeof(double) * (3 * (size_t)levn + 4 * (size_t)maxpp + (size_t)Nb * Nk) + sizeof(uint32_t) * ntil(L) +
+         sizeof(int) * (size_t)Nhk_pad;
 }
 
-// Register tiles built: (p tiles, ab tiles) of the bra side.  The host pads
-// the bra transform matrices to the chosen tile so the kernel has no
-// partial tiles.
-static const int kTiles[][2] = {{1, 1}, {2, 1}, {3, 1}, {3, 2}, {4, 2}, {4, 3}, {6, 3}, {6, 4}, {8, 4}, {11, 6}};
+size_t eri4_lds_bytes(const Eri4Args &a) {
+  return cube_region(a.cube_sz, a.dbuf ? 2 : 1) + side_bytes(a.L, a.levn, a.maxpp, a.Nhk_pad, a.Nb, a.Nk);
+}
 
-bool eri4_pick_tiles(int npt, int nat, int *NPT, int *NAT) {
-  for (const auto &t : kTiles)
-    if (t[0] >= npt && t[1] >= nat) {
-      *NPT = t[0];
-      *NAT = t[1];
-      return true;
+bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int levn, int maxpp, int *npt, int *nps,
+               int *dbuf) {
+  const int need_p = round16(Nhb) / 16, nct = round16(Nk) / 16;
+  int parts = 1;
+  while ((need_p + parts - 1) / parts > 6) ++parts;
+  const int per = (need_p + parts - 1) / parts;
+  *npt = 0;
+  for (int t : kTiles)
+    if (t >= per) {
+      *npt = t;
+      break;
     }
-  return false;
+  if (!*npt || nct * parts + 1 > kMaxWaves) return false;
+  *nps = parts;
+  const size_t lds_budget = 160 * 1024;
+  const size_t rest = side_bytes(L, levn, maxpp, Nhk_pad, Nb, Nk);
+  if (cube_region(cube_sz, 2) + rest <= lds_budget) *dbuf = 1;
+  else if (cube_region(cube_sz, 1) + rest <= lds_budget) *dbuf = 0;
+  else return false;
+  return true;
 }
 
 hipError_t launch_eri4(const Eri4Args &a, hipStream_t s) {
   if (a.nbra <= 0 || a.nket <= 0) return hipSuccess;
-  if (a.Nk_pad / 16 > kMaxWaves) return hipErrorInvalidValue;
-#define MDERI_TILE(P, A) \
-  if (a.npt == P && a.nat == A) return launch_t<P, A>(a, s);
-  MDERI_TILE(1, 1) MDERI_TILE(2, 1) MDERI_TILE(3, 1) MDERI_TILE(3, 2) MDERI_TILE(4, 2)
-  MDERI_TILE(4, 3) MDERI_TILE(6, 3) MDERI_TILE(6, 4) MDERI_TILE(8, 4) MDERI_TILE(11, 6)
-#undef MDERI_TILE
-  return hipErrorInvalidValue;
+  if (a.nct * a.nps + 1 > kMaxWaves) return hipErrorInvalidValue;
+  switch (a.npt) {
+    case 1: return launch_t<1>(a, s);
+    case 2: return launch_t<2>(a, s);
+    case 3: return launch_t<3>(a, s);
+    case 4: return launch_t<4>(a, s);
+    case 6: return launch_t<6>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace mderi

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -170,7 +171,7 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 // context
 // ---------------------------------------------------------------------------
 enum WsSlot {
-  WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_COUNT
+  WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_ORDER, WS_COUNT
 };
 
 struct mderi_ctx {
@@ -447,6 +448,70 @@ mderi_status expand_pairs(const mderi_basis *b, int n, const int32_t *pairs, con
 
 namespace {
 
+// [r] cube strides for total angular momentum L: S2 > L and S1 > L*S2 keep
+// t*S1 + u*S2 + v injective on |r| <= L and additive in r, so [p+q] is found
+// at offset(p) + offset(q).  Among such strides, pick the pair whose bra
+// offsets (|p| <= Lb) fall most evenly into the 16 LDS bank pairs that one
+// 16-lane group of a 64-bit read spans, then the smallest cube.
+void choose_cube(int L, int Lb, int *S1, int *S2) {
+  const int n = ntil(Lb), nt = (n + 15) / 16;
+  long best_key = -1;
+  for (int s2 = L + 1; s2 <= L + 16; ++s2)
+    for (int s1 = L * s2 + 1; s1 <= L * s2 + 16; ++s1) {
+      int hist[16] = {0};
+      for (int d = 0; d <= Lb; ++d)
+        for (int t = d; t >= 0; --t)
+          for (int u = d - t; u >= 0; --u) ++hist[(t * s1 + u * s2 + (d - t - u)) % 16];
+      int mx = 0;
+      for (int r = 0; r < 16; ++r) mx = hist[r] > mx ? hist[r] : mx;
+      const long excess = mx > nt ? mx - nt : 0;
+      const long key = excess * 100000000L + (long)L * s1;
+      if (best_key < 0 || key < best_key) {
+        best_key = key;
+        *S1 = s1;
+        *S2 = s2;
+      }
+    }
+}
+
+// Row order of the bra Hermite functions for tiles of 16 rows: functions
+// sorted by bank (offset mod 16) are dealt round-robin over the tiles, so a
+// tile holds at most ceil(bucket/ntiles) functions of one bank; padding rows
+// (kPadRow) reuse functions of banks the tile does not use yet.
+std::vector<uint32_t> bra_row_order(int Lb, int S1, int S2, int Nh_pad) {
+  std::vector<uint32_t> p;
+  for (int d = 0; d <= Lb; ++d)
+    for (int t = d; t >= 0; --t)
+      for (int u = d - t; u >= 0; --u) p.push_back(pack3(t, u, d - t - u));
+  auto bank = [&](uint32_t h) { return (int)(((h & 0xff) * S1 + ((h >> 8) & 0xff) * S2 + ((h >> 16) & 0xff)) % 16); };
+  std::vector<int> idx(p.size());
+  for (size_t i = 0; i < p.size(); ++i) idx[i] = (int)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return bank(p[x]) < bank(p[y]); });
+  const int nt = Nh_pad / 16;
+  std::vector<std::vector<uint32_t>> tiles(nt);
+  for (size_t k = 0; k < idx.size(); ++k) tiles[k % nt].push_back(p[idx[k]]);
+  std::vector<int> by_bank[16];
+  for (uint32_t h : p) by_bank[bank(h)].push_back(h);
+  std::vector<uint32_t> out;
+  out.reserve(Nh_pad);
+  for (auto &tl : tiles) {
+    bool used[16] = {false};
+    for (uint32_t h : tl) used[bank(h)] = true;
+    int r = 0;
+    while (tl.size() < 16) {
+      while (r < 16 && (used[r] || by_bank[r].empty())) ++r;
+      if (r < 16) {
+        tl.push_back(by_bank[r][0] | kPadRow);
+        used[r] = true;
+      } else {
+        tl.push_back(p[0] | kPadRow);
+      }
+    }
+    out.insert(out.end(), tl.begin(), tl.end());
+  }
+  return out;
+}
+
 // Enqueues pair data (bra and ket) and the fused kernel for one class batch.
 // diag != 0 evaluates only (ij|ij) (bra list == ket list) and writes the
 // diagonal [ij][ab] to V.
@@ -458,13 +523,23 @@ mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb,
   const int Lb = la + lb, Lk = lc + ld, L = Lb + Lk;
   const int Nb = nsph(la) * nsph(lb), Nk = nsph(lc) * nsph(ld);
   const int Nhb = ntil(Lb), Nhk = ntil(Lk);
-  int npt = 0, nat = 0;
-  if (!eri4_pick_tiles(round16(Nhb) / 16, round16(Nb) / 16, &npt, &nat) || round16(Nk) / 16 > 6)
+  const int Nhk_pad = (Nhk + 7) & ~7, Nk_pad = round16(Nk), levn = rr_level_stride(L);
+  int S1 = 1, S2 = 1;
+  choose_cube(L, Lb, &S1, &S2);
+  const int cube_sz = (L * S1 + 2) & ~1;
+  int maxb = 0, maxk = 0;
+  for (int i = 0; i < nbra; ++i) maxb = std::max(maxb, offb[i + 1] - offb[i]);
+  for (int i = 0; i < nket; ++i) maxk = std::max(maxk, offk[i + 1] - offk[i]);
+  const int maxpp = maxb + maxk;
+  int npt = 0, nps = 0, dbuf = 0;
+  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, levn, maxpp, &npt, &nps, &dbuf))
     return fail(MDERI_EUNSUPPORTED, "class (%d%d|%d%d) is beyond the fused kernel's tiles", la, lb, lc, ld);
-  const int Nhb_pad = 16 * npt, Nb_pad = 16 * nat, Nhk_pad = round16(Nhk), Nk_pad = round16(Nk);
+  const int Nhb_pad = 16 * npt * nps, Nb_pad = round16(Nb);
+  const std::vector<uint32_t> border = bra_row_order(Lb, S1, S2, Nhb_pad);
   mderi_status st;
-  void *d_ppb, *d_ppk, *d_offb, *d_offk, *d_Gb, *d_Gk, *d_Hb, *d_Hk;
-  if ((st = ws_get(c, WS_PP_BRA, sizeof(PrimPair) * ppb.size(), &d_ppb)) ||
+  void *d_ppb, *d_ppk, *d_offb, *d_offk, *d_Gb, *d_Gk, *d_Hb, *d_Hk, *d_border;
+  if ((st = ws_get(c, WS_ORDER, sizeof(uint32_t) * border.size(), &d_border)) ||
+      (st = ws_get(c, WS_PP_BRA, sizeof(PrimPair) * ppb.size(), &d_ppb)) ||
       (st = ws_get(c, WS_PP_KET, sizeof(PrimPair) * ppk.size(), &d_ppk)) ||
       (st = ws_get(c, WS_OFF_BRA, sizeof(int) * offb.size(), &d_offb)) ||
       (st = ws_get(c, WS_OFF_KET, sizeof(int) * offk.size(), &d_offk)) ||
@@ -475,13 +550,15 @@ mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb,
     return st;
   if (extra_idx && (st = ws_get(c, WS_IDX, sizeof(int) * extra_idx->size(), d_extra_idx))) return st;
   const size_t stage_need = sizeof(PrimPair) * (ppb.size() + ppk.size()) + sizeof(int) * (offb.size() + offk.size()) +
-                            (extra_idx ? sizeof(int) * extra_idx->size() : 0) + 5 * 256;
+                            (extra_idx ? sizeof(int) * extra_idx->size() : 0) + sizeof(uint32_t) * border.size() +
+                            6 * 256;
   if ((st = stage_begin(c, stage_need))) return st;
   size_t used = 0;
   if ((st = stage_copy(c, d_ppb, ppb.data(), sizeof(PrimPair) * ppb.size(), s, &used)) ||
       (st = stage_copy(c, d_ppk, ppk.data(), sizeof(PrimPair) * ppk.size(), s, &used)) ||
       (st = stage_copy(c, d_offb, offb.data(), sizeof(int) * offb.size(), s, &used)) ||
-      (st = stage_copy(c, d_offk, offk.data(), sizeof(int) * offk.size(), s, &used)))
+      (st = stage_copy(c, d_offk, offk.data(), sizeof(int) * offk.size(), s, &used)) ||
+      (st = stage_copy(c, d_border, border.data(), sizeof(uint32_t) * border.size(), s, &used)))
     return st;
   if (extra_idx && (st = stage_copy(c, *d_extra_idx, extra_idx->data(), sizeof(int) * extra_idx->size(), s, &used)))
     return st;
@@ -499,6 +576,7 @@ mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb,
   pa.Nh_pad = Nhb_pad;
   pa.N_pad = Nb_pad;
   pa.ket_sign = 0;
+  pa.order = (const uint32_t *)d_border;
   pa.G = (double *)d_Gb;
   pa.H = (double *)d_Hb;
   HIP_TRY(launch_pairs(pa, s));
@@ -511,6 +589,7 @@ mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb,
   pa.Nh_pad = Nhk_pad;
   pa.N_pad = Nk_pad;
   pa.ket_sign = 1;
+  pa.order = nullptr;
   pa.G = (double *)d_Gk;
   pa.H = (double *)d_Hk;
   HIP_TRY(launch_pairs(pa, s));
@@ -528,8 +607,15 @@ mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb,
   ea.Nb_pad = Nb_pad;
   ea.Nk_pad = Nk_pad;
   ea.npt = npt;
-  ea.nat = nat;
-  ea.levn = rr_level_stride(L);
+  ea.nps = nps;
+  ea.nct = Nk_pad / 16;
+  ea.dbuf = dbuf;
+  ea.levn = levn;
+  ea.S1 = S1;
+  ea.S2 = S2;
+  ea.cube_sz = cube_sz;
+  ea.maxpp = maxpp;
+  ea.border = (const uint32_t *)d_border;
   ea.diag = diag;
   ea.bra_off = (const int *)d_offb;
   ea.ket_off = (const int *)d_offk;

@@ -35,6 +35,9 @@ __host__ __device__ constexpr int round16(int n) { return (n + 15) & ~15; }
 __host__ __device__ inline uint32_t pack3(int t, int u, int v) {
   return (uint32_t)t | ((uint32_t)u << 8) | ((uint32_t)v << 16);
 }
+// Flag of a padding row in a Hermite row order: the row of H is zero, while
+// its (t,u,v) still names a valid [r] entry for the matrix-core gather.
+constexpr uint32_t kPadRow = 0x80000000u;
 
 // Constant device tables owned by a context.
 struct Tables {
@@ -72,6 +75,8 @@ struct PairArgs {
   int la, lb;
   int Nh, N, Nh_pad, N_pad;
   int ket_sign;  // fold (-1)^{|q|} of Eq. (pq) into a ket transform matrix
+  const uint32_t *order;  // row order (Nh_pad packed (t,u,v); kPadRow set = zero row), or
+                          // nullptr for the global Hermite order with Nh real rows
   Tables tab;
   double *G;  // [npp][4] : zeta_p, P_x, P_y, P_z
   double *H;  // [npp][Nh_pad][N_pad]
@@ -82,8 +87,15 @@ struct Eri4Args {
   int nbra, nket;
   int L, Nhb, Nhk, Nb, Nk;
   int Nhb_pad, Nhk_pad, Nb_pad, Nk_pad;
-  int npt, nat;  // register tile: bra p tiles and ab tiles (Nhb_pad = 16 npt, Nb_pad = 16 nat)
+  int npt;       // p tiles held by a consumer wave
+  int nps;       // bra Hermite rows split over nps waves (Nhb_pad = 16 npt nps)
+  int nct;       // ket column tiles (Nk_pad = 16 nct)
+  int dbuf;      // double-buffered [r] cube
   int levn;      // stride of one R-recursion level buffer (doubles)
+  int S1, S2;    // [r] cube strides: [r] sits at t*S1 + u*S2 + v
+  int cube_sz;   // doubles per cube
+  int maxpp;     // largest (bra + ket) primitive-pair count of one quartet
+  const uint32_t *border;  // bra Hermite row order (Nhb_pad entries, see PairArgs::order)
   int diag;      // Schwarz mode: quartets (ij|ij) only, V receives the diagonal [ij][ab]
   const int *bra_off, *ket_off;  // [n+1] primitive-pair offsets per shell pair
   const double *bra_G, *ket_G;
@@ -97,11 +109,12 @@ hipError_t launch_pairs(const PairArgs &a, hipStream_t s);
 hipError_t launch_eri4(const Eri4Args &a, hipStream_t s);
 // Q[idx[n]] = sqrt(max_ab |D[n][ab]|) for n < npair (Schwarz factors).
 hipError_t launch_schwarz_reduce(int npair, int Nab, const double *D, const int *idx, double *Q, hipStream_t s);
-// Chooses the register tile (p tiles, ab tiles) of the 4-centre kernel for a
-// bra side needing npt x nat tiles; false if none is built.
-bool eri4_pick_tiles(int npt, int nat, int *NPT, int *NAT);
-// LDS bytes needed by the 4-centre kernel for total angular momentum L.
-size_t eri4_lds_bytes(int L, int Nhk_pad, int levn);
+// Chooses the consumer register tile npt, the row split nps and the
+// cube buffering of the 4-centre kernel; false if the class does not fit.
+bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int levn, int maxpp, int *npt, int *nps,
+               int *dbuf);
+// LDS bytes needed by one 4-centre workgroup.
+size_t eri4_lds_bytes(const Eri4Args &a);
 // Stride of a level buffer of the R recursion.
 int rr_level_stride(int L);
 

@@ -69,8 +69,8 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
     const int ph = e / a.N_pad;
     const int ab = e - ph * a.N_pad;
     double h = 0.0;
-    if (ph < a.Nh && ab < a.N) {
-      const uint32_t hp = a.tab.herm[ph];
+    const uint32_t hp = a.order ? a.order[ph] : (ph < a.Nh ? a.tab.herm[ph] : kPadRow);
+    if (!(hp & kPadRow) && ab < a.N) {
       const int t = hp & 0xff, u = (hp >> 8) & 0xff, v = (hp >> 16) & 0xff;
       const int ma = ab / Nbb - la, mb = ab % Nbb - lb;
       const int s0 = a.tab.solid_start[solid_slot(la, ma)], s1 = a.tab.solid_start[solid_slot(la, ma) + 1];
