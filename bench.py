@@ -9,8 +9,13 @@ admitted by Schwarz screening (Q_ij Q_max >= 1e-12) from seeded candidates.
 One step = the six class batches, each including its pair data and transform
 matrices.  Inputs are resident in HBM before timing starts.
 
+The backward/forward ratio is the time of the exchange-energy gradient
+(dE/dR, E = tr(D K)) over the time of the K build itself, both on a synthetic
+cluster (see inputs.cluster; --cluster-atoms sets its size).
+
 Prints one JSON line (rank 0) with per-class rates, the roofline of the
-dominant kernel and the CPU oracle's rate on a bounded sample.
+dominant kernel (its launches timed by HIP events on the launch stream) and
+the CPU oracle's rate on a bounded sample.
 """
 from __future__ import annotations
 
@@ -82,6 +87,38 @@ def cpu_baseline(batches, wall_per_class=2.5):
                       " quartets of each class batch; full-step time extrapolated per class"}
 
 
+def backward_forward(ctx, natom, reps=3):
+    """Exchange gradient time / K-build time on a synthetic cluster."""
+    import torch
+    from paper_2405_01834_amd import inputs
+    sh, atom, pos, D = inputs.cluster(7, natom)
+    basis = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, atom=atom)
+    Dd = torch.tensor(D, device="cuda")
+    K = ctx.kbuild(basis, Dd, tau=TAU)
+    g = ctx.kbuild_grad(basis, Dd, natom, tau=TAU)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        best = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return best
+
+    tf = timed(lambda: ctx.kbuild(basis, Dd, tau=TAU, out=K))
+    tb = timed(lambda: ctx.kbuild_grad(basis, Dd, natom, tau=TAU, out=g))
+    log(f"cluster {natom} atoms, {sh.n} shells, {basis.nao()} AOs: K build {tf * 1e3:.1f} ms, "
+        f"gradient {tb * 1e3:.1f} ms, ratio {tb / tf:.2f}")
+    return {"ratio": tb / tf, "forward_ms": tf * 1e3, "backward_ms": tb * 1e3, "atoms": natom,
+            "shells": int(sh.n), "nao": basis.nao(),
+            "workload": "synthetic cluster, per atom s4 p3 d2 f1 g1 (K=1, exponents geometric 0.08-2000), "
+                        "rank-100 PSD density, Schwarz 1e-12; forward = K build, backward = dE/dR of tr(DK); "
+                        "best of %d" % reps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,7 +127,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-wall", type=float, default=2.5, help="oracle wall seconds per class")
     ap.add_argument("--classes", default="", help="subset, e.g. 4:3,2:1 (l:K)")
+    ap.add_argument("--cluster-atoms", type=int, default=12,
+                    help="atoms of the cluster for the backward/forward ratio (0 = skip)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 2 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 2 GiB")
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the integral batches are independent per GPU and this build "
               "has no multi-GPU path; run with --gpus 1.", file=sys.stderr)
@@ -128,6 +177,8 @@ def main():
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in batches]
           for _ in range(args.steps)]
     per = {k: 0.0 for k in batches}
+    ctx.kernel_times()
+    ctx.kernel_timing(True)
     t0 = time.perf_counter()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
@@ -136,6 +187,9 @@ def main():
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ctx.kernel_timing(False)
+    kt = ctx.kernel_times().reshape(args.steps, len(batches))
+    kern = {k: float(kt[:, i].mean()) for i, k in enumerate(batches)}
     total_ms = start.elapsed_time(stop)
     for s in range(args.steps):
         for i, k in enumerate(batches):
@@ -151,11 +205,12 @@ def main():
         flops = nq * model.eri4_flops(l, l, l, l, K * K, K * K)
         ms = per[(l, K)]
         name = f"[{NAMES[l]}|{NAMES[l]}] K={K}"
-        per_class[name] = {"ms": round(ms, 4), "quartets": nq, "shellsets_per_s": nq / (ms * 1e-3),
+        per_class[name] = {"ms": round(ms, 4), "kernel_ms": round(kern[(l, K)], 4), "quartets": nq,
+                           "shellsets_per_s": nq / (ms * 1e-3),
                            "eris_per_s": eris / (ms * 1e-3), "model_tflops": flops / (ms * 1e-3) / 1e12,
                            "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / model.FP64_PEAK_TFLOPS}
         if flops > dom_flops:
-            dom, dom_flops, dom_ms = name, flops, ms
+            dom, dom_flops, dom_ms = name, flops, kern[(l, K)]
         log(f"{name}: {ms:.3f} ms  {per_class[name]['shellsets_per_s']:.3e} shellsets/s  "
             f"{per_class[name]['model_tflops']:.2f} TFLOP/s ({100 * per_class[name]['frac_fp64_peak']:.1f}% FP64 peak)")
     ms_step = total_ms / args.steps
@@ -171,11 +226,13 @@ def main():
                                "log-U[0.05,500], coefficients U[0.1,1]", "quartets_per_class": NPAIR * NPAIR,
                    "classes": [f"{NAMES[l]}K{K}" for l, K in classes]},
         "per_class": per_class,
-        "roofline": {"bound": "mfma", "kernel": f"eri4 {dom}", "achieved": achieved,
+        "roofline": {"bound": "mfma", "kernel": f"eri4_kernel {dom}", "kernel_ms": dom_ms, "achieved": achieved,
                      "peak": model.FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / model.FP64_PEAK_TFLOPS,
                      "traffic": None},
         "wall_s": wall,
     }
+    if args.cluster_atoms > 0:
+        rec["backward_forward"] = backward_forward(ctx, args.cluster_atoms)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(batches, args.cpu_wall)
     print(json.dumps(rec), flush=True)

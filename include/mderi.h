@@ -107,6 +107,21 @@ mderi_status mderi_eri4(mderi_ctx_t ctx, mderi_basis_t basis, int nbra, const in
                         void *stream);
 
 /*
+ * Class batch of 3-centre integrals (ab|P) (Sec. 2: the 1-centre Hermite
+ * expansion of Eqs. (E1rr)-(E1-aa); the paper writes them [P|ab]).
+ *
+ * pairs_host[npair][2] are int32 shell-index pairs of `basis`, all of one
+ * class (l_a, l_b); aux_host[naux] are int32 shell indices of `aux` (another
+ * uploaded basis, e.g. a fitting basis), all of one l_P.  Writes
+ *     V_dev[ij + npair*(ab + Nab*(mP + N(l_P)*k))]
+ * (ij fastest, ab = m_a*N(l_b) + m_b).  V_elems must be at least
+ * npair*Nab*N(l_P)*naux.  Contracted over all primitives in FP64.
+ */
+mderi_status mderi_eri3(mderi_ctx_t ctx, mderi_basis_t basis, mderi_basis_t aux, int npair, const int32_t *pairs_host,
+                        int naux, const int32_t *aux_host, double *V_dev, size_t V_elems, const mderi_opts *opts,
+                        void *stream);
+
+/*
  * Schwarz factors Q_ij = sqrt(max_ab |(ab|ab)|) of shell pairs, from the
  * diagonal quartets (ij|ij) evaluated by the same MD path as mderi_eri4.
  * Screening (not defined in the paper beyond the remark in Sec. 3 that
@@ -117,6 +132,51 @@ mderi_status mderi_eri4(mderi_ctx_t ctx, mderi_basis_t basis, int nbra, const in
  */
 mderi_status mderi_schwarz(mderi_ctx_t ctx, mderi_basis_t basis, int npair, const int32_t *pairs_host, double *Q_dev,
                            void *stream);
+
+/*
+ * Exchange matrix K_ac = sum_bd (ab|cd) D_bd (Sec. 6, exchange operator; the
+ * paper writes K_bc = sum_ad [ab|cd] D_ad, the same operator for symmetric
+ * D) over every shell quartet of `basis` that survives Schwarz screening
+ * (Q_ij Q_kl >= tau, opts->schwarz_tau, default 1e-12).  Each
+ * symmetry-unique quartet is evaluated once and digested into its four
+ * independent permutational images.  D_dev and K_dev are row-major
+ * nao x nao device matrices over the AOs in shell order (nao must equal
+ * mderi_basis_nao); D must be symmetric; K_dev is overwritten.  The call
+ * synchronises the stream once (to select significant pairs on the host);
+ * the digestion itself is enqueued asynchronously.
+ */
+mderi_status mderi_kbuild(mderi_ctx_t ctx, mderi_basis_t basis, const double *D_dev, double *K_dev, int nao,
+                          const mderi_opts *opts, void *stream);
+
+/*
+ * Kernel timing (measurement support, not part of the method).  While
+ * enabled, every launch of the fused integral kernel (eri4, eri3, Schwarz,
+ * K build and gradient all use it) is bracketed by two HIP events recorded on
+ * the launch stream.  mderi_kernel_times waits for the recorded launches,
+ * writes the durations in milliseconds, in launch order, to ms_host[0..cap)
+ * and stores the number recorded in *count; if cap >= *count the records are
+ * cleared, otherwise they are kept so the call can be repeated with a larger
+ * buffer.
+ */
+mderi_status mderi_kernel_timing(mderi_ctx_t ctx, int enable);
+mderi_status mderi_kernel_times(mderi_ctx_t ctx, double *ms_host, int cap, int *count);
+
+/*
+ * Nuclear gradient of the exchange energy E = tr(D K[D]) =
+ * sum_abcd D_ac (ab|cd) D_bd (the adjoint of mderi_kbuild; the paper gives
+ * no gradient, the derivative follows from differentiating the Gaussians of
+ * Sec. 2: d/dA_x of x_A^{a} e^{-zeta r_A^2} is 2 zeta x_A^{a+1} e^{..} minus
+ * a_x x_A^{a-1} e^{..}, so the MD path runs with bra Hermite degree
+ * l_a+l_b+1 and R up to L+1).
+ * D is held fixed: grad_dev[natom][3] (device, row-major, overwritten)
+ * receives dE/dR_atom summed over the shells of each atom (the atom map given
+ * to mderi_basis_upload; natom must exceed every atom index).  Screening,
+ * D_dev layout and synchronisation are as for mderi_kbuild; D must be
+ * symmetric.  Each quartet of canonical shell pairs is evaluated twice, once
+ * per side, for the derivatives of its bra centres.
+ */
+mderi_status mderi_kbuild_grad(mderi_ctx_t ctx, mderi_basis_t basis, const double *D_dev, int nao, double *grad_dev,
+                               int natom, const mderi_opts *opts, void *stream);
 
 #ifdef __cplusplus
 }

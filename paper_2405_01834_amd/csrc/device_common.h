@@ -58,77 +58,132 @@ __device__ __forceinline__ void lds_wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// One step of Eq. (r) along one direction for a whole m-vector held in
+// registers: with a = [.. k ..]^(m) and b = [.. k-1 ..]^(m) (m = 0..LM),
+// b <- [.. k+1 ..]^(m) = k [.. k-1 ..]^(m+1) + X [.. k ..]^(m+1).
+// Entries past the valid m range carry finite junk that is never stored.
+template <int LM>
+__device__ __forceinline__ void rr_step(double (&a)[LM + 1], double (&b)[LM + 1], double k, double X) {
+#pragma unroll
+  for (int m = 0; m < LM; ++m) b[m] = fma(X, a[m + 1], k * b[m + 1]);
+  b[LM] = 0.0;
+}
+
+// Size (doubles) of the work area of build_R_chains for total L.
+__host__ __device__ constexpr int rr_work_size(int L) { return (L + 1) + (L + 1) * (L + 1) + ntil(L); }
+
+// Offset of the (u, v) m-vector in the packed y-stage buffer (pairs ordered
+// by u, then v; the vector of (u, v) has L-u-v+1 entries).
+__device__ __forceinline__ int uv_base(int L, int u, int v) {
+  const int k0 = L + 1, k1 = L + 1 - u;
+  const int tet = (k0 * (k0 + 1) * (k0 + 2) - k1 * (k1 + 1) * (k1 + 2)) / 6;
+  return tet + v * (L - u + 1) - v * (v - 1) / 2;
+}
+
 // Builds [r]^(0) for all |r| <= L (Eqs. (0m) and (r)) in the LDS cube
-// cube[t*S1 + u*S2 + v] (S2 > L, S1 > L*S2) with a single wave (lanes 0..63)
-// and wave-local synchronisation, so the other waves of the workgroup keep
-// issuing matrix-core work meanwhile.
+// cube[t*S1 + u*S2 + v] (S2 > L, S1 > L*S2) with a single wave and
+// wave-local synchronisation, so the other waves of the workgroup keep
+// issuing matrix-core work meanwhile.  Eq. (r) is applied direction by
+// direction (the same choice of direction as raising the first non-zero
+// component of r): z-chain [00v]^(m) on one lane, y-chains [0uv]^(m) with
+// one lane per v, x-chains [tuv]^(m) with one lane per (u, v); each lane
+// keeps its m-vector in registers (LM >= L at compile time).
 //   p, P: bra Hermite exponent and centre; q, Q: ket.
-//   herm: LDS copy of the Hermite order (degree-major, t then u descending).
-//   lev:  3 rotating level buffers of `levn` doubles each; level n holds
-//         [r]^(m) for |r| = n, m = 0..L-n at [m * T_n + deg_index].
-// A lane owns whole Hermite functions of a level and runs their m chain, so
-// no index division is needed.
-__device__ __forceinline__ void build_R_wave(int L, double p, const double *P, double q, const double *Q,
-                                             double *cube, int S1, int S2, double *lev, int levn,
-                                             const uint32_t *herm, const double *boys, int lane) {
+//   work: rr_work_size(L) doubles of LDS; uv: (u | v << 8) of the pairs
+//         u+v <= L ordered by u+v (longest chains first).
+template <int LM>
+__device__ __forceinline__ void build_R_chains(int L, double p, const double *P, double q, const double *Q,
+                                               double *cube, int S1, int S2, double *work, const uint32_t *uv,
+                                               const double *boys, int lane) {
   const double pq = p + q;
   const double rho = p * q / pq;
   const double X = P[0] - Q[0], Y = P[1] - Q[1], Z = P[2] - Q[2];
   const double T = rho * (X * X + Y * Y + Z * Z);
+  double *f0 = work;                 // [0]^(m), m = 0..L
+  double *zb = f0 + (L + 1);         // [00v]^(m) at v*(L+1) + m
+  double *yb = zb + (L + 1) * (L + 1);  // [0uv]^(m) at uv_base(u, v) + m
   if (lane <= L) {
     double f = 2.0 * 17.493418327624862 / (p * q * sqrt(pq));  // Eq. (0m), 17.49.. = pi^{5/2}
     const double m2r = -2.0 * rho;
     for (int j = 0; j < lane; ++j) f *= m2r;
-    const double v0 = f * boys_m(lane, T, boys);
-    lev[lane] = v0;
-    if (lane == 0) cube[0] = v0;
+    f0[lane] = f * boys_m(lane, T, boys);
   }
   lds_wave_sync();
-  for (int n = 1; n <= L; ++n) {
-    double *cur = lev + (n % 3) * levn;
-    const double *pr1 = lev + ((n - 1) % 3) * levn;
-    const double *pr2 = lev + ((n + 1) % 3) * levn;  // level n-2
-    const int Tn = (n + 1) * (n + 2) / 2, Tn1 = n * (n + 1) / 2, Tn2 = (n - 1) * n / 2;
-    const int M = L - n;  // m = 0..M at this level
-    const uint32_t *hdeg = herm + (n * (n + 1) * (n + 2)) / 6;
-    for (int i = lane; i < Tn; i += 64) {
-      const uint32_t h = hdeg[i];
-      const int t = h & 0xff, u = (h >> 8) & 0xff, v = (h >> 16) & 0xff;
-      // Eq. (r): [r+1_i]^(m) = r_i [r-1_i]^(m+1) + (P_i - Q_i) [r]^(m+1),
-      // raising the first non-zero direction of r
-      double xi, ri;
-      int i1, i2;
-      if (t > 0) {
-        xi = X;
-        ri = t - 1;
-        i1 = deg_index(n - 1, t - 1, u);
-        i2 = t > 1 ? deg_index(n - 2, t - 2, u) : -1;
-      } else if (u > 0) {
-        xi = Y;
-        ri = u - 1;
-        i1 = deg_index(n - 1, 0, u - 1);
-        i2 = u > 1 ? deg_index(n - 2, 0, u - 2) : -1;
-      } else {
-        xi = Z;
-        ri = v - 1;
-        i1 = deg_index(n - 1, 0, 0);
-        i2 = v > 1 ? deg_index(n - 2, 0, 0) : -1;
-      }
-      const double *a1 = pr1 + Tn1 + i1;  // m+1 = 1 at m = 0
-      const double *a2 = pr2 + Tn2 + (i2 < 0 ? 0 : i2);
-      double *o = cur + i;
-      double val = xi * a1[0];
-      if (i2 >= 0) val += ri * a2[0];
-      o[0] = val;
-      cube[t * S1 + u * S2 + v] = val;
-      for (int m = 1; m <= M; ++m) {
-        double w = xi * a1[m * Tn1];
-        if (i2 >= 0) w += ri * a2[m * Tn2];
-        o[m * Tn] = w;
+  double a[LM + 1], b[LM + 1];
+  if (lane == 0) {  // z chain
+#pragma unroll
+    for (int m = 0; m <= LM; ++m) {
+      a[m] = m <= L ? f0[m] : 0.0;
+      b[m] = 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m <= LM; ++m)
+      if (m <= L) zb[m] = a[m];
+    for (int v = 0; v < L; v += 2) {
+      rr_step<LM>(a, b, (double)v, Z);  // b = level v+1
+#pragma unroll
+      for (int m = 0; m <= LM; ++m)
+        if (m <= L - v - 1) zb[(v + 1) * (L + 1) + m] = b[m];
+      if (v + 1 < L) {
+        rr_step<LM>(b, a, (double)(v + 1), Z);  // a = level v+2
+#pragma unroll
+        for (int m = 0; m <= LM; ++m)
+          if (m <= L - v - 2) zb[(v + 2) * (L + 1) + m] = a[m];
       }
     }
-    lds_wave_sync();
   }
+  lds_wave_sync();
+  if (lane <= L) {  // y chains, lane = v
+    const int v = lane, M = L - v;
+#pragma unroll
+    for (int m = 0; m <= LM; ++m) {
+      a[m] = m <= M ? zb[v * (L + 1) + m] : 0.0;
+      b[m] = 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m <= LM; ++m)
+      if (m <= M) yb[uv_base(L, 0, v) + m] = a[m];
+    for (int u = 0; u < M; u += 2) {
+      rr_step<LM>(a, b, (double)u, Y);
+      {
+        const int o = uv_base(L, u + 1, v);
+#pragma unroll
+        for (int m = 0; m <= LM; ++m)
+          if (m <= M - u - 1) yb[o + m] = b[m];
+      }
+      if (u + 1 < M) {
+        rr_step<LM>(b, a, (double)(u + 1), Y);
+        const int o = uv_base(L, u + 2, v);
+#pragma unroll
+        for (int m = 0; m <= LM; ++m)
+          if (m <= M - u - 2) yb[o + m] = a[m];
+      }
+    }
+  }
+  lds_wave_sync();
+  const int npair = (L + 1) * (L + 2) / 2;
+  for (int pi = lane; pi - lane < npair; pi += 64) {  // x chains, lane = (u, v)
+    if (pi < npair) {
+      const int u = uv[pi] & 0xff, v = (uv[pi] >> 8) & 0xff, M = L - u - v;
+      const int base = uv_base(L, u, v);
+#pragma unroll
+      for (int m = 0; m <= LM; ++m) {
+        a[m] = m <= M ? yb[base + m] : 0.0;
+        b[m] = 0.0;
+      }
+      double *cc = cube + u * S2 + v;
+      cc[0] = a[0];
+      for (int t = 0; t < M; t += 2) {
+        rr_step<LM>(a, b, (double)t, X);
+        cc[(t + 1) * S1] = b[0];
+        if (t + 1 < M) {
+          rr_step<LM>(b, a, (double)(t + 1), X);
+          cc[(t + 2) * S1] = a[0];
+        }
+      }
+    }
+  }
+  lds_wave_sync();
 }
 
 // Workgroup id -> work item such that consecutive items land on the same XCD

@@ -26,7 +26,58 @@ namespace {
 
 constexpr int kMaxWaves = 16;
 
-template <int NPT>
+// Exchange digestion of one shellset (ab|cd) held in LDS as v[ab][cd]
+// (Sec. 6, K = sum (ab|cd) D): with K_ac = sum_bd (ab|cd) D_bd, the eight
+// index permutations of a unique shell quartet give the images
+//   K_ac += v D_bd, K_bc += v D_ad, K_ad += v D_bc, K_bd += v D_ac
+// and their transposes; the transposes are added once at the end
+// (K = K' + K'^T).  A quartet stands for its whole permutation orbit, so
+// every image carries w = 2^-(#coincidences among i=j, k=l, ij=kl).
+__device__ __forceinline__ void kdigest(const Eri4Args &a, const double *v, int ij, int kl, int tid) {
+  const int si = a.bra_sh[2 * ij], sj = a.bra_sh[2 * ij + 1];
+  const int sk = a.ket_sh[2 * kl], sl = a.ket_sh[2 * kl + 1];
+  const int na = a.nsa, nb = a.nsb, nc = a.nsc, nd = a.nsd;
+  const int oi = a.ao_off[si], oj = a.ao_off[sj], ok = a.ao_off[sk], ol = a.ao_off[sl];
+  int neq = (si == sj) + (sk == sl) + (a.same_list && ij == kl);
+  const double w = neq == 0 ? 1.0 : neq == 1 ? 0.5 : neq == 2 ? 0.25 : 0.125;
+  const int Nk = a.Nk;  // nc * nd
+  const double *D = a.dm;
+  const size_t n = (size_t)a.nao;
+  // K_ac += sum_bd v[ab][cd] D_bd
+  for (int e = tid; e < na * nc; e += blockDim.x) {
+    const int x = e / nc, c = e - x * nc;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b)
+      for (int d = 0; d < nd; ++d) s += v[(x * nb + b) * Nk + c * nd + d] * D[(oj + b) * n + ol + d];
+    atomicAdd(&a.kx[(oi + x) * n + ok + c], w * s);
+  }
+  // K_bc += sum_ad v[ab][cd] D_ad
+  for (int e = tid; e < nb * nc; e += blockDim.x) {
+    const int b = e / nc, c = e - b * nc;
+    double s = 0.0;
+    for (int x = 0; x < na; ++x)
+      for (int d = 0; d < nd; ++d) s += v[(x * nb + b) * Nk + c * nd + d] * D[(oi + x) * n + ol + d];
+    atomicAdd(&a.kx[(oj + b) * n + ok + c], w * s);
+  }
+  // K_ad += sum_bc v[ab][cd] D_bc
+  for (int e = tid; e < na * nd; e += blockDim.x) {
+    const int x = e / nd, d = e - x * nd;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b)
+      for (int c = 0; c < nc; ++c) s += v[(x * nb + b) * Nk + c * nd + d] * D[(oj + b) * n + ok + c];
+    atomicAdd(&a.kx[(oi + x) * n + ol + d], w * s);
+  }
+  // K_bd += sum_ac v[ab][cd] D_ac
+  for (int e = tid; e < nb * nd; e += blockDim.x) {
+    const int b = e / nd, d = e - b * nd;
+    double s = 0.0;
+    for (int x = 0; x < na; ++x)
+      for (int c = 0; c < nc; ++c) s += v[(x * nb + b) * Nk + c * nd + d] * D[(oi + x) * n + ok + c];
+    atomicAdd(&a.kx[(oj + b) * n + ol + d], w * s);
+  }
+}
+
+template <int NPT, int LM, bool GRAD>
 __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
   extern __shared__ double smem[];
   const int L = a.L;
@@ -34,15 +85,22 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
   const int cube_sz = a.cube_sz;
   double *cube0 = smem;
   double *cube1 = a.dbuf ? smem + cube_sz : smem;
-  double *lev = smem + (a.dbuf ? 2 : 1) * cube_sz;
-  double *gsh = lev + 3 * a.levn;             // G of this quartet's bra then ket primitive pairs
-  double *vsh = gsh + 4 * a.maxpp;            // V[ab][cd] of this quartet (Nb x Nk)
-  uint32_t *hsh = (uint32_t *)(vsh + a.Nb * a.Nk);  // Hermite order, |r| <= L
-  int *offq = (int *)(hsh + ntil(L));
+  double *work = smem + (a.dbuf ? 2 : 1) * cube_sz;  // R-chain work area of the producer
+  double *gsh = work + rr_work_size(L);              // G of this quartet's bra then ket primitive pairs
+  double *gsum = gsh + 4 * a.maxpp;                  // 8 gradient partial sums
+  double *vsh = gsum + 8;                            // V[ab][cd] (or the weights W) of this quartet
+  uint32_t *uvsh = (uint32_t *)(vsh + a.Nb * a.Nk);  // (u, v) pairs, u+v <= L, by u+v
+  int *offq = (int *)(uvsh + (L + 1) * (L + 2) / 2);
 
   const long G = a.diag ? (long)a.nbra : (long)a.nbra * a.nket;
   const long v = xcd_remap(blockIdx.x, G);
   const int ij = (int)(v % a.nbra), kl = a.diag ? ij : (int)(v / a.nbra);
+  if (a.kx) {
+    // screened or symmetry-redundant quartet: the whole workgroup leaves
+    // before any barrier
+    if (a.bra_q[ij] * a.ket_q[kl] < a.tau || (a.same_list && ij < kl)) return;
+  }
+  if (GRAD && a.bra_q[ij] * a.ket_q[kl] < a.tau) return;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -56,14 +114,33 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
 
   for (int e = tid; e < 4 * nbp; e += blockDim.x) gsh[e] = a.bra_G[4 * (size_t)bp0 + e];
   for (int e = tid; e < 4 * nkp; e += blockDim.x) gsh[4 * nbp + e] = a.ket_G[4 * (size_t)kp0 + e];
-  for (int e = tid; e < ntil(L); e += blockDim.x) hsh[e] = a.tab.herm[e];
-  for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) vsh[e] = 0.0;
+  for (int e = tid; e < (L + 1) * (L + 2) / 2; e += blockDim.x) {
+    // e-th pair in the order s = u+v ascending, u ascending
+    int s = 0;
+    while ((s + 1) * (s + 2) / 2 <= e) ++s;
+    const int u = e - s * (s + 1) / 2;
+    uvsh[e] = (uint32_t)u | ((uint32_t)(s - u) << 8);
+  }
+  if (GRAD) {
+    // W[ab][cd] = D_ac D_bd + D_ad D_bc (the two distinct pairings of E = tr(D K))
+    const int si = a.bra_sh[2 * ij], sj = a.bra_sh[2 * ij + 1];
+    const int sk = a.ket_sh[2 * kl], sl = a.ket_sh[2 * kl + 1];
+    const int oi = a.ao_off[si], oj = a.ao_off[sj], ok = a.ao_off[sk], ol = a.ao_off[sl];
+    const size_t n = (size_t)a.nao;
+    for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) {
+      const int ab = e / a.Nk, cd = e - ab * a.Nk;
+      const int x = ab / a.nsb, b = ab - x * a.nsb, c = cd / a.nsd, d = cd - c * a.nsd;
+      vsh[e] = a.dm[(oi + x) * n + ok + c] * a.dm[(oj + b) * n + ol + d] +
+               a.dm[(oi + x) * n + ol + d] * a.dm[(oj + b) * n + ok + c];
+    }
+    if (tid < 8) gsum[tid] = 0.0;
+  } else {
+    for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) vsh[e] = 0.0;
+  }
   for (int q = tid; q < a.Nhk_pad; q += blockDim.x) {
     int o = 0;
-    if (q < a.Nhk) {
-      const uint32_t h = a.tab.herm[q];
-      o = (int)(h & 0xff) * S1 + (int)((h >> 8) & 0xff) * S2 + (int)((h >> 16) & 0xff);
-    }
+    const uint32_t h = a.korder ? a.korder[q] : (q < a.Nhk ? a.tab.herm[q] : kPadRow);
+    if (!(h & kPadRow)) o = (int)(h & 0xff) * S1 + (int)((h >> 8) & 0xff) * S2 + (int)((h >> 16) & 0xff);
     offq[q] = o;
   }
   __syncthreads();
@@ -76,7 +153,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
       const double *Gk = gsh + 4 * (nbp + ik);
       const double P[3] = {Gb[1], Gb[2], Gb[3]};
       const double Q[3] = {Gk[1], Gk[2], Gk[3]};
-      build_R_wave(L, Gb[0], P, Gk[0], Q, cube, S1, S2, lev, a.levn, hsh, a.tab.boys, lane);
+      build_R_chains<LM>(L, Gb[0], P, Gk[0], Q, cube, S1, S2, work, uvsh, a.tab.boys, lane);
     };
     if (nsteps > 0) build(0, cube0);
     for (int n = 0; n < nsteps; ++n) {
@@ -151,7 +228,45 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
         for (int pt = 0; pt < NPT; ++pt) xacc[pt] = mfma16x16x4(aB[pt], bB, xacc[pt]);
         __builtin_amdgcn_sched_barrier(0);
       }
-      if (ik == nkp - 1) {
+      if (GRAD && ik == nkp - 1) {
+        // derivative step: D^(X,x)[ab][cd] = sum_p H^(X,x)[p][ab] X[p][cd] for
+        // X = A, B and x = x, y, z, dotted with W on the fly
+        const size_t mstride = (size_t)a.Nhb_pad * a.Nb_pad;
+#pragma unroll 1
+        for (int mat = 0; mat < 6; ++mat) {
+          const double *Hb = a.bra_H + ((size_t)(bp0 + ib) * 6 + mat) * mstride + (size_t)ph * NPT * 16 * a.Nb_pad;
+          double part = 0.0;
+#pragma unroll 1
+          for (int at = 0; at < nat; ++at) {
+            const double *Ht = Hb + at * 16 + blo;
+            d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = d4{0.0, 0.0, 0.0, 0.0};
+            double h[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h[r] = Ht[(4 * r) * a.Nb_pad];
+#pragma unroll
+            for (int pt = 0; pt < NPT; ++pt) {
+              double hn[4];
+#pragma unroll
+              for (int r = 0; r < 4; ++r) hn[r] = (pt + 1 < NPT) ? Ht[((pt + 1) * 16 + 4 * r) * a.Nb_pad] : 0.0;
+              acc0 = mfma16x16x4(h[0], xacc[pt][0], acc0);
+              acc1 = mfma16x16x4(h[1], xacc[pt][1], acc1);
+              acc0 = mfma16x16x4(h[2], xacc[pt][2], acc0);
+              acc1 = mfma16x16x4(h[3], xacc[pt][3], acc1);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) h[r] = hn[r];
+            }
+            if (col < a.Nk) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int ab = at * 16 + 4 * r + g;
+                if (ab < a.Nb) part += (acc0[r] + acc1[r]) * vsh[ab * a.Nk + col];
+              }
+            }
+          }
+          for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+          if (lane == 0) atomicAdd(&gsum[mat], part);
+        }
+      } else if (ik == nkp - 1) {
         // bra transform: V[ab][cd] += sum_p H_bra[p][ab] X[p][cd], one ab tile
         // at a time (two accumulators), summed into the LDS copy of V
         const double *Hb = a.bra_H + (size_t)(bp0 + ib) * a.Nhb_pad * a.Nb_pad + (size_t)ph * NPT * 16 * a.Nb_pad;
@@ -187,6 +302,26 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
   }
   __syncthreads();  // V complete in LDS
 
+  if (GRAD) {
+    if (tid < 6) {
+      const int si = a.bra_sh[2 * ij], sj = a.bra_sh[2 * ij + 1];
+      const int sk = a.ket_sh[2 * kl], sl = a.ket_sh[2 * kl + 1];
+      // E = sum over ordered combinations (bra pair, ket pair) of canonical
+      // pairs of 2^(1-#(i=j)-#(k=l)) sum W (ab|cd).  The ket-centre terms of
+      // visit (p, q) equal the bra-centre terms of visit (q, p), so each visit
+      // adds twice its bra-centre derivatives.
+      const int neq = (si == sj) + (sk == sl);
+      const double w = neq == 0 ? 4.0 : neq == 1 ? 2.0 : 1.0;
+      const int at = a.atom[tid < 3 ? si : sj];
+      atomicAdd(&a.grad[3 * at + (tid % 3)], w * gsum[tid]);
+    }
+    return;
+  }
+
+  if (a.kx) {
+    kdigest(a, vsh, ij, kl, tid);
+    return;
+  }
   if (a.diag) {
     for (int ab = tid; ab < a.Nb; ab += blockDim.x) a.V[(size_t)ij * a.Nb + ab] = vsh[ab * a.Nk + ab];
     return;
@@ -198,19 +333,19 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
   }
 }
 
-template <int NPT>
+template <int NPT, int LM, bool GRAD>
 hipError_t launch_t(const Eri4Args &a, hipStream_t s) {
   const int waves = a.nct * a.nps + 1;
   const size_t lds = eri4_lds_bytes(a);
   const long G = a.diag ? (long)a.nbra : (long)a.nbra * a.nket;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)eri4_kernel<NPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
+    hipError_t e = hipFuncSetAttribute((const void *)eri4_kernel<NPT, LM, GRAD>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((eri4_kernel<NPT>), dim3((unsigned)G), dim3(64 * waves), lds, s, a);
+  hipLaunchKernelGGL((eri4_kernel<NPT, LM, GRAD>), dim3((unsigned)G), dim3(64 * waves), lds, s, a);
   return hipGetLastError();
 }
 
@@ -224,9 +359,35 @@ __global__ void schwarz_reduce_kernel(int npair, int Nab, const double *__restri
 }
 
 // p tiles per consumer wave that are built.
-const int kTiles[] = {1, 2, 3, 4, 6};
+const int kTiles[] = {1, 2, 3, 4, 6, 7};
+
+__global__ void symmetrize_kernel(int n, const double *__restrict__ in, double *__restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * n) return;
+  const size_t r = e / n, c = e - r * n;
+  out[e] = in[e] + in[c * n + r];
+}
+
+__global__ void zero_kernel(size_t n, double *__restrict__ x) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    x[e] = 0.0;
+}
 
 }  // namespace
+
+hipError_t launch_symmetrize(int n, const double *in, double *out, hipStream_t s) {
+  const size_t tot = (size_t)n * n;
+  if (!tot) return hipSuccess;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(size_t n, double *x, hipStream_t s) {
+  if (!n) return hipSuccess;
+  const size_t blocks = (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, n, x);
+  return hipGetLastError();
+}
 
 hipError_t launch_schwarz_reduce(int npair, int Nab, const double *D, const int *idx, double *Q, hipStream_t s) {
   if (npair <= 0) return hipSuccess;
@@ -234,59 +395,75 @@ hipError_t launch_schwarz_reduce(int npair, int Nab, const double *D, const int 
   return hipGetLastError();
 }
 
-int rr_level_stride(int L) {
-  int mx = L + 1;
-  for (int n = 1; n <= L; ++n) {
-    const int e = (L - n + 1) * (n + 1) * (n + 2) / 2;
-    if (e > mx) mx = e;
-  }
-  return mx;
-}
-
 static size_t cube_region(int cube_sz, int ncube) { return sizeof(double) * (size_t)cube_sz * ncube; }
 
-static size_t side_bytes(int L, int levn, int maxpp, int Nhk_pad, int Nb, int Nk) {
-  return sizeof(double) * (3 * (size_t)levn + 4 * (size_t)maxpp + (size_t)Nb * Nk) + sizeof(uint32_t) * ntil(L) +
-         sizeof(int) * (size_t)Nhk_pad;
+static size_t side_bytes(int L, int maxpp, int Nhk_pad, int Nb, int Nk) {
+  return sizeof(double) * ((size_t)rr_work_size(L) + 4 * (size_t)maxpp + 8 + (size_t)Nb * Nk) +
+         sizeof(uint32_t) * (size_t)((L + 1) * (L + 2) / 2) + sizeof(int) * (size_t)Nhk_pad;
 }
 
 size_t eri4_lds_bytes(const Eri4Args &a) {
-  return cube_region(a.cube_sz, a.dbuf ? 2 : 1) + side_bytes(a.L, a.levn, a.maxpp, a.Nhk_pad, a.Nb, a.Nk);
+  return cube_region(a.cube_sz, a.dbuf ? 2 : 1) + side_bytes(a.L, a.maxpp, a.Nhk_pad, a.Nb, a.Nk);
 }
 
-bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int levn, int maxpp, int *npt, int *nps,
+bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int maxpp, bool grad, int *npt, int *nps,
                int *dbuf) {
   const int need_p = round16(Nhb) / 16, nct = round16(Nk) / 16;
-  int parts = 1;
-  while ((need_p + parts - 1) / parts > 6) ++parts;
-  const int per = (need_p + parts - 1) / parts;
+  // bra rows split over `parts` waves of at most 6 tiles each; when that
+  // needs more waves than a workgroup holds, 7-tile waves (gradient mode's
+  // [gg| bra with Hermite degree 9 is the one such case)
   *npt = 0;
-  for (int t : kTiles)
-    if (t >= per) {
-      *npt = t;
-      break;
-    }
-  if (!*npt || nct * parts + 1 > kMaxWaves) return false;
-  *nps = parts;
+  for (int maxt = 6; maxt <= (grad ? 7 : 6) && !*npt; ++maxt) {
+    int parts = 1;
+    while ((need_p + parts - 1) / parts > maxt) ++parts;
+    const int per = (need_p + parts - 1) / parts;
+    if (nct * parts + 1 > kMaxWaves) continue;
+    for (int t : kTiles)
+      if (t >= per) {
+        *npt = t;
+        break;
+      }
+    *nps = parts;
+  }
+  if (!*npt) return false;
   const size_t lds_budget = 160 * 1024;
-  const size_t rest = side_bytes(L, levn, maxpp, Nhk_pad, Nb, Nk);
+  if (L > 26) return false;
+  const size_t rest = side_bytes(L, maxpp, Nhk_pad, Nb, Nk);
   if (cube_region(cube_sz, 2) + rest <= lds_budget) *dbuf = 1;
   else if (cube_region(cube_sz, 1) + rest <= lds_budget) *dbuf = 0;
   else return false;
   return true;
 }
 
+template <int LM, bool GRAD>
+hipError_t launch_lm(const Eri4Args &a, hipStream_t s) {
+  switch (a.npt) {
+    case 1: return launch_t<1, LM, GRAD>(a, s);
+    case 2: return launch_t<2, LM, GRAD>(a, s);
+    case 3: return launch_t<3, LM, GRAD>(a, s);
+    case 4: return launch_t<4, LM, GRAD>(a, s);
+    case 6: return launch_t<6, LM, GRAD>(a, s);
+    case 7:
+      if constexpr (GRAD) return launch_t<7, LM, GRAD>(a, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <bool GRAD>
+hipError_t launch_g(const Eri4Args &a, hipStream_t s) {
+  // register length of the producer's m-vectors: smallest bound >= L
+  if (a.L <= 8) return launch_lm<8, GRAD>(a, s);
+  if (a.L <= 10) return launch_lm<10, GRAD>(a, s);
+  if (a.L <= 16) return launch_lm<16, GRAD>(a, s);
+  if (a.L <= 26) return launch_lm<26, GRAD>(a, s);
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_eri4(const Eri4Args &a, hipStream_t s) {
   if (a.nbra <= 0 || a.nket <= 0) return hipSuccess;
   if (a.nct * a.nps + 1 > kMaxWaves) return hipErrorInvalidValue;
-  switch (a.npt) {
-    case 1: return launch_t<1>(a, s);
-    case 2: return launch_t<2>(a, s);
-    case 3: return launch_t<3>(a, s);
-    case 4: return launch_t<4>(a, s);
-    case 6: return launch_t<6>(a, s);
-    default: return hipErrorInvalidValue;
-  }
+  return a.grad ? launch_g<true>(a, s) : launch_g<false>(a, s);
 }
 
 }  // namespace mderi

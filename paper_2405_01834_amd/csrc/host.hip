@@ -171,7 +171,7 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 // context
 // ---------------------------------------------------------------------------
 enum WsSlot {
-  WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_ORDER, WS_COUNT
+  WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_ORDER, WS_KORDER, WS_QB, WS_QK, WS_SHB, WS_SHK, WS_KTMP, WS_QALL, WS_PAIRS, WS_COUNT
 };
 
 struct mderi_ctx {
@@ -184,12 +184,16 @@ struct mderi_ctx {
   size_t stage_cap = 0;
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
+  // kernel timing: when on, each fused-kernel launch is bracketed by a pair
+  // of events on its stream (pairs are recycled after they are read)
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
 };
 
 struct mderi_basis {
   mderi_ctx *ctx = nullptr;
   int nshell = 0, nao = 0;
-  std::vector<int> l, K, poff, atom;
+  std::vector<int> l, K, poff, atom, ao_off;
   DevBasis dev;
 };
 
@@ -307,7 +311,40 @@ extern "C" void mderi_destroy(mderi_ctx_t c) {
   for (int i = 0; i < WS_COUNT; ++i) (void)hipFree(c->ws[i]);
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  for (auto *v : {&c->ev_used, &c->ev_free})
+    for (auto &e : *v) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
   delete c;
+}
+
+extern "C" mderi_status mderi_kernel_timing(mderi_ctx_t c, int enable) {
+  if (!c) return fail(MDERI_EINVAL, "mderi_kernel_timing: NULL context");
+  c->timing = enable != 0;
+  return MDERI_OK;
+}
+
+extern "C" mderi_status mderi_kernel_times(mderi_ctx_t c, double *ms_host, int cap, int *count) {
+  if (!c || !count) return fail(MDERI_EINVAL, "mderi_kernel_times: NULL context or count");
+  if (cap > 0 && !ms_host) return fail(MDERI_EINVAL, "mderi_kernel_times: NULL output with cap %d", cap);
+  HIP_TRY(hipSetDevice(c->device));
+  const int n = (int)c->ev_used.size();
+  *count = n;
+  for (int i = 0; i < n; ++i) {
+    auto &e = c->ev_used[i];
+    if (i < cap) {
+      HIP_TRY(hipEventSynchronize(e.second));
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+      ms_host[i] = ms;
+    }
+  }
+  if (cap >= n) {
+    c->ev_free.insert(c->ev_free.end(), c->ev_used.begin(), c->ev_used.end());
+    c->ev_used.clear();
+  }
+  return MDERI_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -327,6 +364,7 @@ extern "C" mderi_status mderi_basis_upload(mderi_ctx_t c, int nshell, const int 
   b->K.assign(nprim, nprim + nshell);
   b->poff.resize(nshell);
   b->atom.resize(nshell);
+  b->ao_off.resize(nshell);
   int np = 0;
   for (int i = 0; i < nshell; ++i) {
     if (l[i] < 0 || l[i] > kLmax) {
@@ -339,6 +377,7 @@ extern "C" mderi_status mderi_basis_upload(mderi_ctx_t c, int nshell, const int 
     }
     b->poff[i] = np;
     np += nprim[i];
+    b->ao_off[i] = b->nao;
     b->nao += 2 * l[i] + 1;
     b->atom[i] = atom ? atom[i] : i;
     for (int x = 0; x < 3; ++x)
@@ -387,6 +426,7 @@ extern "C" mderi_status mderi_basis_upload(mderi_ctx_t c, int nshell, const int 
   if (e == hipSuccess) e = upload(&b->dev.K, b->K);
   if (e == hipSuccess) e = upload(&b->dev.poff, b->poff);
   if (e == hipSuccess) e = upload(&b->dev.atom, b->atom);
+  if (e == hipSuccess) e = upload(&b->dev.ao_off, b->ao_off);
   if (e == hipSuccess) e = upload(&b->dev.centers, cen);
   if (e == hipSuccess) e = upload(&b->dev.exps, ex);
   if (e == hipSuccess) e = upload(&b->dev.coefs, cn);
@@ -405,6 +445,7 @@ extern "C" void mderi_basis_free(mderi_basis_t b) {
   (void)hipFree(b->dev.K);
   (void)hipFree(b->dev.poff);
   (void)hipFree(b->dev.atom);
+  (void)hipFree(b->dev.ao_off);
   (void)hipFree(b->dev.centers);
   (void)hipFree(b->dev.exps);
   (void)hipFree(b->dev.coefs);
@@ -512,32 +553,74 @@ std::vector<uint32_t> bra_row_order(int Lb, int S1, int S2, int Nh_pad) {
   return out;
 }
 
+// One side of a class batch: shell pairs of one class (or single shells of
+// one l when one_centre) expanded into primitive pairs.
+struct Side {
+  const mderi_basis *b;
+  int la, lb;
+  bool one_centre;
+  std::vector<PrimPair> pp;
+  std::vector<int> off;
+};
+
+// Top-degree Hermite functions of degree l (t, then u descending), the only
+// ones a single solid-harmonic Gaussian expands into (Hobson's theorem; the
+// lower rows of its transform matrix vanish identically), padded with
+// kPadRow to a multiple of 8.
+std::vector<uint32_t> top_degree_rows(int l) {
+  std::vector<uint32_t> r;
+  for (int t = l; t >= 0; --t)
+    for (int u = l - t; u >= 0; --u) r.push_back(pack3(t, u, l - t - u));
+  while (r.size() % 8) r.push_back(kPadRow);
+  return r;
+}
+
 // Enqueues pair data (bra and ket) and the fused kernel for one class batch.
 // diag != 0 evaluates only (ij|ij) (bra list == ket list) and writes the
 // diagonal [ij][ab] to V.
-mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb, int lc, int ld,
-                             const std::vector<PrimPair> &ppb, const std::vector<int> &offb,
-                             const std::vector<PrimPair> &ppk, const std::vector<int> &offk, int diag, double *V,
-                             const std::vector<int> *extra_idx, void **d_extra_idx, hipStream_t s) {
-  const int nbra = (int)offb.size() - 1, nket = (int)offk.size() - 1;
-  const int Lb = la + lb, Lk = lc + ld, L = Lb + Lk;
-  const int Nb = nsph(la) * nsph(lb), Nk = nsph(lc) * nsph(ld);
-  const int Nhb = ntil(Lb), Nhk = ntil(Lk);
-  const int Nhk_pad = (Nhk + 7) & ~7, Nk_pad = round16(Nk), levn = rr_level_stride(L);
+// Exchange-digest parameters of a class batch (see kdigest in eri4.hip).
+struct Digest {
+  double *kx;
+  const double *dm;
+  int nao;
+  double tau;
+  std::vector<double> qb, qk;       // Schwarz factors per bra / ket pair
+  std::vector<int32_t> shb, shk;    // shell pairs [n][2]
+  // gradient mode: instead of digesting into K, add twice the bra-centre
+  // derivatives of sum W (ab|cd) to grad[atom][xyz] (bra pair data in
+  // derivative form, Hermite rows up to l_a+l_b+1)
+  double *grad = nullptr;
+  const int *atom = nullptr;
+};
+
+mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int diag, double *V,
+                             const std::vector<int> *extra_idx, void **d_extra_idx, hipStream_t s,
+                             const Digest *dg = nullptr) {
+  const int nbra = (int)bra.off.size() - 1, nket = (int)ket.off.size() - 1;
+  const int la = bra.la, lb = bra.lb, lc = ket.la, ld = ket.one_centre ? 0 : ket.lb;
+  const bool grad = dg && dg->grad;
+  const int Lb = la + lb + (grad ? 1 : 0), Lk = lc + ld, L = Lb + Lk;
+  const int Nb = nsph(la) * nsph(lb), Nk = ket.one_centre ? nsph(lc) : nsph(lc) * nsph(ld);
+  const int Nhb = ntil(Lb);
+  const std::vector<uint32_t> korder = ket.one_centre ? top_degree_rows(lc) : std::vector<uint32_t>();
+  const int Nhk = ket.one_centre ? (lc + 1) * (lc + 2) / 2 : ntil(Lk);
+  const int Nhk_pad = (Nhk + 7) & ~7, Nk_pad = round16(Nk);
   int S1 = 1, S2 = 1;
   choose_cube(L, Lb, &S1, &S2);
   const int cube_sz = (L * S1 + 2) & ~1;
   int maxb = 0, maxk = 0;
-  for (int i = 0; i < nbra; ++i) maxb = std::max(maxb, offb[i + 1] - offb[i]);
-  for (int i = 0; i < nket; ++i) maxk = std::max(maxk, offk[i + 1] - offk[i]);
+  for (int i = 0; i < nbra; ++i) maxb = std::max(maxb, bra.off[i + 1] - bra.off[i]);
+  for (int i = 0; i < nket; ++i) maxk = std::max(maxk, ket.off[i + 1] - ket.off[i]);
   const int maxpp = maxb + maxk;
   int npt = 0, nps = 0, dbuf = 0;
-  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, levn, maxpp, &npt, &nps, &dbuf))
+  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, grad, &npt, &nps, &dbuf))
     return fail(MDERI_EUNSUPPORTED, "class (%d%d|%d%d) is beyond the fused kernel's tiles", la, lb, lc, ld);
   const int Nhb_pad = 16 * npt * nps, Nb_pad = round16(Nb);
   const std::vector<uint32_t> border = bra_row_order(Lb, S1, S2, Nhb_pad);
+  const std::vector<PrimPair> &ppb = bra.pp, &ppk = ket.pp;
+  const std::vector<int> &offb = bra.off, &offk = ket.off;
   mderi_status st;
-  void *d_ppb, *d_ppk, *d_offb, *d_offk, *d_Gb, *d_Gk, *d_Hb, *d_Hk, *d_border;
+  void *d_ppb, *d_ppk, *d_offb, *d_offk, *d_Gb, *d_Gk, *d_Hb, *d_Hk, *d_border, *d_korder = nullptr;
   if ((st = ws_get(c, WS_ORDER, sizeof(uint32_t) * border.size(), &d_border)) ||
       (st = ws_get(c, WS_PP_BRA, sizeof(PrimPair) * ppb.size(), &d_ppb)) ||
       (st = ws_get(c, WS_PP_KET, sizeof(PrimPair) * ppk.size(), &d_ppk)) ||
@@ -545,13 +628,23 @@ mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb,
       (st = ws_get(c, WS_OFF_KET, sizeof(int) * offk.size(), &d_offk)) ||
       (st = ws_get(c, WS_G_BRA, sizeof(double) * 4 * ppb.size(), &d_Gb)) ||
       (st = ws_get(c, WS_G_KET, sizeof(double) * 4 * ppk.size(), &d_Gk)) ||
-      (st = ws_get(c, WS_H_BRA, sizeof(double) * (size_t)Nhb_pad * Nb_pad * ppb.size(), &d_Hb)) ||
+      (st = ws_get(c, WS_H_BRA, sizeof(double) * (grad ? 6 : 1) * (size_t)Nhb_pad * Nb_pad * ppb.size(), &d_Hb)) ||
       (st = ws_get(c, WS_H_KET, sizeof(double) * (size_t)Nhk_pad * Nk_pad * ppk.size(), &d_Hk)))
+    return st;
+  if (!korder.empty() && (st = ws_get(c, WS_KORDER, sizeof(uint32_t) * korder.size(), &d_korder))) return st;
+  void *d_qb = nullptr, *d_qk = nullptr, *d_shb = nullptr, *d_shk = nullptr;
+  if (dg && ((st = ws_get(c, WS_QB, sizeof(double) * dg->qb.size(), &d_qb)) ||
+             (st = ws_get(c, WS_QK, sizeof(double) * dg->qk.size(), &d_qk)) ||
+             (st = ws_get(c, WS_SHB, sizeof(int32_t) * dg->shb.size(), &d_shb)) ||
+             (st = ws_get(c, WS_SHK, sizeof(int32_t) * dg->shk.size(), &d_shk))))
     return st;
   if (extra_idx && (st = ws_get(c, WS_IDX, sizeof(int) * extra_idx->size(), d_extra_idx))) return st;
   const size_t stage_need = sizeof(PrimPair) * (ppb.size() + ppk.size()) + sizeof(int) * (offb.size() + offk.size()) +
                             (extra_idx ? sizeof(int) * extra_idx->size() : 0) + sizeof(uint32_t) * border.size() +
-                            6 * 256;
+                            sizeof(uint32_t) * korder.size() + 12 * 256 +
+                            (dg ? sizeof(double) * (dg->qb.size() + dg->qk.size()) +
+                                      sizeof(int32_t) * (dg->shb.size() + dg->shk.size())
+                                : 0);
   if ((st = stage_begin(c, stage_need))) return st;
   size_t used = 0;
   if ((st = stage_copy(c, d_ppb, ppb.data(), sizeof(PrimPair) * ppb.size(), s, &used)) ||
@@ -560,12 +653,20 @@ mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb,
       (st = stage_copy(c, d_offk, offk.data(), sizeof(int) * offk.size(), s, &used)) ||
       (st = stage_copy(c, d_border, border.data(), sizeof(uint32_t) * border.size(), s, &used)))
     return st;
+  if (!korder.empty() &&
+      (st = stage_copy(c, d_korder, korder.data(), sizeof(uint32_t) * korder.size(), s, &used)))
+    return st;
   if (extra_idx && (st = stage_copy(c, *d_extra_idx, extra_idx->data(), sizeof(int) * extra_idx->size(), s, &used)))
+    return st;
+  if (dg && ((st = stage_copy(c, d_qb, dg->qb.data(), sizeof(double) * dg->qb.size(), s, &used)) ||
+             (st = stage_copy(c, d_qk, dg->qk.data(), sizeof(double) * dg->qk.size(), s, &used)) ||
+             (st = stage_copy(c, d_shb, dg->shb.data(), sizeof(int32_t) * dg->shb.size(), s, &used)) ||
+             (st = stage_copy(c, d_shk, dg->shk.data(), sizeof(int32_t) * dg->shk.size(), s, &used))))
     return st;
   if ((st = stage_end(c, s))) return st;
 
   PairArgs pa{};
-  pa.basis = b->dev;
+  pa.basis = bra.b->dev;
   pa.tab = c->tab;
   pa.npp = (int)ppb.size();
   pa.pp = (const PrimPair *)d_ppb;
@@ -576,10 +677,13 @@ mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb,
   pa.Nh_pad = Nhb_pad;
   pa.N_pad = Nb_pad;
   pa.ket_sign = 0;
+  pa.one_centre = 0;
+  pa.deriv = grad ? 1 : 0;
   pa.order = (const uint32_t *)d_border;
   pa.G = (double *)d_Gb;
   pa.H = (double *)d_Hb;
   HIP_TRY(launch_pairs(pa, s));
+  pa.basis = ket.b->dev;
   pa.npp = (int)ppk.size();
   pa.pp = (const PrimPair *)d_ppk;
   pa.la = lc;
@@ -589,7 +693,9 @@ mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb,
   pa.Nh_pad = Nhk_pad;
   pa.N_pad = Nk_pad;
   pa.ket_sign = 1;
-  pa.order = nullptr;
+  pa.one_centre = ket.one_centre ? 1 : 0;
+  pa.deriv = 0;
+  pa.order = (const uint32_t *)d_korder;
   pa.G = (double *)d_Gk;
   pa.H = (double *)d_Hk;
   HIP_TRY(launch_pairs(pa, s));
@@ -610,12 +716,12 @@ mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb,
   ea.nps = nps;
   ea.nct = Nk_pad / 16;
   ea.dbuf = dbuf;
-  ea.levn = levn;
   ea.S1 = S1;
   ea.S2 = S2;
   ea.cube_sz = cube_sz;
   ea.maxpp = maxpp;
   ea.border = (const uint32_t *)d_border;
+  ea.korder = (const uint32_t *)d_korder;
   ea.diag = diag;
   ea.bra_off = (const int *)d_offb;
   ea.ket_off = (const int *)d_offk;
@@ -625,7 +731,58 @@ mderi_status run_class_batch(mderi_ctx *c, const mderi_basis *b, int la, int lb,
   ea.ket_H = (const double *)d_Hk;
   ea.tab = c->tab;
   ea.V = V;
-  HIP_TRY(launch_eri4(ea, s));
+  if (dg) {
+    ea.kx = grad ? nullptr : dg->kx;
+    ea.grad = grad ? dg->grad : nullptr;
+    ea.atom = grad ? dg->atom : nullptr;
+    ea.dm = dg->dm;
+    ea.nao = dg->nao;
+    ea.tau = dg->tau;
+    ea.same_list = (!grad && &bra == &ket) ? 1 : 0;
+    ea.bra_q = (const double *)d_qb;
+    ea.ket_q = (const double *)d_qk;
+    ea.bra_sh = (const int *)d_shb;
+    ea.ket_sh = (const int *)d_shk;
+    ea.ao_off = bra.b->dev.ao_off;
+    ea.nsa = nsph(la);
+    ea.nsb = nsph(lb);
+    ea.nsc = nsph(lc);
+    ea.nsd = nsph(ld);
+  }
+  if (c->timing) {
+    if (c->ev_free.empty()) {
+      std::pair<hipEvent_t, hipEvent_t> e;
+      HIP_TRY(hipEventCreate(&e.first));
+      HIP_TRY(hipEventCreate(&e.second));
+      c->ev_free.push_back(e);
+    }
+    const auto e = c->ev_free.back();
+    c->ev_free.pop_back();
+    c->ev_used.push_back(e);
+    HIP_TRY(hipEventRecord(e.first, s));
+    HIP_TRY(launch_eri4(ea, s));
+    HIP_TRY(hipEventRecord(e.second, s));
+  } else {
+    HIP_TRY(launch_eri4(ea, s));
+  }
+  return MDERI_OK;
+}
+
+// Validates single shells of one l and expands them into primitives.
+mderi_status expand_shells(const mderi_basis *b, int n, const int32_t *idx, const char *what, int *l, Side &side) {
+  if (n <= 0) return fail(MDERI_EINVAL, "%s: need at least one shell (got %d)", what, n);
+  if (!idx) return fail(MDERI_EINVAL, "%s: NULL shell list", what);
+  side.pp.clear();
+  side.off.assign(1, 0);
+  for (int i = 0; i < n; ++i) {
+    const int s0 = idx[i];
+    if (s0 < 0 || s0 >= b->nshell) return fail(MDERI_EINVAL, "%s: shell %d = %d out of range [0,%d)", what, i, s0, b->nshell);
+    if (i == 0) *l = b->l[s0];
+    else if (b->l[s0] != *l)
+      return fail(MDERI_EINVAL, "%s: shell %d has l=%d but the batch has l=%d", what, i, b->l[s0], *l);
+    for (int k = 0; k < b->K[s0]; ++k) side.pp.push_back(PrimPair{s0, s0, b->poff[s0] + k, b->poff[s0] + k});
+    side.off.push_back((int)side.pp.size());
+  }
   return MDERI_OK;
 }
 
@@ -637,17 +794,32 @@ extern "C" mderi_status mderi_eri4(mderi_ctx_t c, mderi_basis_t b, int nbra, con
   if (!c || !b) return fail(MDERI_EINVAL, "mderi_eri4: NULL context or basis");
   if (b->ctx != c) return fail(MDERI_EINVAL, "mderi_eri4: basis belongs to another context");
   if (opts && opts->precision != 0) return fail(MDERI_EUNSUPPORTED, "mderi_eri4: precision %d", opts->precision);
-  int la, lb, lc, ld;
-  std::vector<PrimPair> ppb, ppk;
-  std::vector<int> offb, offk;
+  Side sb{b, 0, 0, false, {}, {}}, sk{b, 0, 0, false, {}, {}};
   mderi_status st;
-  if ((st = expand_pairs(b, nbra, bra, "bra", &la, &lb, ppb, offb)) != MDERI_OK) return st;
-  if ((st = expand_pairs(b, nket, ket, "ket", &lc, &ld, ppk, offk)) != MDERI_OK) return st;
-  const size_t need = (size_t)nbra * nsph(la) * nsph(lb) * nsph(lc) * nsph(ld) * nket;
+  if ((st = expand_pairs(b, nbra, bra, "bra", &sb.la, &sb.lb, sb.pp, sb.off)) != MDERI_OK) return st;
+  if ((st = expand_pairs(b, nket, ket, "ket", &sk.la, &sk.lb, sk.pp, sk.off)) != MDERI_OK) return st;
+  const size_t need = (size_t)nbra * nsph(sb.la) * nsph(sb.lb) * nsph(sk.la) * nsph(sk.lb) * nket;
   if (!V) return fail(MDERI_EINVAL, "mderi_eri4: NULL output");
   if (V_elems < need) return fail(MDERI_ESIZE, "mderi_eri4: output holds %zu doubles, needs %zu", V_elems, need);
   HIP_TRY(hipSetDevice(c->device));
-  return run_class_batch(c, b, la, lb, lc, ld, ppb, offb, ppk, offk, 0, V, nullptr, nullptr, (hipStream_t)stream);
+  return run_class_batch(c, sb, sk, 0, V, nullptr, nullptr, (hipStream_t)stream);
+}
+
+extern "C" mderi_status mderi_eri3(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t aux, int npair, const int32_t *pairs,
+                                   int naux, const int32_t *auxidx, double *V, size_t V_elems, const mderi_opts *opts,
+                                   void *stream) {
+  if (!c || !b || !aux) return fail(MDERI_EINVAL, "mderi_eri3: NULL context or basis");
+  if (b->ctx != c || aux->ctx != c) return fail(MDERI_EINVAL, "mderi_eri3: basis belongs to another context");
+  if (opts && opts->precision != 0) return fail(MDERI_EUNSUPPORTED, "mderi_eri3: precision %d", opts->precision);
+  Side sb{b, 0, 0, false, {}, {}}, sk{aux, 0, 0, true, {}, {}};
+  mderi_status st;
+  if ((st = expand_pairs(b, npair, pairs, "pairs", &sb.la, &sb.lb, sb.pp, sb.off)) != MDERI_OK) return st;
+  if ((st = expand_shells(aux, naux, auxidx, "aux", &sk.la, sk)) != MDERI_OK) return st;
+  const size_t need = (size_t)npair * nsph(sb.la) * nsph(sb.lb) * nsph(sk.la) * naux;
+  if (!V) return fail(MDERI_EINVAL, "mderi_eri3: NULL output");
+  if (V_elems < need) return fail(MDERI_ESIZE, "mderi_eri3: output holds %zu doubles, needs %zu", V_elems, need);
+  HIP_TRY(hipSetDevice(c->device));
+  return run_class_batch(c, sb, sk, 0, V, nullptr, nullptr, (hipStream_t)stream);
 }
 
 extern "C" mderi_status mderi_schwarz(mderi_ctx_t c, mderi_basis_t b, int npair, const int32_t *pairs, double *Q,
@@ -673,16 +845,165 @@ extern "C" mderi_status mderi_schwarz(mderi_ctx_t c, mderi_basis_t b, int npair,
       sub[2 * k] = pairs[2 * grp[k]];
       sub[2 * k + 1] = pairs[2 * grp[k] + 1];
     }
-    int la, lb;
-    std::vector<PrimPair> pp;
-    std::vector<int> off;
-    if ((st = expand_pairs(b, (int)grp.size(), sub.data(), "pairs", &la, &lb, pp, off)) != MDERI_OK) return st;
-    const int Nab = nsph(la) * nsph(lb);
+    Side sd{b, 0, 0, false, {}, {}};
+    if ((st = expand_pairs(b, (int)grp.size(), sub.data(), "pairs", &sd.la, &sd.lb, sd.pp, sd.off)) != MDERI_OK)
+      return st;
+    const int Nab = nsph(sd.la) * nsph(sd.lb);
     void *d_diag, *d_idx = nullptr;
     if ((st = ws_get(c, WS_DIAG, sizeof(double) * grp.size() * Nab, &d_diag))) return st;
-    if ((st = run_class_batch(c, b, la, lb, la, lb, pp, off, pp, off, 1, (double *)d_diag, &grp, &d_idx, s)))
-      return st;
+    if ((st = run_class_batch(c, sd, sd, 1, (double *)d_diag, &grp, &d_idx, s))) return st;
     HIP_TRY(launch_schwarz_reduce((int)grp.size(), Nab, (const double *)d_diag, (const int *)d_idx, Q, s));
+  }
+  return MDERI_OK;
+}
+
+namespace {
+
+// Canonical shell pairs (l_i > l_j, or l_i == l_j and i >= j) whose Schwarz
+// factor passes Q_ij Q_max >= tau, grouped by class (l_i, l_j) and expanded
+// into primitive pairs.  Synchronises the stream once (the selection runs on
+// the host).
+struct PairSets {
+  std::vector<int32_t> pairs;          // all canonical pairs [np][2]
+  std::vector<double> q;               // their Schwarz factors
+  std::vector<std::vector<int>> cls;   // significant pairs per class
+  std::vector<Side> sides;             // their primitive expansion
+};
+
+mderi_status select_pairs(mderi_ctx *c, mderi_basis *b, double tau, hipStream_t s, PairSets &ps) {
+  for (int i = 0; i < b->nshell; ++i)
+    for (int j = 0; j < b->nshell; ++j)
+      if (b->l[i] > b->l[j] || (b->l[i] == b->l[j] && i >= j)) {
+        ps.pairs.push_back(i);
+        ps.pairs.push_back(j);
+      }
+  const int np = (int)ps.pairs.size() / 2;
+  mderi_status st;
+  void *d_q;
+  if ((st = ws_get(c, WS_QALL, sizeof(double) * np, &d_q))) return st;
+  if ((st = mderi_schwarz(c, b, np, ps.pairs.data(), (double *)d_q, s))) return st;
+  ps.q.assign(np, 0.0);
+  HIP_TRY(hipMemcpyAsync(ps.q.data(), d_q, sizeof(double) * np, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double qmax = 0.0;
+  for (double x : ps.q) qmax = std::max(qmax, x);
+  const int ncls = (kLmax + 1) * (kLmax + 1);
+  ps.cls.assign(ncls, {});
+  for (int p = 0; p < np; ++p)
+    if (ps.q[p] * qmax >= tau) ps.cls[b->l[ps.pairs[2 * p]] * (kLmax + 1) + b->l[ps.pairs[2 * p + 1]]].push_back(p);
+  ps.sides.assign(ncls, Side{b, 0, 0, false, {}, {}});
+  for (int ci = 0; ci < ncls; ++ci) {
+    if (ps.cls[ci].empty()) continue;
+    std::vector<int32_t> sub;
+    for (int p : ps.cls[ci]) {
+      sub.push_back(ps.pairs[2 * p]);
+      sub.push_back(ps.pairs[2 * p + 1]);
+    }
+    Side &sd = ps.sides[ci];
+    if ((st = expand_pairs(b, (int)ps.cls[ci].size(), sub.data(), "pairs", &sd.la, &sd.lb, sd.pp, sd.off))) return st;
+  }
+  return MDERI_OK;
+}
+
+// Fills the per-pair screening data of a (bra class, ket class) block.
+void digest_block(const PairSets &ps, int c1, int c2, Digest &dg) {
+  dg.qb.clear();
+  dg.qk.clear();
+  dg.shb.clear();
+  dg.shk.clear();
+  for (int p : ps.cls[c1]) {
+    dg.qb.push_back(ps.q[p]);
+    dg.shb.push_back(ps.pairs[2 * p]);
+    dg.shb.push_back(ps.pairs[2 * p + 1]);
+  }
+  for (int p : ps.cls[c2]) {
+    dg.qk.push_back(ps.q[p]);
+    dg.shk.push_back(ps.pairs[2 * p]);
+    dg.shk.push_back(ps.pairs[2 * p + 1]);
+  }
+}
+
+mderi_status check_density(const char *fn, mderi_ctx *c, mderi_basis *b, const double *D, int nao,
+                           const mderi_opts *opts) {
+  if (!c || !b) return fail(MDERI_EINVAL, "%s: NULL context or basis", fn);
+  if (b->ctx != c) return fail(MDERI_EINVAL, "%s: basis belongs to another context", fn);
+  if (!D) return fail(MDERI_EINVAL, "%s: NULL density", fn);
+  if (nao != b->nao) return fail(MDERI_EINVAL, "%s: nao=%d but the basis has %d AOs", fn, nao, b->nao);
+  if (opts && opts->precision != 0) return fail(MDERI_EUNSUPPORTED, "%s: precision %d", fn, opts->precision);
+  return MDERI_OK;
+}
+
+}  // namespace
+
+extern "C" mderi_status mderi_kbuild(mderi_ctx_t c, mderi_basis_t b, const double *D, double *K, int nao,
+                                     const mderi_opts *opts, void *stream) {
+  mderi_status st;
+  if ((st = check_density("mderi_kbuild", c, b, D, nao, opts))) return st;
+  if (!K) return fail(MDERI_EINVAL, "mderi_kbuild: NULL output");
+  const double tau = (opts && opts->schwarz_tau > 0.0) ? opts->schwarz_tau : 1e-12;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  PairSets ps;
+  if ((st = select_pairs(c, b, tau, s, ps))) return st;
+  void *d_kt;
+  if ((st = ws_get(c, WS_KTMP, sizeof(double) * (size_t)nao * nao, &d_kt))) return st;
+  HIP_TRY(launch_zero((size_t)nao * nao, (double *)d_kt, s));
+  Digest dg;
+  dg.kx = (double *)d_kt;
+  dg.dm = D;
+  dg.nao = nao;
+  dg.tau = tau;
+  const int ncls = (int)ps.cls.size();
+  // unordered class blocks; inside a diagonal block the kernel keeps ij >= kl
+  for (int c1 = 0; c1 < ncls; ++c1) {
+    if (ps.cls[c1].empty()) continue;
+    for (int c2 = c1; c2 < ncls; ++c2) {
+      if (ps.cls[c2].empty()) continue;
+      if ((double)ps.cls[c1].size() * ps.cls[c2].size() > 2.0e9)
+        return fail(MDERI_EUNSUPPORTED, "mderi_kbuild: class block of %zu x %zu pairs is too large",
+                    ps.cls[c1].size(), ps.cls[c2].size());
+      digest_block(ps, c1, c2, dg);
+      if ((st = run_class_batch(c, ps.sides[c1], ps.sides[c2], 0, nullptr, nullptr, nullptr, s, &dg))) return st;
+    }
+  }
+  HIP_TRY(launch_symmetrize(nao, (const double *)d_kt, K, s));
+  return MDERI_OK;
+}
+
+extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, const double *D, int nao, double *grad,
+                                          int natom, const mderi_opts *opts, void *stream) {
+  mderi_status st;
+  if ((st = check_density("mderi_kbuild_grad", c, b, D, nao, opts))) return st;
+  if (!grad) return fail(MDERI_EINVAL, "mderi_kbuild_grad: NULL output");
+  for (int i = 0; i < b->nshell; ++i)
+    if (b->atom[i] < 0 || b->atom[i] >= natom)
+      return fail(MDERI_EINVAL, "mderi_kbuild_grad: shell %d sits on atom %d, outside [0,%d)", i, b->atom[i], natom);
+  const double tau = (opts && opts->schwarz_tau > 0.0) ? opts->schwarz_tau : 1e-12;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  PairSets ps;
+  if ((st = select_pairs(c, b, tau, s, ps))) return st;
+  HIP_TRY(launch_zero((size_t)natom * 3, grad, s));
+  Digest dg;
+  dg.kx = nullptr;
+  dg.dm = D;
+  dg.nao = nao;
+  dg.tau = tau;
+  dg.grad = grad;
+  dg.atom = b->dev.atom;
+  const int ncls = (int)ps.cls.size();
+  // every ordered (bra class, ket class) block: each visit supplies the
+  // bra-centre derivatives, its swapped visit the ket-centre ones
+  for (int c1 = 0; c1 < ncls; ++c1) {
+    if (ps.cls[c1].empty()) continue;
+    for (int c2 = 0; c2 < ncls; ++c2) {
+      if (ps.cls[c2].empty()) continue;
+      if ((double)ps.cls[c1].size() * ps.cls[c2].size() > 2.0e9)
+        return fail(MDERI_EUNSUPPORTED, "mderi_kbuild_grad: class block of %zu x %zu pairs is too large",
+                    ps.cls[c1].size(), ps.cls[c2].size());
+      digest_block(ps, c1, c2, dg);
+      if ((st = run_class_batch(c, ps.sides[c1], ps.sides[c2], 0, nullptr, nullptr, nullptr, s, &dg))) return st;
+    }
   }
   return MDERI_OK;
 }

@@ -61,6 +61,7 @@ struct PrimPair {
 struct DevBasis {
   int nshell = 0, nprim = 0;
   int *l = nullptr, *K = nullptr, *poff = nullptr, *atom = nullptr;
+  int *ao_off = nullptr;      // first AO of every shell
   double *centers = nullptr;  // [nshell][3]
   double *exps = nullptr;     // [nprim]
   double *coefs = nullptr;    // [nprim], normalised contraction coefficients
@@ -75,6 +76,9 @@ struct PairArgs {
   int la, lb;
   int Nh, N, Nh_pad, N_pad;
   int ket_sign;  // fold (-1)^{|q|} of Eq. (pq) into a ket transform matrix
+  int one_centre;  // single shells (lb ignored): Eqs. (E1rr)-(E1-aa), zeta_p = zeta_a, P = A
+  int deriv;       // write the six centre-derivative matrices d/dA_x, d/dB_x (see pairs.hip)
+                   // as H[6][Nh_pad][N_pad]; rows then span |p| <= la+lb+1
   const uint32_t *order;  // row order (Nh_pad packed (t,u,v); kPadRow set = zero row), or
                           // nullptr for the global Hermite order with Nh real rows
   Tables tab;
@@ -91,12 +95,29 @@ struct Eri4Args {
   int nps;       // bra Hermite rows split over nps waves (Nhb_pad = 16 npt nps)
   int nct;       // ket column tiles (Nk_pad = 16 nct)
   int dbuf;      // double-buffered [r] cube
-  int levn;      // stride of one R-recursion level buffer (doubles)
   int S1, S2;    // [r] cube strides: [r] sits at t*S1 + u*S2 + v
   int cube_sz;   // doubles per cube
   int maxpp;     // largest (bra + ket) primitive-pair count of one quartet
   const uint32_t *border;  // bra Hermite row order (Nhb_pad entries, see PairArgs::order)
+  const uint32_t *korder;  // ket Hermite row order (Nhk_pad entries), or nullptr for the global order
   int diag;      // Schwarz mode: quartets (ij|ij) only, V receives the diagonal [ij][ab]
+  // exchange digest mode (kx != nullptr): instead of storing V, quartets with
+  // Q_ij Q_kl >= tau (and ij >= kl when bra and ket are the same list) add
+  // their four permutational images to K (see kdigest in eri4.hip)
+  double *kx;                     // K' [nao][nao], FP64 atomics
+  const double *dm;               // D [nao][nao]
+  int nao;
+  int same_list;                  // bra list == ket list: keep ij >= kl only
+  double tau;
+  const double *bra_q, *ket_q;    // Schwarz factors per pair
+  const int *bra_sh, *ket_sh;     // shell indices [n][2] (one-centre lists repeat the shell)
+  const int *ao_off;              // first AO of every shell
+  int nsa, nsb, nsc, nsd;         // N(l) of the four shells
+  // gradient mode (grad != nullptr): bra_H holds the six derivative matrices
+  // per bra primitive pair, the bra rows span |p| <= l_a+l_b+1, and the
+  // workgroup adds sum W d(ab|cd)/dA, dB to grad[atom][xyz] (see kgrad)
+  double *grad;
+  const int *atom;                // atom of every shell
   const int *bra_off, *ket_off;  // [n+1] primitive-pair offsets per shell pair
   const double *bra_G, *ket_G;
   const double *bra_H, *ket_H;
@@ -109,13 +130,16 @@ hipError_t launch_pairs(const PairArgs &a, hipStream_t s);
 hipError_t launch_eri4(const Eri4Args &a, hipStream_t s);
 // Q[idx[n]] = sqrt(max_ab |D[n][ab]|) for n < npair (Schwarz factors).
 hipError_t launch_schwarz_reduce(int npair, int Nab, const double *D, const int *idx, double *Q, hipStream_t s);
+// K = K' + K'^T (in place would race, so out != in), n x n.
+hipError_t launch_symmetrize(int n, const double *in, double *out, hipStream_t s);
+// x[0..n) = 0 with a plain kernel (no memset node, capture-safe).
+hipError_t launch_zero(size_t n, double *x, hipStream_t s);
 // Chooses the consumer register tile npt, the row split nps and the
 // cube buffering of the 4-centre kernel; false if the class does not fit.
-bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int levn, int maxpp, int *npt, int *nps,
+// grad admits 7-tile consumer waves (built only for gradient mode).
+bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int maxpp, bool grad, int *npt, int *nps,
                int *dbuf);
 // LDS bytes needed by one 4-centre workgroup.
 size_t eri4_lds_bytes(const Eri4Args &a);
-// Stride of a level buffer of the R recursion.
-int rr_level_stride(int L);
 
 }  // namespace mderi

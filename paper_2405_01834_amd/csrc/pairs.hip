@@ -1,5 +1,6 @@
 // pairs.hip -- primitive-pair data G and Hermite->solid transform matrices H
-// for one class batch of shell pairs.
+// for one class batch of shell pairs (or of single shells, for the auxiliary
+// side of 3-centre integrals).
 //
 // For each primitive pair of shells (a, b) with exponents za, zb:
 //   zeta_p = za + zb, P = (za A + zb B) / zeta_p                  (Sec. 2)
@@ -26,12 +27,12 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
   __shared__ double sc[2];
 
   const PrimPair d = a.pp[pp];
-  const double za = a.basis.exps[d.pa], zb = a.basis.exps[d.pb];
+  const double za = a.basis.exps[d.pa], zb = a.one_centre ? 0.0 : a.basis.exps[d.pb];
   const double *A = a.basis.centers + 3 * d.sa;
-  const double *B = a.basis.centers + 3 * d.sb;
+  const double *B = a.one_centre ? A : a.basis.centers + 3 * d.sb;
   const double p = za + zb;
   const double mu = za * zb / p;
-  const int la = a.la, lb = a.lb;
+  const int la = a.la, lb = a.one_centre ? 0 : a.lb;
 
   for (int e = tid; e < 3 * kEmaxA * kEmaxA * kEmaxT; e += kPairThreads) (&E[0][0][0][0])[e] = 0.0;
   __syncthreads();
@@ -41,17 +42,18 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
     const double XPA = Px - A[x], XPB = Px - B[x], XAB = A[x] - B[x];
     const double o2p = 0.5 / p;
     double(*Ex)[kEmaxA][kEmaxT] = E[x];
-    Ex[0][0][0] = exp(-mu * XAB * XAB);  // Eq. (E2-000)
-    for (int i = 0; i < la; ++i)         // Eq. (E2rr1), b = 0
+    // Eq. (E2-000); a single Gaussian has E^0_0 = 1 and, with zeta_b = 0 and
+    // P = A, Eq. (E2rr1) reduces to Eq. (E1rr)
+    Ex[0][0][0] = exp(-mu * XAB * XAB);
+    const int lae = la + a.deriv, lbe = lb + a.deriv;  // one more on each centre for derivatives
+    for (int i = 0; i < lae; ++i)  // Eq. (E2rr1), b = 0
       for (int t = 0; t <= i + 1; ++t)
         Ex[i + 1][0][t] = (t > 0 ? o2p * Ex[i][0][t - 1] : 0.0) + XPA * Ex[i][0][t] + (t + 1) * Ex[i][0][t + 1];
-    for (int i = 0; i <= la; ++i)  // Eq. (E2rr2)
-      for (int j = 0; j < lb; ++j)
+    for (int i = 0; i <= lae; ++i)  // Eq. (E2rr2)
+      for (int j = 0; j < lbe; ++j)
         for (int t = 0; t <= i + j + 1; ++t)
           Ex[i][j + 1][t] = (t > 0 ? o2p * Ex[i][j][t - 1] : 0.0) + XPB * Ex[i][j][t] + (t + 1) * Ex[i][j][t + 1];
-    if (x == 0) {
-      sc[0] = a.basis.coefs[d.pa] * a.basis.coefs[d.pb];
-    }
+    if (x == 0) sc[0] = a.basis.coefs[d.pa] * (a.one_centre ? 1.0 : a.basis.coefs[d.pb]);
   }
   if (tid == 0) {
     double *G = a.G + 4 * (size_t)pp;
@@ -63,6 +65,55 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
   __syncthreads();
   const double cab = sc[0];
   const int Nbb = nsph(lb);
+  if (a.deriv) {
+    // d/dA_x (x_A^{a} e^{-za r_A^2}) = 2 za x_A^{a+1x} e^{..} - a_x x_A^{a-1x} e^{..},
+    // the same for B: H^(X,x)[p][ab] = c_a c_b sum C C [2 z E^{(a+1x) b}_p - a_x E^{(a-1x) b}_p]
+    double *H = a.H + (size_t)pp * 6 * a.Nh_pad * a.N_pad;
+    const int total = 6 * a.Nh_pad * a.N_pad;
+    for (int e = tid; e < total; e += kPairThreads) {
+      const int mat = e / (a.Nh_pad * a.N_pad);
+      const int rem = e - mat * (a.Nh_pad * a.N_pad);
+      const int ph = rem / a.N_pad;
+      const int ab = rem - ph * a.N_pad;
+      const int cen = mat / 3, dir = mat - 3 * cen;  // cen 0 = A, 1 = B
+      double h = 0.0;
+      const uint32_t hp = a.order[ph];
+      if (!(hp & kPadRow) && ab < a.N) {
+        const int tq[3] = {(int)(hp & 0xff), (int)((hp >> 8) & 0xff), (int)((hp >> 16) & 0xff)};
+        const int ma = ab / Nbb - la, mb = ab % Nbb - lb;
+        const int s0 = a.tab.solid_start[solid_slot(la, ma)], s1 = a.tab.solid_start[solid_slot(la, ma) + 1];
+        const int r0 = a.tab.solid_start[solid_slot(lb, mb)], r1 = a.tab.solid_start[solid_slot(lb, mb) + 1];
+        const double z2 = 2.0 * (cen == 0 ? za : zb);
+        for (int s_ = s0; s_ < s1; ++s_) {
+          const uint32_t ca = a.tab.solid_cart[s_];
+          const int av[3] = {(int)(ca & 0xff), (int)((ca >> 8) & 0xff), (int)((ca >> 16) & 0xff)};
+          double inner = 0.0;
+          for (int r = r0; r < r1; ++r) {
+            const uint32_t cb = a.tab.solid_cart[r];
+            int bv[3] = {(int)(cb & 0xff), (int)((cb >> 8) & 0xff), (int)((cb >> 16) & 0xff)};
+            int up[3] = {av[0], av[1], av[2]}, vp[3] = {bv[0], bv[1], bv[2]};
+            // raised / lowered component on the differentiated centre
+            int *sh = cen == 0 ? up : vp;
+            const int n0 = sh[dir];
+            double term = 0.0;
+            sh[dir] = n0 + 1;
+            if (tq[0] <= up[0] + vp[0] && tq[1] <= up[1] + vp[1] && tq[2] <= up[2] + vp[2])
+              term += z2 * E[0][up[0]][vp[0]][tq[0]] * E[1][up[1]][vp[1]][tq[1]] * E[2][up[2]][vp[2]][tq[2]];
+            if (n0 > 0) {
+              sh[dir] = n0 - 1;
+              if (tq[0] <= up[0] + vp[0] && tq[1] <= up[1] + vp[1] && tq[2] <= up[2] + vp[2])
+                term -= n0 * E[0][up[0]][vp[0]][tq[0]] * E[1][up[1]][vp[1]][tq[1]] * E[2][up[2]][vp[2]][tq[2]];
+            }
+            inner += a.tab.solid_coef[r] * term;
+          }
+          h += a.tab.solid_coef[s_] * inner;
+        }
+        h *= cab;
+      }
+      H[e] = h;
+    }
+    return;
+  }
   double *H = a.H + (size_t)pp * a.Nh_pad * a.N_pad;
   const int total = a.Nh_pad * a.N_pad;
   for (int e = tid; e < total; e += kPairThreads) {

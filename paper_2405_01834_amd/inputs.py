@@ -10,6 +10,13 @@ Sec. 6, none of which ship with the paper):
   * class_pairs  -- candidate shell pairs of one class for the l-class batches:
                     centres U[0,20)^3, exponents log-uniform in [0.05, 500],
                     coefficients U[0.1, 1], K primitives per shell.
+  * cluster      -- atoms at least 2 bohr apart, drawn uniformly in a box
+                    whose side scales as 30 bohr x (natom / 150)^(1/3) (the
+                    density of a 150-atom cluster in a 30-bohr box); per atom
+                    the shells s4 p3 d2 f1 g1, K=1, exponents of the n shells
+                    of one l geometric from 0.08 to 2000 (a single shell takes
+                    the geometric mean); symmetric PSD density of rank 100
+                    (or nao if smaller), D = C C^T with C ~ N(0, 1/nao).
 Draw order per shell: centre (3 uniforms), K exponents, K coefficients.
 """
 from __future__ import annotations
@@ -94,3 +101,32 @@ def near_pairs(seed: int, la: int, lb: int, K: int, npairs: int, box: float = 20
     sh = Shells(np.array(ls, np.int32), np.array(Ks, np.int32), np.concatenate(ex), np.concatenate(co),
                 np.array(cen))
     return sh, np.arange(2 * npairs, dtype=np.int32).reshape(-1, 2)
+
+
+CLUSTER_SHELLS = ((0, 4), (1, 3), (2, 2), (3, 1), (4, 1))  # (l, shells per atom)
+
+
+def cluster(seed: int, natom: int, min_dist: float = 2.0, rank: int = 100):
+    """Synthetic molecular cluster.  Returns (shells, atom_of_shell, positions, D)."""
+    rng = np.random.default_rng(seed)
+    box = 30.0 * (natom / 150.0) ** (1.0 / 3.0)
+    pos = []
+    while len(pos) < natom:
+        x = rng.uniform(0.0, box, 3)
+        if all(np.linalg.norm(x - y) >= min_dist for y in pos):
+            pos.append(x)
+    pos = np.array(pos)
+    ls, ex, atom = [], [], []
+    for a in range(natom):
+        for l, n in CLUSTER_SHELLS:
+            e = [np.sqrt(0.08 * 2000.0)] if n == 1 else np.geomspace(0.08, 2000.0, n)
+            for z in e:
+                ls.append(l)
+                ex.append(z)
+                atom.append(a)
+    ls = np.array(ls, np.int32)
+    atom = np.array(atom, np.int32)
+    sh = Shells(ls, np.ones(len(ls), np.int32), np.array(ex), np.ones(len(ls)), pos[atom])
+    nao = int(np.sum(2 * ls + 1))
+    C = rng.normal(size=(nao, min(rank, nao))) / np.sqrt(nao)
+    return sh, atom, pos, C @ C.T

@@ -59,6 +59,17 @@ def load_library():
     L.mderi_eri4.argtypes = [_vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
                              ctypes.POINTER(Opts), _vp]
     L.mderi_eri4.restype = ctypes.c_int
+    L.mderi_eri3.argtypes = [_vp, _vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
+                             ctypes.POINTER(Opts), _vp]
+    L.mderi_eri3.restype = ctypes.c_int
+    L.mderi_kbuild.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _vp]
+    L.mderi_kbuild.restype = ctypes.c_int
+    L.mderi_kernel_timing.argtypes = [_vp, ctypes.c_int]
+    L.mderi_kernel_timing.restype = ctypes.c_int
+    L.mderi_kernel_times.argtypes = [_vp, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.mderi_kernel_times.restype = ctypes.c_int
+    L.mderi_kbuild_grad.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.POINTER(Opts), _vp]
+    L.mderi_kbuild_grad.restype = ctypes.c_int
     L.mderi_schwarz.argtypes = [_vp, _vp, ctypes.c_int, _ip, _vp, _vp]
     L.mderi_schwarz.restype = ctypes.c_int
     _lib = L
@@ -129,6 +140,68 @@ class Context:
         return out[:n].view(len(ket), ncd, nab, len(bra)).permute(3, 2, 1, 0)
 
 
+    def eri3(self, basis: "Basis", aux: "Basis", pairs, auxidx, out=None, stream=None):
+        """Class batch (ab|P) -> torch float64 tensor V[ij, ab, mP, k] (shape
+        (npair, Nab, NP, naux), a Fortran-order view of the flat output)."""
+        import torch
+        pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        auxidx = np.ascontiguousarray(np.asarray(auxidx, dtype=np.int32).reshape(-1))
+        nab = basis.pair_dim(pairs)
+        ok_aux = len(auxidx) > 0 and auxidx.min() >= 0 and auxidx.max() < aux.nshell
+        if nab is None or not ok_aux:
+            _check(load_library().mderi_eri3(self._h, basis._h, aux._h, len(pairs), pairs.ctypes.data_as(_ip),
+                                             len(auxidx), auxidx.ctypes.data_as(_ip), None, 0, None,
+                                             _stream_handle(stream)))
+        npp = nsph(int(aux.l[auxidx[0]]))
+        n = len(pairs) * nab * npp * len(auxidx)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=f"cuda:{self.device}")
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        _check(load_library().mderi_eri3(self._h, basis._h, aux._h, len(pairs), pairs.ctypes.data_as(_ip),
+                                         len(auxidx), auxidx.ctypes.data_as(_ip), _vp(out.data_ptr()), out.numel(),
+                                         None, _stream_handle(stream)))
+        return out[:n].view(len(auxidx), npp, nab, len(pairs)).permute(3, 2, 1, 0)
+
+    def kbuild(self, basis: "Basis", D, tau=1e-12, out=None, stream=None):
+        """Exchange matrix K_ac = sum_bd (ab|cd) D_bd for a symmetric density D
+        (torch float64 [nao, nao] on the device) -> K (same shape)."""
+        import torch
+        nao = basis.nao()
+        assert D.dtype == torch.float64 and D.is_cuda and D.shape == (nao, nao)
+        D = D.contiguous()
+        if out is None:
+            out = torch.empty((nao, nao), dtype=torch.float64, device=D.device)
+        opts = Opts(0, float(tau))
+        _check(load_library().mderi_kbuild(self._h, basis._h, _vp(D.data_ptr()), _vp(out.data_ptr()), nao,
+                                           ctypes.byref(opts), _stream_handle(stream)))
+        return out
+
+    def kernel_timing(self, enable: bool):
+        """Brackets every fused-kernel launch with HIP events on its stream."""
+        _check(load_library().mderi_kernel_timing(self._h, int(bool(enable))))
+
+    def kernel_times(self):
+        """Durations (ms) of the fused-kernel launches recorded since the last read."""
+        n = ctypes.c_int(0)
+        _check(load_library().mderi_kernel_times(self._h, None, 0, ctypes.byref(n)))
+        buf = np.zeros(max(n.value, 1))
+        _check(load_library().mderi_kernel_times(self._h, buf.ctypes.data_as(_dp), len(buf), ctypes.byref(n)))
+        return buf[:n.value].copy()
+
+    def kbuild_grad(self, basis: "Basis", D, natom, tau=1e-12, out=None, stream=None):
+        """dE/dR for E = tr(D K[D]) with D held fixed -> torch float64 [natom, 3]
+        (atoms as mapped by the basis' atom list)."""
+        import torch
+        nao = basis.nao()
+        assert D.dtype == torch.float64 and D.is_cuda and D.shape == (nao, nao)
+        D = D.contiguous()
+        if out is None:
+            out = torch.empty((natom, 3), dtype=torch.float64, device=D.device)
+        opts = Opts(0, float(tau))
+        _check(load_library().mderi_kbuild_grad(self._h, basis._h, _vp(D.data_ptr()), nao, _vp(out.data_ptr()),
+                                                int(natom), ctypes.byref(opts), _stream_handle(stream)))
+        return out
+
     def schwarz(self, basis: "Basis", pairs, stream=None):
         """Schwarz factors Q_ij = sqrt(max |(ab|ab)|) -> torch float64 tensor [npair]."""
         import torch
@@ -180,3 +253,53 @@ class Basis:
             self.close()
         except Exception:
             pass
+
+
+def exchange_energy(ctx: Context, coords, D, shells, tau=1e-12):
+    """E = tr(D K[D]) as a differentiable function of atom coordinates
+    coords [natom, 3] (bohr) and the symmetric density D [nao, nao] (both
+    float64 on the device).  shells = (l, nprim, exps, coefs, atom) places
+    shell s at coords[atom[s]].  Backward: dE/dcoords from mderi_kbuild_grad,
+    dE/dD = 2 K."""
+    return _ExchangeEnergy.apply(coords, D, ctx, shells, float(tau))
+
+
+def _make_exchange_function():
+    import torch
+
+    class ExchangeEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, coords, D, ctx, shells, tau):
+            l, nprim, exps, coefs, atom = shells
+            atom = np.ascontiguousarray(atom, dtype=np.int32)
+            centers = coords.detach().cpu().numpy()[atom]
+            basis = Basis(ctx, l, nprim, exps, coefs, centers, atom=atom)
+            K = ctx.kbuild(basis, D.detach(), tau=tau)
+            fctx.ctx, fctx.basis, fctx.tau, fctx.natom = ctx, basis, tau, coords.shape[0]
+            fctx.save_for_backward(D.detach(), K)
+            return (D.detach() * K).sum()
+
+        @staticmethod
+        def backward(fctx, gE):
+            D, K = fctx.saved_tensors
+            gc = gD = None
+            if fctx.needs_input_grad[0]:
+                gc = gE * fctx.ctx.kbuild_grad(fctx.basis, D, fctx.natom, tau=fctx.tau)
+            if fctx.needs_input_grad[1]:
+                gD = 2.0 * gE * K
+            return gc, gD, None, None, None
+
+    return ExchangeEnergy
+
+
+class _Lazy:
+    def __init__(self):
+        self._f = None
+
+    def apply(self, *args):
+        if self._f is None:
+            self._f = _make_exchange_function()
+        return self._f.apply(*args)
+
+
+_ExchangeEnergy = _Lazy()
