@@ -36,6 +36,25 @@ NPAIR = 256
 TAU = 1e-12
 
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2) and
+# WRITE_SIZE (x1) counters (profiles/eri4_ggK3_hbm_counters.md), valid only for
+# the kernel sources they were taken with.
+TRAFFIC = {"kernel": "eri4_kernel [gg|gg] K=3", "bytes": 1.0024e11,
+           "sources": {"eri4.hip": "e2691d8407c87fd5", "device_common.h": "e6641ab7efa0b0ee",
+                       "internal.h": "3f0c6d0b96ade833"}}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    if kernel != TRAFFIC["kernel"]:
+        return None
+    for name, h in TRAFFIC["sources"].items():
+        with open(os.path.join(ROOT, "paper_2405_01834_amd", "csrc", name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != h:
+                return None
+    return TRAFFIC["bytes"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -228,7 +247,7 @@ def main():
         "per_class": per_class,
         "roofline": {"bound": "mfma", "kernel": f"eri4_kernel {dom}", "kernel_ms": dom_ms, "achieved": achieved,
                      "peak": model.FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / model.FP64_PEAK_TFLOPS,
-                     "traffic": None},
+                     "traffic": measured_traffic(f"eri4_kernel {dom}"), "traffic_unit": "B"},
         "wall_s": wall,
     }
     if args.cluster_atoms > 0:
