@@ -25,6 +25,7 @@ namespace mderi {
 namespace {
 
 constexpr int kMaxWaves = 16;
+constexpr int kBufferWord3 = 0x00020000;  // buffer resource word 3 for gfx9-family raw loads
 
 // Exchange digestion of one shellset (ab|cd) held in LDS as v[ab][cd]
 // (Sec. 6, K = sum (ab|cd) D): with K_ac = sum_bd (ab|cd) D_bd, the eight
@@ -180,6 +181,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
     const int blo = g * a.Nb_pad + c;
     const int nat = a.Nb_pad >> 4;
     d4 xacc[NPT];
+    double gpart[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int n = 0; n < nsteps; ++n) {
       if (!a.dbuf && n > 0) __syncthreads();
       __syncthreads();
@@ -214,7 +216,8 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int pt = 0; pt < NPT; ++pt) xacc[pt] = mfma16x16x4(aA[pt], bA, xacc[pt]);
+        for (int pt = 0; pt < NPT; ++pt)
+          xacc[pt] = GRAD ? mfma16x16x4(bA, aA[pt], xacc[pt]) : mfma16x16x4(aA[pt], bA, xacc[pt]);
         __builtin_amdgcn_sched_barrier(0);
         {
           const int ks2 = min(ks + 2, nks - 1);
@@ -225,46 +228,52 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int pt = 0; pt < NPT; ++pt) xacc[pt] = mfma16x16x4(aB[pt], bB, xacc[pt]);
+        for (int pt = 0; pt < NPT; ++pt)
+          xacc[pt] = GRAD ? mfma16x16x4(bB, aB[pt], xacc[pt]) : mfma16x16x4(aB[pt], bB, xacc[pt]);
         __builtin_amdgcn_sched_barrier(0);
       }
       if (GRAD && ik == nkp - 1) {
-        // derivative step: D^(X,x)[ab][cd] = sum_p H^(X,x)[p][ab] X[p][cd] for
-        // X = A, B and x = x, y, z, dotted with W on the fly
-        const size_t mstride = (size_t)a.Nhb_pad * a.Nb_pad;
+        // Gradient mode keeps X transposed (the ket step above swaps the MFMA
+        // operands): register r of lane c + 16 g holds X^T[cd][p] with
+        // cd = 16 ct + 4 r + g and p the c-th row of tile pt.  The weighted
+        // derivative sum_ab,cd W[ab][cd] sum_p H^(X,x)[p][ab] X[p][cd] is
+        // sum_p,ab H^(X,x)[p][ab] Y[p][ab] with Y = X W^T: one MFMA product
+        // (Y^T = W X^T over this wave's 16 cd) and six elementwise dots.
+        const int mstride = a.Nhb_pad * a.Nb_pad;  // doubles per derivative matrix
+        // buffer loads: one resource per bra primitive pair, the per-lane part
+        // of the offset in a VGPR and the (tile, matrix, row) part in an SGPR,
+        // so no per-combination addresses stay live across the ab loop
+        const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a.bra_H + (size_t)(bp0 + ib) * 6 * mstride), (short)0, 6 * mstride * 8, kBufferWord3);
+        const int cd0 = ct * 16 + g;
 #pragma unroll 1
-        for (int mat = 0; mat < 6; ++mat) {
-          const double *Hb = a.bra_H + ((size_t)(bp0 + ib) * 6 + mat) * mstride + (size_t)ph * NPT * 16 * a.Nb_pad;
-          double part = 0.0;
-#pragma unroll 1
-          for (int at = 0; at < nat; ++at) {
-            const double *Ht = Hb + at * 16 + blo;
-            d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = d4{0.0, 0.0, 0.0, 0.0};
-            double h[4];
+        for (int at = 0; at < nat; ++at) {
+          const int abw = at * 16 + c;  // W row read by this lane
+          double w[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) h[r] = Ht[(4 * r) * a.Nb_pad];
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int cd = cd0 + 4 * s4;
+            w[s4] = (abw < a.Nb && cd < a.Nk) ? vsh[abw * a.Nk + cd] : 0.0;
+          }
+          // this lane's element of the [mat][ab][p] derivative matrices:
+          // ab = 16 at + g (+ 4 r), p = ph NPT 16 (+ 16 pt) + c
+          const int vo = 8 * (ph * NPT * 16 + c + (at * 16 + g) * a.Nhb_pad);
 #pragma unroll
-            for (int pt = 0; pt < NPT; ++pt) {
-              double hn[4];
+          for (int pt = 0; pt < NPT; ++pt) {
+            d4 y = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-              for (int r = 0; r < 4; ++r) hn[r] = (pt + 1 < NPT) ? Ht[((pt + 1) * 16 + 4 * r) * a.Nb_pad] : 0.0;
-              acc0 = mfma16x16x4(h[0], xacc[pt][0], acc0);
-              acc1 = mfma16x16x4(h[1], xacc[pt][1], acc1);
-              acc0 = mfma16x16x4(h[2], xacc[pt][2], acc0);
-              acc1 = mfma16x16x4(h[3], xacc[pt][3], acc1);
+            for (int s4 = 0; s4 < 4; ++s4) y = mfma16x16x4(w[s4], xacc[pt][s4], y);
+            // y[r] = Y^T[ab = 16 at + 4 r + g][p = row c of tile pt]
 #pragma unroll
-              for (int r = 0; r < 4; ++r) h[r] = hn[r];
-            }
-            if (col < a.Nk) {
+            for (int mat = 0; mat < 6; ++mat)
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int ab = at * 16 + 4 * r + g;
-                if (ab < a.Nb) part += (acc0[r] + acc1[r]) * vsh[ab * a.Nk + col];
+                const int so = 8 * (mat * mstride + pt * 16 + 4 * r * a.Nhb_pad);
+                const double h =
+                    __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(hrs, vo, so, 0));
+                gpart[mat] += y[r] * h;
               }
-            }
           }
-          for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-          if (lane == 0) atomicAdd(&gsum[mat], part);
         }
       } else if (ik == nkp - 1) {
         // bra transform: V[ab][cd] += sum_p H_bra[p][ab] X[p][cd], one ab tile
@@ -297,6 +306,14 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
             }
           }
         }
+      }
+    }
+    if (GRAD) {
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        double x = gpart[m];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (lane == 0) atomicAdd(&gsum[m], x);
       }
     }
   }
@@ -456,6 +473,7 @@ hipError_t launch_g(const Eri4Args &a, hipStream_t s) {
   if (a.L <= 8) return launch_lm<8, GRAD>(a, s);
   if (a.L <= 10) return launch_lm<10, GRAD>(a, s);
   if (a.L <= 16) return launch_lm<16, GRAD>(a, s);
+  if (a.L <= 18) return launch_lm<18, GRAD>(a, s);
   if (a.L <= 26) return launch_lm<26, GRAD>(a, s);
   return hipErrorInvalidValue;
 }

@@ -78,7 +78,7 @@ struct PairArgs {
   int ket_sign;  // fold (-1)^{|q|} of Eq. (pq) into a ket transform matrix
   int one_centre;  // single shells (lb ignored): Eqs. (E1rr)-(E1-aa), zeta_p = zeta_a, P = A
   int deriv;       // write the six centre-derivative matrices d/dA_x, d/dB_x (see pairs.hip)
-                   // as H[6][Nh_pad][N_pad]; rows then span |p| <= la+lb+1
+                   // transposed, H[6][N_pad][Nh_pad]; rows then span |p| <= la+lb+1
   const uint32_t *order;  // row order (Nh_pad packed (t,u,v); kPadRow set = zero row), or
                           // nullptr for the global Hermite order with Nh real rows
   Tables tab;

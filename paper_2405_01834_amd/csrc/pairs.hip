@@ -68,13 +68,15 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
   if (a.deriv) {
     // d/dA_x (x_A^{a} e^{-za r_A^2}) = 2 za x_A^{a+1x} e^{..} - a_x x_A^{a-1x} e^{..},
     // the same for B: H^(X,x)[p][ab] = c_a c_b sum C C [2 z E^{(a+1x) b}_p - a_x E^{(a-1x) b}_p]
+    // stored transposed, [mat][ab][p] with p fastest (the gradient stage of
+    // the fused kernel reads 16 consecutive p per lane group)
     double *H = a.H + (size_t)pp * 6 * a.Nh_pad * a.N_pad;
     const int total = 6 * a.Nh_pad * a.N_pad;
     for (int e = tid; e < total; e += kPairThreads) {
       const int mat = e / (a.Nh_pad * a.N_pad);
       const int rem = e - mat * (a.Nh_pad * a.N_pad);
-      const int ph = rem / a.N_pad;
-      const int ab = rem - ph * a.N_pad;
+      const int ab = rem / a.Nh_pad;
+      const int ph = rem - ab * a.Nh_pad;
       const int cen = mat / 3, dir = mat - 3 * cen;  // cen 0 = A, 1 = B
       double h = 0.0;
       const uint32_t hp = a.order[ph];
