@@ -57,8 +57,12 @@ typedef struct mderi_basis *mderi_basis_t;
 typedef struct {
   int precision;      /* 0 = FP64 (only value supported by the FP64 entry points) */
   double schwarz_tau; /* screening threshold for the K build (default 1e-12) */
-  int reserved[4];
+  int flags;          /* MDERI_FLAG_* (used by mderi_eri3_batch) */
+  int reserved[3];
 } mderi_opts;
+
+#define MDERI_FLAG_GRAPH 1    /* capture the call's launches in a hipGraph, replay it on identical calls */
+#define MDERI_FLAG_AUTOTUNE 2 /* choose each class block's kernel tiles by timing the candidates */
 
 /* Creates a context on HIP device `device`: uploads the Boys-function
  * interpolation table and the constant Hermite / solid-harmonic tables.
@@ -120,6 +124,29 @@ mderi_status mderi_eri4(mderi_ctx_t ctx, mderi_basis_t basis, int nbra, const in
 mderi_status mderi_eri3(mderi_ctx_t ctx, mderi_basis_t basis, mderi_basis_t aux, int npair, const int32_t *pairs_host,
                         int naux, const int32_t *aux_host, double *V_dev, size_t V_elems, const mderi_opts *opts,
                         void *stream);
+
+/*
+ * 3-centre integrals (ab|P) over pairs and auxiliary shells of ANY classes in
+ * one call (the class-batched form of mderi_eri3 generalised to a task list).
+ * pairs_host[npair][2] index `basis`, aux_host[naux] index `aux`.  Output is
+ * the matrix B with rows = the AO pairs of the pair list (pair i contributes
+ * N(l_a)N(l_b) rows, ab = m_a N(l_b) + m_b, in list order) and columns = the
+ * AOs of the aux list (aux k contributes N(l_k) columns), column-major:
+ *     V_dev[(rowoff_i + ab) + nrow * (coloff_k + m)],
+ * nrow = sum_i N(l_a)N(l_b); V_elems >= nrow * ncol.
+ * The call groups the triplets by class block (pair class x aux l), sorts
+ * them by the cost of Table md-scheme and runs one persistent launch per
+ * kernel shape; the plan (pair data, block descriptors, task lists) stays on
+ * the device, keyed by (bases, lists, V_dev, flags), and an identical later
+ * call only relaunches it.  opts->flags: MDERI_FLAG_GRAPH captures the
+ * launches in a hipGraph on the first call and replays it afterwards;
+ * MDERI_FLAG_AUTOTUNE times every candidate tile shape of a new class
+ * signature on the first call (results are kept in the context).  The first
+ * call of a plan synchronises the stream.
+ */
+mderi_status mderi_eri3_batch(mderi_ctx_t ctx, mderi_basis_t basis, mderi_basis_t aux, int npair,
+                              const int32_t *pairs_host, int naux, const int32_t *aux_host, double *V_dev,
+                              size_t V_elems, const mderi_opts *opts, void *stream);
 
 /*
  * Schwarz factors Q_ij = sqrt(max_ab |(ab|ab)|) of shell pairs, from the

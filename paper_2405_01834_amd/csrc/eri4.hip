@@ -78,9 +78,11 @@ __device__ __forceinline__ void kdigest(const Eri4Args &a, const double *v, int 
   }
 }
 
+// One shell quartet (ij, kl) by the whole workgroup.  Waves beyond the
+// block's nct * nps consumers and its producer (a task-list launch sizes the
+// workgroup for its largest block) only take part in the barriers.
 template <int NPT, int LM, bool GRAD>
-__global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
-  extern __shared__ double smem[];
+__device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, double *smem) {
   const int L = a.L;
   const int S1 = a.S1, S2 = a.S2;
   const int cube_sz = a.cube_sz;
@@ -92,16 +94,6 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
   double *vsh = gsum + 8;                            // V[ab][cd] (or the weights W) of this quartet
   uint32_t *uvsh = (uint32_t *)(vsh + a.Nb * a.Nk);  // (u, v) pairs, u+v <= L, by u+v
   int *offq = (int *)(uvsh + (L + 1) * (L + 2) / 2);
-
-  const long G = a.diag ? (long)a.nbra : (long)a.nbra * a.nket;
-  const long v = xcd_remap(blockIdx.x, G);
-  const int ij = (int)(v % a.nbra), kl = a.diag ? ij : (int)(v / a.nbra);
-  if (a.kx) {
-    // screened or symmetry-redundant quartet: the whole workgroup leaves
-    // before any barrier
-    if (a.bra_q[ij] * a.ket_q[kl] < a.tau || (a.same_list && ij < kl)) return;
-  }
-  if (GRAD && a.bra_q[ij] * a.ket_q[kl] < a.tau) return;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -164,6 +156,12 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
       }
       __syncthreads();  // [r] of step n published
       if (a.dbuf && n + 1 < nsteps) build(n + 1, ((n + 1) & 1) ? cube1 : cube0);
+    }
+  } else if (wave > ncons) {
+    // ---------------- surplus waves: barriers only ----------------
+    for (int n = 0; n < nsteps; ++n) {
+      if (!a.dbuf && n > 0) __syncthreads();
+      __syncthreads();
     }
   } else {
     // ---------------- consumers ----------------
@@ -239,7 +237,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
         // derivative sum_ab,cd W[ab][cd] sum_p H^(X,x)[p][ab] X[p][cd] is
         // sum_p,ab H^(X,x)[p][ab] Y[p][ab] with Y = X W^T: one MFMA product
         // (Y^T = W X^T over this wave's 16 cd) and six elementwise dots.
-        const int mstride = a.Nhb_pad * a.Nb_pad;  // doubles per derivative matrix
+        const int mstride = a.Hb_rows * a.Nb_pad;  // doubles per derivative matrix
         // buffer loads: one resource per bra primitive pair, the per-lane part
         // of the offset in a VGPR and the (tile, matrix, row) part in an SGPR,
         // so no per-combination addresses stay live across the ab loop
@@ -257,7 +255,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
           }
           // this lane's element of the [mat][ab][p] derivative matrices:
           // ab = 16 at + g (+ 4 r), p = ph NPT 16 (+ 16 pt) + c
-          const int vo = 8 * (ph * NPT * 16 + c + (at * 16 + g) * a.Nhb_pad);
+          const int vo = 8 * (ph * NPT * 16 + c + (at * 16 + g) * a.Hb_rows);
 #pragma unroll
           for (int pt = 0; pt < NPT; ++pt) {
             d4 y = d4{0.0, 0.0, 0.0, 0.0};
@@ -268,7 +266,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
             for (int mat = 0; mat < 6; ++mat)
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int so = 8 * (mat * mstride + pt * 16 + 4 * r * a.Nhb_pad);
+                const int so = 8 * (mat * mstride + pt * 16 + 4 * r * a.Hb_rows);
                 const double h =
                     __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(hrs, vo, so, 0));
                 gpart[mat] += y[r] * h;
@@ -278,7 +276,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
       } else if (ik == nkp - 1) {
         // bra transform: V[ab][cd] += sum_p H_bra[p][ab] X[p][cd], one ab tile
         // at a time (two accumulators), summed into the LDS copy of V
-        const double *Hb = a.bra_H + (size_t)(bp0 + ib) * a.Nhb_pad * a.Nb_pad + (size_t)ph * NPT * 16 * a.Nb_pad;
+        const double *Hb = a.bra_H + (size_t)(bp0 + ib) * a.Hb_rows * a.Nb_pad + (size_t)ph * NPT * 16 * a.Nb_pad;
 #pragma unroll 1
         for (int at = 0; at < nat; ++at) {
           const double *Ht = Hb + at * 16 + blo;
@@ -343,10 +341,63 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
     for (int ab = tid; ab < a.Nb; ab += blockDim.x) a.V[(size_t)ij * a.Nb + ab] = vsh[ab * a.Nk + ab];
     return;
   }
+  if (a.orow) {
+    // matrix output: (ab, cd) of quartet (ij, kl) at V[orow[ij] + ab + ld (ocol[kl] + cd)]
+    const long r0 = a.orow[ij], c0 = a.ocol[kl];
+    for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) {
+      const int cd = e / a.Nb, ab = e - cd * a.Nb;
+      a.V[r0 + ab + a.ld * (c0 + cd)] = vsh[ab * a.Nk + cd];
+    }
+    return;
+  }
   const size_t base = (size_t)ij + (size_t)a.nbra * (size_t)a.Nb * (size_t)a.Nk * kl;
   for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) {
     const int cd = e / a.Nb, ab = e - cd * a.Nb;
     a.V[base + (size_t)a.nbra * ((size_t)ab + (size_t)a.Nb * cd)] = vsh[ab * a.Nk + cd];
+  }
+}
+
+// One workgroup per quartet of one class batch.
+template <int NPT, int LM, bool GRAD>
+__global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
+  extern __shared__ double smem[];
+  const long G = a.diag ? (long)a.nbra : (long)a.nbra * a.nket;
+  const long v = xcd_remap(blockIdx.x, G);
+  const int ij = (int)(v % a.nbra), kl = a.diag ? ij : (int)(v / a.nbra);
+  if (a.kx) {
+    // screened or symmetry-redundant quartet: the whole workgroup leaves
+    // before any barrier
+    if (a.bra_q[ij] * a.ket_q[kl] < a.tau || (a.same_list && ij < kl)) return;
+  }
+  if (GRAD && a.bra_q[ij] * a.ket_q[kl] < a.tau) return;
+  eri4_quartet<NPT, LM, GRAD>(a, ij, kl, smem);
+}
+
+// Persistent task-list kernel: the workgroups stride over tasks (block id,
+// quartet index ij + nbra kl), sorted by the host by decreasing cost, of any
+// number of class blocks that share the register tile NPT and the producer
+// length LM; the workgroup holds the largest block's waves and LDS.
+template <int NPT, int LM>
+__global__ void __launch_bounds__(64 * kMaxWaves)
+    eri4_tasks_kernel(const Eri4Args *__restrict__ blocks, const int2 *__restrict__ tasks, int ntask) {
+  extern __shared__ double smem[];
+  for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
+    // wave-uniform by construction; readfirstlane lets the block's arguments
+    // be fetched with scalar loads
+    const int bi = __builtin_amdgcn_readfirstlane(tasks[t].x);
+    const int q = __builtin_amdgcn_readfirstlane(tasks[t].y);
+    // the descriptors are read-only for the kernel's lifetime: viewed through
+    // the constant address space they load with scalar loads and can be
+    // reloaded instead of being kept live
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef __attribute__((address_space(4))) const Eri4Args ConstArgs;
+    const Eri4Args a = ((ConstArgs *)(blocks))[bi];
+#else
+    const Eri4Args a = blocks[bi];  // host pass: the kernel is never run there
+#endif
+    const int ij = q % a.nbra, kl = q / a.nbra;
+    __syncthreads();  // the previous task is done with LDS
+    eri4_quartet<NPT, LM, false>(a, ij, kl, smem);
   }
 }
 
@@ -467,6 +518,32 @@ hipError_t launch_lm(const Eri4Args &a, hipStream_t s) {
   }
 }
 
+template <int NPT, int LM>
+hipError_t launch_tasks_t(const Eri4Args *b, const int2 *t, int n, int waves, size_t lds, int grid, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)eri4_tasks_kernel<NPT, LM>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((eri4_tasks_kernel<NPT, LM>), dim3((unsigned)grid), dim3(64 * waves), lds, s, b, t, n);
+  return hipGetLastError();
+}
+
+template <int LM>
+hipError_t launch_tasks_lm(const Eri4Args *b, const int2 *t, int n, int npt, int waves, size_t lds, int grid,
+                           hipStream_t s) {
+  switch (npt) {
+    case 1: return launch_tasks_t<1, LM>(b, t, n, waves, lds, grid, s);
+    case 2: return launch_tasks_t<2, LM>(b, t, n, waves, lds, grid, s);
+    case 3: return launch_tasks_t<3, LM>(b, t, n, waves, lds, grid, s);
+    case 4: return launch_tasks_t<4, LM>(b, t, n, waves, lds, grid, s);
+    case 6: return launch_tasks_t<6, LM>(b, t, n, waves, lds, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <bool GRAD>
 hipError_t launch_g(const Eri4Args &a, hipStream_t s) {
   // register length of the producer's m-vectors: smallest bound >= L
@@ -482,6 +559,22 @@ hipError_t launch_eri4(const Eri4Args &a, hipStream_t s) {
   if (a.nbra <= 0 || a.nket <= 0) return hipSuccess;
   if (a.nct * a.nps + 1 > kMaxWaves) return hipErrorInvalidValue;
   return a.grad ? launch_g<true>(a, s) : launch_g<false>(a, s);
+}
+
+int eri4_lm_bucket(int L) { return L <= 8 ? 8 : L <= 10 ? 10 : L <= 16 ? 16 : L <= 18 ? 18 : L <= 26 ? 26 : -1; }
+
+hipError_t launch_eri4_tasks(const Eri4Args *d_blocks, const int2 *d_tasks, int ntask, int npt, int Lmax, int waves,
+                             size_t lds, int grid, hipStream_t s) {
+  if (ntask <= 0) return hipSuccess;
+  if (waves < 2 || waves > kMaxWaves || grid <= 0) return hipErrorInvalidValue;
+  switch (eri4_lm_bucket(Lmax)) {
+    case 8: return launch_tasks_lm<8>(d_blocks, d_tasks, ntask, npt, waves, lds, grid, s);
+    case 10: return launch_tasks_lm<10>(d_blocks, d_tasks, ntask, npt, waves, lds, grid, s);
+    case 16: return launch_tasks_lm<16>(d_blocks, d_tasks, ntask, npt, waves, lds, grid, s);
+    case 18: return launch_tasks_lm<18>(d_blocks, d_tasks, ntask, npt, waves, lds, grid, s);
+    case 26: return launch_tasks_lm<26>(d_blocks, d_tasks, ntask, npt, waves, lds, grid, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace mderi

@@ -9,6 +9,9 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <map>
+#include <array>
+#include <numeric>
 
 #include "internal.h"
 
@@ -174,6 +177,9 @@ enum WsSlot {
   WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_ORDER, WS_KORDER, WS_QB, WS_QK, WS_SHB, WS_SHK, WS_KTMP, WS_QALL, WS_PAIRS, WS_COUNT
 };
 
+struct TaskPlan;
+void free_plan(TaskPlan *p);
+
 struct mderi_ctx {
   int device = 0;
   Tables tab;
@@ -188,10 +194,17 @@ struct mderi_ctx {
   // of events on its stream (pairs are recycled after they are read)
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+  // task-list plans of mderi_eri3_batch, most recent last, and the tile
+  // choices of the autotuner per class signature
+  std::vector<TaskPlan *> plans;
+  std::map<std::array<int, 6>, std::array<int, 3>> tune;
+  hipStream_t cap_stream = nullptr;  // stream used to capture graphs
+  uint64_t next_serial = 1;
 };
 
 struct mderi_basis {
   mderi_ctx *ctx = nullptr;
+  uint64_t serial = 0;  // unique per upload (keys cached task plans)
   int nshell = 0, nao = 0;
   std::vector<int> l, K, poff, atom, ao_off;
   DevBasis dev;
@@ -311,6 +324,8 @@ extern "C" void mderi_destroy(mderi_ctx_t c) {
   for (int i = 0; i < WS_COUNT; ++i) (void)hipFree(c->ws[i]);
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  for (TaskPlan *p : c->plans) free_plan(p);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto *v : {&c->ev_used, &c->ev_free})
     for (auto &e : *v) {
       (void)hipEventDestroy(e.first);
@@ -359,6 +374,7 @@ extern "C" mderi_status mderi_basis_upload(mderi_ctx_t c, int nshell, const int 
   if (!l || !nprim || !exps || !coefs || !centers) return fail(MDERI_EINVAL, "mderi_basis_upload: NULL array");
   mderi_basis *b = new mderi_basis;
   b->ctx = c;
+  b->serial = c->next_serial++;
   b->nshell = nshell;
   b->l.assign(l, l + nshell);
   b->K.assign(nprim, nprim + nshell);
@@ -709,6 +725,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   ea.Nb = Nb;
   ea.Nk = Nk;
   ea.Nhb_pad = Nhb_pad;
+  ea.Hb_rows = Nhb_pad;
   ea.Nhk_pad = Nhk_pad;
   ea.Nb_pad = Nb_pad;
   ea.Nk_pad = Nk_pad;
@@ -1005,5 +1022,492 @@ extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, const 
       if ((st = run_class_batch(c, ps.sides[c1], ps.sides[c2], 0, nullptr, nullptr, nullptr, s, &dg))) return st;
     }
   }
+  return MDERI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// task lists: mixed-class 3-centre batches in persistent launches
+// ---------------------------------------------------------------------------
+struct TaskGroup {
+  int npt, Lmax, waves, grid, ntask;
+  size_t lds;
+  const Eri4Args *d_blocks;
+  const int2 *d_tasks;
+};
+
+struct TaskPlan {
+  uint64_t key = 0;
+  int flags = 0;
+  void *dmem = nullptr;  // one device allocation holding every array of the plan
+  std::vector<PairArgs> pairs;  // pair-data launches (bra classes, then aux l)
+  std::vector<TaskGroup> groups;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+void free_plan(TaskPlan *p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->dmem) (void)hipFree(p->dmem);
+  delete p;
+}
+
+namespace {
+
+uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
+  const unsigned char *d = (const unsigned char *)data;
+  for (size_t i = 0; i < n; ++i) h = (h ^ d[i]) * 1099511628211ull;
+  return h;
+}
+
+// Host image of the plan's device arrays: every array is appended at a
+// 256-byte aligned offset; device pointers are base + offset once the single
+// allocation exists.
+struct Image {
+  std::vector<char> bytes;
+  size_t add(const void *src, size_t n) {
+    const size_t off = (bytes.size() + 255) & ~(size_t)255;
+    bytes.resize(off + ((n + 255) & ~(size_t)255), 0);
+    if (src && n) memcpy(bytes.data() + off, src, n);
+    return off;
+  }
+};
+
+// Candidate (npt, nps, dbuf) plans of a block: every row split with at most
+// 6 tiles per wave that fits the wave and LDS limits; the first is the
+// default (fewest waves).
+std::vector<std::array<int, 3>> block_candidates(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad,
+                                                 int maxpp) {
+  std::vector<std::array<int, 3>> out;
+  int npt = 0, nps = 0, dbuf = 0;
+  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, false, &npt, &nps, &dbuf)) return out;
+  out.push_back({npt, nps, dbuf});
+  const int need = (Nhb + 15) / 16, nct = (Nk + 15) / 16;
+  const int tiles[] = {1, 2, 3, 4, 6};
+  for (int parts = 1; parts <= 4; ++parts) {
+    const int per = (need + parts - 1) / parts;
+    int t = 0;
+    for (int x : tiles)
+      if (x >= per) {
+        t = x;
+        break;
+      }
+    if (!t || nct * parts + 1 > 16) continue;
+    for (int db = 1; db >= 0; --db) {
+      if (db && !dbuf) continue;  // double buffering does not fit
+      const std::array<int, 3> cand = {t, parts, db};
+      if (std::find(out.begin(), out.end(), cand) == out.end()) out.push_back(cand);
+    }
+  }
+  return out;
+}
+
+size_t block_lds(const Eri4Args &a) { return eri4_lds_bytes(a); }
+
+int group_grid(size_t lds, int waves, long ntask) {
+  const long per_cu_lds = lds ? (long)(160 * 1024 / lds) : 16;
+  const long per_cu_waves = 16 / waves;  // 128 VGPRs per lane: 4 waves per SIMD
+  long per_cu = std::max(1L, std::min(per_cu_lds, per_cu_waves));
+  long g = 256 * per_cu;
+  return (int)std::max(1L, std::min(g, ntask));
+}
+
+mderi_status launch_plan(mderi_ctx *c, TaskPlan *p, hipStream_t s) {
+  for (const PairArgs &pa : p->pairs) HIP_TRY(launch_pairs(pa, s));
+  for (const TaskGroup &g : p->groups)
+    HIP_TRY(launch_eri4_tasks(g.d_blocks, g.d_tasks, g.ntask, g.npt, g.Lmax, g.waves, g.lds, g.grid, s));
+  return MDERI_OK;
+}
+
+}  // namespace
+
+extern "C" mderi_status mderi_eri3_batch(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t aux, int npair,
+                                         const int32_t *pairs, int naux, const int32_t *auxidx, double *V,
+                                         size_t V_elems, const mderi_opts *opts, void *stream) {
+  if (!c || !b || !aux) return fail(MDERI_EINVAL, "mderi_eri3_batch: NULL context or basis");
+  if (b->ctx != c || aux->ctx != c) return fail(MDERI_EINVAL, "mderi_eri3_batch: basis belongs to another context");
+  if (opts && opts->precision != 0) return fail(MDERI_EUNSUPPORTED, "mderi_eri3_batch: precision %d", opts->precision);
+  if (npair <= 0 || naux <= 0 || !pairs || !auxidx)
+    return fail(MDERI_EINVAL, "mderi_eri3_batch: need non-empty pair and aux lists");
+  if (!V) return fail(MDERI_EINVAL, "mderi_eri3_batch: NULL output");
+  const int flags = opts ? opts->flags : 0;
+  if (flags & ~(MDERI_FLAG_GRAPH | MDERI_FLAG_AUTOTUNE))
+    return fail(MDERI_EINVAL, "mderi_eri3_batch: unknown flags 0x%x", flags);
+  for (int i = 0; i < npair; ++i)
+    if (pairs[2 * i] < 0 || pairs[2 * i] >= b->nshell || pairs[2 * i + 1] < 0 || pairs[2 * i + 1] >= b->nshell)
+      return fail(MDERI_EINVAL, "mderi_eri3_batch: pair %d = (%d,%d) out of range [0,%d)", i, pairs[2 * i],
+                  pairs[2 * i + 1], b->nshell);
+  for (int k = 0; k < naux; ++k)
+    if (auxidx[k] < 0 || auxidx[k] >= aux->nshell)
+      return fail(MDERI_EINVAL, "mderi_eri3_batch: aux %d = %d out of range [0,%d)", k, auxidx[k], aux->nshell);
+  // output geometry: rows = AO pairs in list order, columns = aux AOs in list order
+  std::vector<long> rowoff(npair), coloff(naux);
+  long nrow = 0, ncol = 0;
+  for (int i = 0; i < npair; ++i) {
+    rowoff[i] = nrow;
+    nrow += (long)nsph(b->l[pairs[2 * i]]) * nsph(b->l[pairs[2 * i + 1]]);
+  }
+  for (int k = 0; k < naux; ++k) {
+    coloff[k] = ncol;
+    ncol += nsph(aux->l[auxidx[k]]);
+  }
+  if (V_elems < (size_t)nrow * (size_t)ncol)
+    return fail(MDERI_ESIZE, "mderi_eri3_batch: output holds %zu doubles, needs %ld", V_elems, nrow * ncol);
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+
+  uint64_t key = 1469598103934665603ull;
+  key = fnv1a(key, &b->serial, sizeof(b->serial));
+  key = fnv1a(key, &aux->serial, sizeof(aux->serial));
+  key = fnv1a(key, &npair, sizeof(npair));
+  key = fnv1a(key, pairs, sizeof(int32_t) * 2 * (size_t)npair);
+  key = fnv1a(key, &naux, sizeof(naux));
+  key = fnv1a(key, auxidx, sizeof(int32_t) * (size_t)naux);
+  key = fnv1a(key, &V, sizeof(V));
+  key = fnv1a(key, &flags, sizeof(flags));
+  for (size_t i = 0; i < c->plans.size(); ++i) {
+    TaskPlan *p = c->plans[i];
+    if (p->key != key) continue;
+    c->plans.erase(c->plans.begin() + i);
+    c->plans.push_back(p);  // most recently used last
+    if (p->exec) {
+      HIP_TRY(hipGraphLaunch(p->exec, s));
+      return MDERI_OK;
+    }
+    return launch_plan(c, p, s);
+  }
+
+  // ---- build the plan ----
+  // classes: bra (la, lb) groups of pairs; aux l groups of shells
+  std::map<std::pair<int, int>, std::vector<int>> bcls;
+  std::map<int, std::vector<int>> acls;
+  for (int i = 0; i < npair; ++i) bcls[{b->l[pairs[2 * i]], b->l[pairs[2 * i + 1]]}].push_back(i);
+  for (int k = 0; k < naux; ++k) acls[aux->l[auxidx[k]]].push_back(k);
+  const int lPmax = acls.rbegin()->first;
+  mderi_status st;
+  Image img;
+  struct SideData {
+    int la, lb, Nh, N, Nh_pad, N_pad, S1, S2, npp, maxpp;
+    size_t o_pp, o_off, o_G, o_H, o_order, o_rows;
+    std::vector<int> off;
+  };
+  // aux (1-centre ket) sides, one per l
+  std::map<int, SideData> aside;
+  for (auto &kv : acls) {
+    const int l = kv.first;
+    std::vector<PrimPair> pp;
+    std::vector<int> off(1, 0);
+    std::vector<long> cols;
+    for (int k : kv.second) {
+      const int sh = auxidx[k];
+      for (int q = 0; q < aux->K[sh]; ++q) pp.push_back(PrimPair{sh, sh, aux->poff[sh] + q, aux->poff[sh] + q});
+      off.push_back((int)pp.size());
+      cols.push_back(coloff[k]);
+    }
+    std::vector<uint32_t> ko = top_degree_rows(l);
+    SideData d{};
+    d.la = l;
+    d.lb = 0;
+    d.Nh = (l + 1) * (l + 2) / 2;
+    d.N = nsph(l);
+    d.Nh_pad = (int)ko.size();
+    d.N_pad = round16(d.N);
+    d.npp = (int)pp.size();
+    d.maxpp = 0;
+    for (size_t i = 0; i + 1 < off.size(); ++i) d.maxpp = std::max(d.maxpp, off[i + 1] - off[i]);
+    d.o_pp = img.add(pp.data(), sizeof(PrimPair) * pp.size());
+    d.o_off = img.add(off.data(), sizeof(int) * off.size());
+    d.o_G = img.add(nullptr, sizeof(double) * 4 * pp.size());
+    d.o_H = img.add(nullptr, sizeof(double) * (size_t)d.Nh_pad * d.N_pad * pp.size());
+    d.o_order = img.add(ko.data(), sizeof(uint32_t) * ko.size());
+    d.o_rows = img.add(cols.data(), sizeof(long) * cols.size());
+    d.off = off;
+    aside[l] = d;
+  }
+  // bra sides, one per class; strides fit the largest L the class meets
+  std::map<std::pair<int, int>, SideData> bside;
+  struct BlockPlan {
+    std::pair<int, int> bc;
+    int l;
+    Eri4Args a;
+    std::vector<std::array<int, 3>> cands;
+    std::array<int, 6> sig;
+  };
+  std::vector<BlockPlan> blocks;
+  for (auto &kv : bcls) {
+    const int la = kv.first.first, lb = kv.first.second, Lb = la + lb;
+    std::vector<PrimPair> pp;
+    std::vector<int> off(1, 0);
+    std::vector<long> rows;
+    int maxb = 0;
+    for (int i : kv.second) {
+      const int s0 = pairs[2 * i], s1 = pairs[2 * i + 1];
+      for (int ka = 0; ka < b->K[s0]; ++ka)
+        for (int kb = 0; kb < b->K[s1]; ++kb) pp.push_back(PrimPair{s0, s1, b->poff[s0] + ka, b->poff[s1] + kb});
+      off.push_back((int)pp.size());
+      maxb = std::max(maxb, off.back() - off[off.size() - 2]);
+      rows.push_back(rowoff[i]);
+    }
+    SideData d{};
+    d.la = la;
+    d.lb = lb;
+    d.Nh = ntil(Lb);
+    d.N = nsph(la) * nsph(lb);
+    d.N_pad = round16(d.N);
+    choose_cube(Lb + lPmax, Lb, &d.S1, &d.S2);
+    d.npp = (int)pp.size();
+    d.maxpp = maxb;
+    // blocks of this class and their candidate tiles
+    int nh_pad = round16(d.Nh);
+    for (auto &akv : aside) {
+      const SideData &ad = akv.second;
+      const int L = Lb + ad.la;
+      BlockPlan bp;
+      bp.bc = kv.first;
+      bp.l = ad.la;
+      Eri4Args &a = bp.a;
+      a = Eri4Args{};
+      a.nbra = (int)kv.second.size();
+      a.nket = (int)acls[ad.la].size();
+      a.L = L;
+      a.Nhb = d.Nh;
+      a.Nhk = ad.Nh;
+      a.Nb = d.N;
+      a.Nk = ad.N;
+      a.Nb_pad = d.N_pad;
+      a.Nhk_pad = ad.Nh_pad;
+      a.Nk_pad = ad.N_pad;
+      a.nct = ad.N_pad / 16;
+      a.S1 = d.S1;
+      a.S2 = d.S2;
+      a.cube_sz = (L * d.S1 + 2) & ~1;
+      a.maxpp = maxb + ad.maxpp;
+      a.ld = nrow;
+      bp.cands = block_candidates(a.Nhb, a.Nb, a.Nk, L, a.cube_sz, a.Nhk_pad, a.maxpp);
+      if (bp.cands.empty())
+        return fail(MDERI_EUNSUPPORTED, "mderi_eri3_batch: class (%d%d|%d) is beyond the fused kernel's tiles", la, lb,
+                    ad.la);
+      int kb = 0, kk = 0;
+      for (int i : kv.second) kb = std::max(kb, b->K[pairs[2 * i]] * b->K[pairs[2 * i + 1]]);
+      for (int k : acls[ad.la]) kk = std::max(kk, aux->K[auxidx[k]]);
+      bp.sig = {la, lb, ad.la, -1, kb, kk};
+      auto it = c->tune.find(bp.sig);
+      if (it != c->tune.end() &&
+          std::find(bp.cands.begin(), bp.cands.end(), it->second) != bp.cands.end()) {
+        bp.cands = {it->second};
+      } else if (!(flags & MDERI_FLAG_AUTOTUNE)) {
+        bp.cands.resize(1);
+      }
+      for (auto &cd : bp.cands) nh_pad = std::max(nh_pad, 16 * cd[0] * cd[1]);
+      blocks.push_back(bp);
+    }
+    d.Nh_pad = nh_pad;
+    // bank-spread row order over the class's own tiles, then zero padding rows
+    std::vector<uint32_t> order = bra_row_order(Lb, d.S1, d.S2, round16(d.Nh));
+    while ((int)order.size() < nh_pad) order.push_back(order[0] | kPadRow);
+    d.o_pp = img.add(pp.data(), sizeof(PrimPair) * pp.size());
+    d.o_off = img.add(off.data(), sizeof(int) * off.size());
+    d.o_G = img.add(nullptr, sizeof(double) * 4 * pp.size());
+    d.o_H = img.add(nullptr, sizeof(double) * (size_t)nh_pad * d.N_pad * pp.size());
+    d.o_order = img.add(order.data(), sizeof(uint32_t) * order.size());
+    d.o_rows = img.add(rows.data(), sizeof(long) * rows.size());
+    d.off = off;
+    bside[kv.first] = d;
+  }
+  // space for block descriptors and task lists (filled after tuning)
+  const size_t o_blocks = img.add(nullptr, sizeof(Eri4Args) * blocks.size());
+  long ntask_all = 0;
+  for (auto &bp : blocks) ntask_all += (long)bp.a.nbra * bp.a.nket;
+  if (ntask_all > 0x7fffffffL) return fail(MDERI_EUNSUPPORTED, "mderi_eri3_batch: %ld triplets is too many", ntask_all);
+  const size_t o_tasks = img.add(nullptr, sizeof(int2) * (size_t)ntask_all);
+
+  TaskPlan *plan = new TaskPlan;
+  plan->key = key;
+  plan->flags = flags;
+  if (hipMalloc(&plan->dmem, img.bytes.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    delete plan;
+    return fail(MDERI_ENOMEM, "mderi_eri3_batch: plan of %zu bytes could not be allocated", img.bytes.size());
+  }
+  char *base = (char *)plan->dmem;
+  auto dev = [&](size_t off) { return (void *)(base + off); };
+  // fill descriptors (pointers are final now)
+  for (auto &bp : blocks) {
+    const SideData &bd = bside[bp.bc], &ad = aside[bp.l];
+    Eri4Args &a = bp.a;
+    a.Hb_rows = bd.Nh_pad;
+    a.bra_off = (const int *)dev(bd.o_off);
+    a.ket_off = (const int *)dev(ad.o_off);
+    a.bra_G = (const double *)dev(bd.o_G);
+    a.ket_G = (const double *)dev(ad.o_G);
+    a.bra_H = (const double *)dev(bd.o_H);
+    a.ket_H = (const double *)dev(ad.o_H);
+    a.border = (const uint32_t *)dev(bd.o_order);
+    a.korder = (const uint32_t *)dev(ad.o_order);
+    a.orow = (const long *)dev(bd.o_rows);
+    a.ocol = (const long *)dev(ad.o_rows);
+    a.tab = c->tab;
+    a.V = V;
+  }
+  // pair-data launches
+  auto pair_args = [&](const SideData &d, const mderi_basis *bb, bool ket) {
+    PairArgs pa{};
+    pa.basis = bb->dev;
+    pa.tab = c->tab;
+    pa.npp = d.npp;
+    pa.pp = (const PrimPair *)dev(d.o_pp);
+    pa.la = d.la;
+    pa.lb = d.lb;
+    pa.Nh = d.Nh;
+    pa.N = d.N;
+    pa.Nh_pad = d.Nh_pad;
+    pa.N_pad = d.N_pad;
+    pa.ket_sign = ket ? 1 : 0;
+    pa.one_centre = ket ? 1 : 0;
+    pa.deriv = 0;
+    pa.order = (const uint32_t *)dev(d.o_order);
+    pa.G = (double *)dev(d.o_G);
+    pa.H = (double *)dev(d.o_H);
+    return pa;
+  };
+  for (auto &kv : bside) plan->pairs.push_back(pair_args(kv.second, b, false));
+  for (auto &kv : aside) plan->pairs.push_back(pair_args(kv.second, aux, true));
+  // upload everything written so far (descriptors and tasks follow)
+  if (hipMemcpy(base, img.bytes.data(), o_blocks, hipMemcpyHostToDevice) != hipSuccess) {
+    free_plan(plan);
+    return fail(MDERI_EDEVICE, "mderi_eri3_batch: plan upload failed");
+  }
+  for (const PairArgs &pa : plan->pairs)
+    if (launch_pairs(pa, s) != hipSuccess) {
+      free_plan(plan);
+      return fail(MDERI_EDEVICE, "mderi_eri3_batch: pair-data launch failed");
+    }
+  // per-block task lists (quartet index ij + nbra kl), cost for ordering
+  auto block_cost = [&](const BlockPlan &bp) {
+    const Eri4Args &a = bp.a;
+    return (double)a.Nhb * a.Nhk * a.Nk + (double)a.Nb * a.Nhb * a.Nk + (double)(a.L + 1) * (a.L + 2) * (a.L + 3) / 6;
+  };
+  // autotune: time each candidate of an untuned block alone
+  if (flags & MDERI_FLAG_AUTOTUNE) {
+    std::vector<Eri4Args> one(1);
+    std::vector<int2> tk;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    for (size_t bi = 0; bi < blocks.size(); ++bi) {
+      BlockPlan &bp = blocks[bi];
+      if (bp.cands.size() <= 1) continue;
+      const int nq = bp.a.nbra * bp.a.nket;
+      tk.resize(nq);
+      for (int q = 0; q < nq; ++q) tk[q] = make_int2(0, q);
+      HIP_TRY(hipMemcpyAsync(dev(o_tasks), tk.data(), sizeof(int2) * nq, hipMemcpyHostToDevice, s));
+      float best = 1e30f;
+      std::array<int, 3> bestc = bp.cands[0];
+      for (auto &cd : bp.cands) {
+        one[0] = bp.a;
+        one[0].npt = cd[0];
+        one[0].nps = cd[1];
+        one[0].dbuf = cd[2];
+        one[0].Nhb_pad = 16 * cd[0] * cd[1];
+        HIP_TRY(hipMemcpyAsync(dev(o_blocks), one.data(), sizeof(Eri4Args), hipMemcpyHostToDevice, s));
+        const int waves = one[0].nct * cd[1] + 1;
+        const size_t lds = block_lds(one[0]);
+        const int grid = group_grid(lds, waves, nq);
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches
+          HIP_TRY(hipEventRecord(e0, s));
+          HIP_TRY(launch_eri4_tasks((const Eri4Args *)dev(o_blocks), (const int2 *)dev(o_tasks), nq, cd[0], bp.a.L,
+                                    waves, lds, grid, s));
+          HIP_TRY(hipEventRecord(e1, s));
+          HIP_TRY(hipEventSynchronize(e1));
+          HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        }
+        if (ms < best) {
+          best = ms;
+          bestc = cd;
+        }
+      }
+      bp.cands = {bestc};
+      c->tune[bp.sig] = bestc;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  // groups: blocks sharing (npt, producer bucket)
+  std::map<std::pair<int, int>, std::vector<int>> gmap;
+  for (size_t bi = 0; bi < blocks.size(); ++bi) {
+    BlockPlan &bp = blocks[bi];
+    const std::array<int, 3> cd = bp.cands[0];
+    bp.a.npt = cd[0];
+    bp.a.nps = cd[1];
+    bp.a.dbuf = cd[2];
+    bp.a.Nhb_pad = 16 * cd[0] * cd[1];
+    gmap[{cd[0], eri4_lm_bucket(bp.a.L)}].push_back((int)bi);
+  }
+  std::vector<Eri4Args> dblocks(blocks.size());
+  std::vector<int2> tasks;
+  tasks.reserve(ntask_all);
+  size_t bslot = 0;
+  for (auto &gkv : gmap) {
+    TaskGroup g{};
+    g.npt = gkv.first.first;
+    g.Lmax = 0;
+    g.waves = 2;
+    g.lds = 0;
+    const size_t first_block = bslot, first_task = tasks.size();
+    std::vector<std::pair<double, int2>> tl;
+    for (int bi : gkv.second) {
+      const BlockPlan &bp = blocks[bi];
+      dblocks[bslot] = bp.a;
+      g.Lmax = std::max(g.Lmax, bp.a.L);
+      g.waves = std::max(g.waves, bp.a.nct * bp.a.nps + 1);
+      g.lds = std::max(g.lds, block_lds(bp.a));
+      const double cost = block_cost(bp);
+      const int nq = bp.a.nbra * bp.a.nket;
+      for (int q = 0; q < nq; ++q) {
+        const int ij = q % bp.a.nbra, kl = q / bp.a.nbra;
+        const std::vector<int> &bo = bside[bp.bc].off, &ao = aside[bp.l].off;
+        const double w = cost * (bo[ij + 1] - bo[ij]) * (ao[kl + 1] - ao[kl]);
+        tl.push_back({w, make_int2((int)(bslot - first_block), q)});
+      }
+      ++bslot;
+    }
+    std::stable_sort(tl.begin(), tl.end(), [](const std::pair<double, int2> &x, const std::pair<double, int2> &y) {
+      return x.first > y.first;
+    });
+    for (auto &t : tl) tasks.push_back(t.second);
+    g.ntask = (int)tl.size();
+    g.d_blocks = (const Eri4Args *)dev(o_blocks) + first_block;
+    g.d_tasks = (const int2 *)dev(o_tasks) + first_task;
+    g.grid = group_grid(g.lds, g.waves, g.ntask);
+    plan->groups.push_back(g);
+  }
+  HIP_TRY(hipMemcpyAsync(dev(o_blocks), dblocks.data(), sizeof(Eri4Args) * dblocks.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dev(o_tasks), tasks.data(), sizeof(int2) * tasks.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));  // host vectors above go out of scope
+  // keep at most 8 plans
+  if (c->plans.size() >= 8) {
+    HIP_TRY(hipDeviceSynchronize());
+    free_plan(c->plans.front());
+    c->plans.erase(c->plans.begin());
+  }
+  c->plans.push_back(plan);
+  if (flags & MDERI_FLAG_GRAPH) {
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    st = launch_plan(c, plan, c->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+    if (st) return st;
+    if (ec != hipSuccess) return fail(MDERI_EDEVICE, "mderi_eri3_batch: graph capture failed (%s)", hipGetErrorString(ec));
+    plan->graph = graph;
+    HIP_TRY(hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0));
+    HIP_TRY(hipGraphLaunch(plan->exec, s));
+    return MDERI_OK;
+  }
+  // pair data was already produced on s above; run the groups
+  for (const TaskGroup &g : plan->groups)
+    HIP_TRY(launch_eri4_tasks(g.d_blocks, g.d_tasks, g.ntask, g.npt, g.Lmax, g.waves, g.lds, g.grid, s));
   return MDERI_OK;
 }

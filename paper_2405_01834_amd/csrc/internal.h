@@ -91,6 +91,7 @@ struct Eri4Args {
   int nbra, nket;
   int L, Nhb, Nhk, Nb, Nk;
   int Nhb_pad, Nhk_pad, Nb_pad, Nk_pad;
+  int Hb_rows;   // rows allocated per bra transform matrix (>= Nhb_pad; its stride)
   int npt;       // p tiles held by a consumer wave
   int nps;       // bra Hermite rows split over nps waves (Nhb_pad = 16 npt nps)
   int nct;       // ket column tiles (Nk_pad = 16 nct)
@@ -118,6 +119,10 @@ struct Eri4Args {
   // workgroup adds sum W d(ab|cd)/dA, dB to grad[atom][xyz] (see kgrad)
   double *grad;
   const int *atom;                // atom of every shell
+  // matrix output (orow != nullptr): (ab, cd) of quartet (ij, kl) goes to
+  // V[orow[ij] + ab + ld * (ocol[kl] + cd)] instead of the class-batch layout
+  const long *orow, *ocol;
+  long ld;
   const int *bra_off, *ket_off;  // [n+1] primitive-pair offsets per shell pair
   const double *bra_G, *ket_G;
   const double *bra_H, *ket_H;
@@ -139,6 +144,15 @@ hipError_t launch_zero(size_t n, double *x, hipStream_t s);
 // grad admits 7-tile consumer waves (built only for gradient mode).
 bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int maxpp, bool grad, int *npt, int *nps,
                int *dbuf);
+// Persistent task-list launch over class blocks that share npt and the
+// producer length bucket of Lmax: d_blocks[nblk] device copies of the blocks'
+// arguments, d_tasks[ntask] = (block, ij + nbra kl); the workgroup has
+// `waves` waves and `lds` bytes (the largest block's), the grid `grid`
+// workgroups.
+hipError_t launch_eri4_tasks(const Eri4Args *d_blocks, const int2 *d_tasks, int ntask, int npt, int Lmax, int waves,
+                             size_t lds, int grid, hipStream_t s);
+// The producer length bucket (m-vector registers) used for total L.
+int eri4_lm_bucket(int L);
 // LDS bytes needed by one 4-centre workgroup.
 size_t eri4_lds_bytes(const Eri4Args &a);
 

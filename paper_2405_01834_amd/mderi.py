@@ -26,7 +26,12 @@ def lib_path() -> str:
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("schwarz_tau", ctypes.c_double), ("reserved", ctypes.c_int * 4)]
+    _fields_ = [("precision", ctypes.c_int), ("schwarz_tau", ctypes.c_double), ("flags", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
+
+
+FLAG_GRAPH = 1
+FLAG_AUTOTUNE = 2
 
 
 _vp = ctypes.c_void_p
@@ -64,6 +69,9 @@ def load_library():
     L.mderi_eri3.restype = ctypes.c_int
     L.mderi_kbuild.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _vp]
     L.mderi_kbuild.restype = ctypes.c_int
+    L.mderi_eri3_batch.argtypes = [_vp, _vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
+                                   ctypes.POINTER(Opts), _vp]
+    L.mderi_eri3_batch.restype = ctypes.c_int
     L.mderi_kernel_timing.argtypes = [_vp, ctypes.c_int]
     L.mderi_kernel_timing.restype = ctypes.c_int
     L.mderi_kernel_times.argtypes = [_vp, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
@@ -161,6 +169,31 @@ class Context:
                                          len(auxidx), auxidx.ctypes.data_as(_ip), _vp(out.data_ptr()), out.numel(),
                                          None, _stream_handle(stream)))
         return out[:n].view(len(auxidx), npp, nab, len(pairs)).permute(3, 2, 1, 0)
+
+    def eri3_batch(self, basis: "Basis", aux: "Basis", pairs, auxidx, flags=0, out=None, stream=None):
+        """(ab|P) over pairs and auxiliary shells of any classes in one task-list
+        call -> torch float64 matrix [sum_i N_ab(i), sum_k N(l_k)] (a column-major
+        view): row block i = pair i, column block k = aux shell k, both in list
+        order.  flags: FLAG_GRAPH, FLAG_AUTOTUNE."""
+        import torch
+        pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        auxidx = np.ascontiguousarray(np.asarray(auxidx, dtype=np.int32).reshape(-1))
+        ok = (len(pairs) > 0 and len(auxidx) > 0 and pairs.min() >= 0 and pairs.max() < basis.nshell and
+              auxidx.min() >= 0 and auxidx.max() < aux.nshell)
+        opts = Opts(0, 1e-12, int(flags))
+        if not ok:
+            _check(load_library().mderi_eri3_batch(self._h, basis._h, aux._h, len(pairs), pairs.ctypes.data_as(_ip),
+                                                   len(auxidx), auxidx.ctypes.data_as(_ip), None, 0,
+                                                   ctypes.byref(opts), _stream_handle(stream)))
+        nrow = int(sum(nsph(int(basis.l[a])) * nsph(int(basis.l[b])) for a, b in pairs))
+        ncol = int(sum(nsph(int(aux.l[k])) for k in auxidx))
+        if out is None:
+            out = torch.empty(nrow * ncol, dtype=torch.float64, device=f"cuda:{self.device}")
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        _check(load_library().mderi_eri3_batch(self._h, basis._h, aux._h, len(pairs), pairs.ctypes.data_as(_ip),
+                                               len(auxidx), auxidx.ctypes.data_as(_ip), _vp(out.data_ptr()),
+                                               out.numel(), ctypes.byref(opts), _stream_handle(stream)))
+        return out[:nrow * ncol].view(ncol, nrow).t()
 
     def kbuild(self, basis: "Basis", D, tau=1e-12, out=None, stream=None):
         """Exchange matrix K_ac = sum_bd (ab|cd) D_bd for a symmetric density D
