@@ -106,6 +106,45 @@ def cpu_baseline(batches, wall_per_class=2.5):
                       " quartets of each class batch; full-step time extrapolated per class"}
 
 
+def eri3_task_list(ctx, steps, flags):
+    """512 mixed primary pairs x 512 auxiliary shells (262,144 triplets) in one
+    task-list call; the first call builds, tunes and captures the plan."""
+    import torch
+    from paper_2405_01834_amd import inputs, model
+    from paper_2405_01834_amd.mderi import FLAG_AUTOTUNE, FLAG_GRAPH
+    prim, aux, pairs, auxidx = inputs.eri3_batch(3)
+    b = ctx.basis(prim.l, prim.nprim, prim.exps, prim.coefs, prim.centers)
+    a = ctx.basis(aux.l, aux.nprim, aux.exps, aux.coefs, aux.centers)
+    fl = {"graph+autotune": FLAG_GRAPH | FLAG_AUTOTUNE, "graph": FLAG_GRAPH, "plain": 0}[flags]
+    t = time.perf_counter()
+    B = ctx.eri3_batch(b, a, pairs, auxidx, flags=fl)
+    out = B.t().view(-1)
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        ctx.eri3_batch(b, a, pairs, auxidx, flags=fl, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    flops = 0.0
+    for i, (p0, p1) in enumerate(pairs):
+        kb = int(prim.nprim[p0] * prim.nprim[p1])
+        for k in auxidx:
+            flops += model.eri3_flops(int(prim.l[p0]), int(prim.l[p1]), int(aux.l[k]), kb, 1)
+    ntrip = len(pairs) * len(auxidx)
+    neri = B.shape[0] * B.shape[1]
+    log(f"eri3 task list ({flags}): {ntrip} triplets, {neri} ERIs, {ms:.3f} ms per call "
+        f"({ntrip / (ms * 1e-3):.3e} triplets/s, {flops / (ms * 1e-3) / 1e12:.2f} TFLOP/s); first call {first:.2f} s")
+    return {"ms": ms, "triplets": ntrip, "eris": neri, "triplets_per_s": ntrip / (ms * 1e-3),
+            "eris_per_s": neri / (ms * 1e-3), "model_tflops": flops / (ms * 1e-3) / 1e12,
+            "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / model.FP64_PEAK_TFLOPS, "flags": flags,
+            "first_call_s": first,
+            "workload": "512 primary pairs (l_a, l_b in 0..3, K 1..5 per shell) x 512 auxiliary shells "
+                        "(l_P in 0..6, K=1); 20-bohr cube, exponents log-U[0.05,500]; one mderi_eri3_batch call"}
+
+
 def backward_forward(ctx, natom, reps=3):
     """Exchange gradient time / K-build time on a synthetic cluster."""
     import torch
@@ -146,6 +185,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-wall", type=float, default=2.5, help="oracle wall seconds per class")
     ap.add_argument("--classes", default="", help="subset, e.g. 4:3,2:1 (l:K)")
+    ap.add_argument("--eri3", default="graph+autotune", choices=["graph+autotune", "graph", "plain", "off"],
+                    help="mode of the 3-centre task-list measurement")
     ap.add_argument("--cluster-atoms", type=int, default=12,
                     help="atoms of the cluster for the backward/forward ratio (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -250,6 +291,8 @@ def main():
                      "traffic": measured_traffic(f"eri4_kernel {dom}"), "traffic_unit": "B"},
         "wall_s": wall,
     }
+    if args.eri3 != "off":
+        rec["eri3_batch"] = eri3_task_list(ctx, max(args.steps, 3), args.eri3)
     if args.cluster_atoms > 0:
         rec["backward_forward"] = backward_forward(ctx, args.cluster_atoms)
     if not args.no_cpu:

@@ -82,8 +82,13 @@ __device__ __forceinline__ void kdigest(const Eri4Args &a, const double *v, int 
 // block's nct * nps consumers and its producer (a task-list launch sizes the
 // workgroup for its largest block) only take part in the barriers.
 template <int NPT, int LM, bool GRAD>
-__device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, double *smem) {
+__device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, int slab, double *smem) {
   const int L = a.L;
+  // column slab: this workgroup owns ket columns [c0, c0 + 16 nct); V keeps
+  // only those columns (row stride vstride) when the quartet is split
+  const int c0 = slab * a.nct * 16;
+  const int vstride = a.nslab > 1 ? a.nct * 16 : a.Nk;
+  const int vcols = min(a.Nk - c0, a.nct * 16);
   const int S1 = a.S1, S2 = a.S2;
   const int cube_sz = a.cube_sz;
   double *cube0 = smem;
@@ -92,7 +97,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
   double *gsh = work + rr_work_size(L);              // G of this quartet's bra then ket primitive pairs
   double *gsum = gsh + 4 * a.maxpp;                  // 8 gradient partial sums
   double *vsh = gsum + 8;                            // V[ab][cd] (or the weights W) of this quartet
-  uint32_t *uvsh = (uint32_t *)(vsh + a.Nb * a.Nk);  // (u, v) pairs, u+v <= L, by u+v
+  uint32_t *uvsh = (uint32_t *)(vsh + a.Nb * vstride);  // (u, v) pairs, u+v <= L, by u+v
   int *offq = (int *)(uvsh + (L + 1) * (L + 2) / 2);
 
   const int tid = threadIdx.x;
@@ -128,7 +133,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     }
     if (tid < 8) gsum[tid] = 0.0;
   } else {
-    for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) vsh[e] = 0.0;
+    for (int e = tid; e < a.Nb * vstride; e += blockDim.x) vsh[e] = 0.0;
   }
   for (int q = tid; q < a.Nhk_pad; q += blockDim.x) {
     int o = 0;
@@ -166,7 +171,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
   } else {
     // ---------------- consumers ----------------
     const int ct = wave % a.nct, ph = wave / a.nct;
-    const int col = ct * 16 + c;  // this lane's ket column cd
+    const int col = c0 + ct * 16 + c;  // this lane's ket column cd
     int offp[NPT];
 #pragma unroll
     for (int pt = 0; pt < NPT; ++pt) {
@@ -300,7 +305,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int ab = at * 16 + 4 * r + g;
-              if (ab < a.Nb) atomicAdd(&vsh[ab * a.Nk + col], acc0[r] + acc1[r]);
+              if (ab < a.Nb) atomicAdd(&vsh[ab * vstride + (col - c0)], acc0[r] + acc1[r]);
             }
           }
         }
@@ -343,17 +348,17 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
   }
   if (a.orow) {
     // matrix output: (ab, cd) of quartet (ij, kl) at V[orow[ij] + ab + ld (ocol[kl] + cd)]
-    const long r0 = a.orow[ij], c0 = a.ocol[kl];
-    for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) {
-      const int cd = e / a.Nb, ab = e - cd * a.Nb;
-      a.V[r0 + ab + a.ld * (c0 + cd)] = vsh[ab * a.Nk + cd];
+    const long r0 = a.orow[ij], q0 = a.ocol[kl];
+    for (int e = tid; e < a.Nb * vcols; e += blockDim.x) {
+      const int cl = e / a.Nb, ab = e - cl * a.Nb;
+      a.V[r0 + ab + a.ld * (q0 + c0 + cl)] = vsh[ab * vstride + cl];
     }
     return;
   }
   const size_t base = (size_t)ij + (size_t)a.nbra * (size_t)a.Nb * (size_t)a.Nk * kl;
-  for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) {
-    const int cd = e / a.Nb, ab = e - cd * a.Nb;
-    a.V[base + (size_t)a.nbra * ((size_t)ab + (size_t)a.Nb * cd)] = vsh[ab * a.Nk + cd];
+  for (int e = tid; e < a.Nb * vcols; e += blockDim.x) {
+    const int cl = e / a.Nb, ab = e - cl * a.Nb;
+    a.V[base + (size_t)a.nbra * ((size_t)ab + (size_t)a.Nb * (c0 + cl))] = vsh[ab * vstride + cl];
   }
 }
 
@@ -361,8 +366,10 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
 template <int NPT, int LM, bool GRAD>
 __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
   extern __shared__ double smem[];
-  const long G = a.diag ? (long)a.nbra : (long)a.nbra * a.nket;
-  const long v = xcd_remap(blockIdx.x, G);
+  const long G = (a.diag ? (long)a.nbra : (long)a.nbra * a.nket) * a.nslab;
+  const long v0 = xcd_remap(blockIdx.x, G);
+  const int slab = (int)(v0 % a.nslab);  // slabs of one quartet are neighbours (shared bra data)
+  const long v = v0 / a.nslab;
   const int ij = (int)(v % a.nbra), kl = a.diag ? ij : (int)(v / a.nbra);
   if (a.kx) {
     // screened or symmetry-redundant quartet: the whole workgroup leaves
@@ -370,7 +377,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
     if (a.bra_q[ij] * a.ket_q[kl] < a.tau || (a.same_list && ij < kl)) return;
   }
   if (GRAD && a.bra_q[ij] * a.ket_q[kl] < a.tau) return;
-  eri4_quartet<NPT, LM, GRAD>(a, ij, kl, smem);
+  eri4_quartet<NPT, LM, GRAD>(a, ij, kl, slab, smem);
 }
 
 // Persistent task-list kernel: the workgroups stride over tasks (block id,
@@ -397,7 +404,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves)
 #endif
     const int ij = q % a.nbra, kl = q / a.nbra;
     __syncthreads();  // the previous task is done with LDS
-    eri4_quartet<NPT, LM, false>(a, ij, kl, smem);
+    eri4_quartet<NPT, LM, false>(a, ij, kl, 0, smem);
   }
 }
 
@@ -405,7 +412,7 @@ template <int NPT, int LM, bool GRAD>
 hipError_t launch_t(const Eri4Args &a, hipStream_t s) {
   const int waves = a.nct * a.nps + 1;
   const size_t lds = eri4_lds_bytes(a);
-  const long G = a.diag ? (long)a.nbra : (long)a.nbra * a.nket;
+  const long G = (a.diag ? (long)a.nbra : (long)a.nbra * a.nket) * a.nslab;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)eri4_kernel<NPT, LM, GRAD>,
@@ -471,36 +478,49 @@ static size_t side_bytes(int L, int maxpp, int Nhk_pad, int Nb, int Nk) {
 }
 
 size_t eri4_lds_bytes(const Eri4Args &a) {
-  return cube_region(a.cube_sz, a.dbuf ? 2 : 1) + side_bytes(a.L, a.maxpp, a.Nhk_pad, a.Nb, a.Nk);
+  const int vcols = a.nslab > 1 ? a.nct * 16 : a.Nk;
+  return cube_region(a.cube_sz, a.dbuf ? 2 : 1) + side_bytes(a.L, a.maxpp, a.Nhk_pad, a.Nb, vcols);
 }
 
-bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int maxpp, bool grad, int *npt, int *nps,
-               int *dbuf) {
-  const int need_p = round16(Nhb) / 16, nct = round16(Nk) / 16;
-  // bra rows split over `parts` waves of at most 6 tiles each; when that
-  // needs more waves than a workgroup holds, 7-tile waves (gradient mode's
-  // [gg| bra with Hermite degree 9 is the one such case)
-  *npt = 0;
-  for (int maxt = 6; maxt <= (grad ? 7 : 6) && !*npt; ++maxt) {
-    int parts = 1;
-    while ((need_p + parts - 1) / parts > maxt) ++parts;
-    const int per = (need_p + parts - 1) / parts;
-    if (nct * parts + 1 > kMaxWaves) continue;
-    for (int t : kTiles)
-      if (t >= per) {
-        *npt = t;
-        break;
-      }
-    *nps = parts;
-  }
-  if (!*npt) return false;
-  const size_t lds_budget = 160 * 1024;
+bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int maxpp, bool grad, bool slabs,
+               Eri4Plan *p) {
   if (L > 26) return false;
-  const size_t rest = side_bytes(L, maxpp, Nhk_pad, Nb, Nk);
-  if (cube_region(cube_sz, 2) + rest <= lds_budget) *dbuf = 1;
-  else if (cube_region(cube_sz, 1) + rest <= lds_budget) *dbuf = 0;
-  else return false;
-  return true;
+  const int need_p = round16(Nhb) / 16, nct_all = round16(Nk) / 16;
+  const size_t lds_budget = 160 * 1024;
+  // Preferred: all ket columns in one workgroup, bra rows split over `parts`
+  // waves of at most 6 tiles each (7 in gradient mode, which is built for
+  // the [gg| bra of Hermite degree 9).  When that does not fit the wave or
+  // LDS limits and `slabs` is allowed, the ket columns are split into slabs
+  // of nct tiles handled by separate workgroups.
+  for (int nslab = 1; nslab <= (slabs ? nct_all : 1); ++nslab) {
+    const int nct = (nct_all + nslab - 1) / nslab;
+    if (nslab > 1 && (nct_all + nct - 1) / nct != nslab) continue;  // same split as a smaller nslab
+    for (int maxt = 6; maxt <= (grad ? 7 : 6); ++maxt) {
+      int parts = 1;
+      while ((need_p + parts - 1) / parts > maxt) ++parts;
+      const int per = (need_p + parts - 1) / parts;
+      if (nct * parts + 1 > kMaxWaves) continue;
+      int npt = 0;
+      for (int t : kTiles)
+        if (t >= per && (t < 7 || grad)) {
+          npt = t;
+          break;
+        }
+      if (!npt) continue;
+      const size_t rest = side_bytes(L, maxpp, Nhk_pad, Nb, nslab > 1 ? nct * 16 : Nk);
+      int dbuf;
+      if (cube_region(cube_sz, 2) + rest <= lds_budget) dbuf = 1;
+      else if (cube_region(cube_sz, 1) + rest <= lds_budget) dbuf = 0;
+      else continue;
+      p->npt = npt;
+      p->nps = parts;
+      p->dbuf = dbuf;
+      p->nct = nct;
+      p->nslab = nslab;
+      return true;
+    }
+  }
+  return false;
 }
 
 template <int LM, bool GRAD>

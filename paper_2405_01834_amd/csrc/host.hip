@@ -12,6 +12,7 @@
 #include <map>
 #include <array>
 #include <numeric>
+#include <mutex>
 
 #include "internal.h"
 
@@ -174,7 +175,8 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 // context
 // ---------------------------------------------------------------------------
 enum WsSlot {
-  WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_ORDER, WS_KORDER, WS_QB, WS_QK, WS_SHB, WS_SHK, WS_KTMP, WS_QALL, WS_PAIRS, WS_COUNT
+  WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_ORDER,
+  WS_KORDER, WS_KTMP, WS_QALL, WS_PAIRS, WS_COUNT
 };
 
 struct TaskPlan;
@@ -505,16 +507,44 @@ mderi_status expand_pairs(const mderi_basis *b, int n, const int32_t *pairs, con
 
 namespace {
 
-// [r] cube strides for total angular momentum L: S2 > L and S1 > L*S2 keep
-// t*S1 + u*S2 + v injective on |r| <= L and additive in r, so [p+q] is found
-// at offset(p) + offset(q).  Among such strides, pick the pair whose bra
-// offsets (|p| <= Lb) fall most evenly into the 16 LDS bank pairs that one
-// 16-lane group of a 64-bit read spans, then the smallest cube.
+// Whether t*s1 + u*s2 + v is injective on |r| = t+u+v <= L.
+bool cube_injective(int L, int s1, int s2, std::vector<char> &seen) {
+  seen.assign((size_t)L * s1 + (size_t)L * s2 + L + 1, 0);
+  for (int t = 0; t <= L; ++t)
+    for (int u = 0; u <= L - t; ++u)
+      for (int v = 0; v <= L - t - u; ++v) {
+        char &x = seen[(size_t)t * s1 + (size_t)u * s2 + v];
+        if (x) return false;
+        x = 1;
+      }
+  return true;
+}
+
+// [r] cube strides for total angular momentum L: any (S1, S2) that keeps
+// t*S1 + u*S2 + v injective on |r| <= L makes the offset additive, so [p+q]
+// is found at offset(p) + offset(q) (S2 > L, S1 > L*S2 always works; smaller
+// S1 that stay injective give a cube up to a quarter smaller).  Among
+// injective strides near the smallest, pick the pair whose bra offsets
+// (|p| <= Lb) fall most evenly into the 16 LDS bank pairs that one 16-lane
+// group of a 64-bit read spans, then the smallest cube.  Cached per (L, Lb).
 void choose_cube(int L, int Lb, int *S1, int *S2) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, std::pair<int, int>> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find({L, Lb});
+  if (it != cache.end()) {
+    *S1 = it->second.first;
+    *S2 = it->second.second;
+    return;
+  }
   const int n = ntil(Lb), nt = (n + 15) / 16;
   long best_key = -1;
-  for (int s2 = L + 1; s2 <= L + 16; ++s2)
-    for (int s1 = L * s2 + 1; s1 <= L * s2 + 16; ++s1) {
+  std::vector<char> seen;
+  for (int s2 = L + 1; s2 <= L + 16; ++s2) {
+    int s1min = s2 + 1;
+    while (s1min <= L * s2 + 1 && !cube_injective(L, s1min, s2, seen)) ++s1min;
+    for (int s1 = s1min; s1 <= s1min + 24; ++s1) {
+      if (s1 > s1min && !cube_injective(L, s1, s2, seen)) continue;
       int hist[16] = {0};
       for (int d = 0; d <= Lb; ++d)
         for (int t = d; t >= 0; --t)
@@ -529,6 +559,8 @@ void choose_cube(int L, int Lb, int *S1, int *S2) {
         *S2 = s2;
       }
     }
+  }
+  cache[{L, Lb}] = {*S1, *S2};
 }
 
 // Row order of the bra Hermite functions for tiles of 16 rows: functions
@@ -600,8 +632,6 @@ struct Digest {
   const double *dm;
   int nao;
   double tau;
-  std::vector<double> qb, qk;       // Schwarz factors per bra / ket pair
-  std::vector<int32_t> shb, shk;    // shell pairs [n][2]
   // gradient mode: instead of digesting into K, add twice the bra-centre
   // derivatives of sum W (ab|cd) to grad[atom][xyz] (bra pair data in
   // derivative form, Hermite rows up to l_a+l_b+1)
@@ -609,18 +639,37 @@ struct Digest {
   const int *atom = nullptr;
 };
 
+// Launches the fused kernel, bracketed by timing events when timing is on.
+mderi_status launch_eri4_timed(mderi_ctx *c, const Eri4Args &ea, hipStream_t s) {
+  if (c->timing) {
+    if (c->ev_free.empty()) {
+      std::pair<hipEvent_t, hipEvent_t> e;
+      HIP_TRY(hipEventCreate(&e.first));
+      HIP_TRY(hipEventCreate(&e.second));
+      c->ev_free.push_back(e);
+    }
+    const auto e = c->ev_free.back();
+    c->ev_free.pop_back();
+    c->ev_used.push_back(e);
+    HIP_TRY(hipEventRecord(e.first, s));
+    HIP_TRY(launch_eri4(ea, s));
+    HIP_TRY(hipEventRecord(e.second, s));
+  } else {
+    HIP_TRY(launch_eri4(ea, s));
+  }
+  return MDERI_OK;
+}
+
 mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int diag, double *V,
-                             const std::vector<int> *extra_idx, void **d_extra_idx, hipStream_t s,
-                             const Digest *dg = nullptr) {
+                             const std::vector<int> *extra_idx, void **d_extra_idx, hipStream_t s) {
   const int nbra = (int)bra.off.size() - 1, nket = (int)ket.off.size() - 1;
   const int la = bra.la, lb = bra.lb, lc = ket.la, ld = ket.one_centre ? 0 : ket.lb;
-  const bool grad = dg && dg->grad;
-  const int Lb = la + lb + (grad ? 1 : 0), Lk = lc + ld, L = Lb + Lk;
+  const int Lb = la + lb, Lk = lc + ld, L = Lb + Lk;
   const int Nb = nsph(la) * nsph(lb), Nk = ket.one_centre ? nsph(lc) : nsph(lc) * nsph(ld);
   const int Nhb = ntil(Lb);
   const std::vector<uint32_t> korder = ket.one_centre ? top_degree_rows(lc) : std::vector<uint32_t>();
   const int Nhk = ket.one_centre ? (lc + 1) * (lc + 2) / 2 : ntil(Lk);
-  const int Nhk_pad = (Nhk + 7) & ~7, Nk_pad = round16(Nk);
+  const int Nhk_pad = (Nhk + 7) & ~7;
   int S1 = 1, S2 = 1;
   choose_cube(L, Lb, &S1, &S2);
   const int cube_sz = (L * S1 + 2) & ~1;
@@ -628,10 +677,12 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   for (int i = 0; i < nbra; ++i) maxb = std::max(maxb, bra.off[i + 1] - bra.off[i]);
   for (int i = 0; i < nket; ++i) maxk = std::max(maxk, ket.off[i + 1] - ket.off[i]);
   const int maxpp = maxb + maxk;
-  int npt = 0, nps = 0, dbuf = 0;
-  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, grad, &npt, &nps, &dbuf))
+  Eri4Plan pl{};
+  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, false, diag == 0, &pl))
     return fail(MDERI_EUNSUPPORTED, "class (%d%d|%d%d) is beyond the fused kernel's tiles", la, lb, lc, ld);
+  const int npt = pl.npt, nps = pl.nps, dbuf = pl.dbuf;
   const int Nhb_pad = 16 * npt * nps, Nb_pad = round16(Nb);
+  const int Nk_pad = std::max(round16(Nk), 16 * pl.nct * pl.nslab);  // slabs read whole tiles
   const std::vector<uint32_t> border = bra_row_order(Lb, S1, S2, Nhb_pad);
   const std::vector<PrimPair> &ppb = bra.pp, &ppk = ket.pp;
   const std::vector<int> &offb = bra.off, &offk = ket.off;
@@ -644,23 +695,14 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
       (st = ws_get(c, WS_OFF_KET, sizeof(int) * offk.size(), &d_offk)) ||
       (st = ws_get(c, WS_G_BRA, sizeof(double) * 4 * ppb.size(), &d_Gb)) ||
       (st = ws_get(c, WS_G_KET, sizeof(double) * 4 * ppk.size(), &d_Gk)) ||
-      (st = ws_get(c, WS_H_BRA, sizeof(double) * (grad ? 6 : 1) * (size_t)Nhb_pad * Nb_pad * ppb.size(), &d_Hb)) ||
+      (st = ws_get(c, WS_H_BRA, sizeof(double) * (size_t)Nhb_pad * Nb_pad * ppb.size(), &d_Hb)) ||
       (st = ws_get(c, WS_H_KET, sizeof(double) * (size_t)Nhk_pad * Nk_pad * ppk.size(), &d_Hk)))
     return st;
   if (!korder.empty() && (st = ws_get(c, WS_KORDER, sizeof(uint32_t) * korder.size(), &d_korder))) return st;
-  void *d_qb = nullptr, *d_qk = nullptr, *d_shb = nullptr, *d_shk = nullptr;
-  if (dg && ((st = ws_get(c, WS_QB, sizeof(double) * dg->qb.size(), &d_qb)) ||
-             (st = ws_get(c, WS_QK, sizeof(double) * dg->qk.size(), &d_qk)) ||
-             (st = ws_get(c, WS_SHB, sizeof(int32_t) * dg->shb.size(), &d_shb)) ||
-             (st = ws_get(c, WS_SHK, sizeof(int32_t) * dg->shk.size(), &d_shk))))
-    return st;
   if (extra_idx && (st = ws_get(c, WS_IDX, sizeof(int) * extra_idx->size(), d_extra_idx))) return st;
   const size_t stage_need = sizeof(PrimPair) * (ppb.size() + ppk.size()) + sizeof(int) * (offb.size() + offk.size()) +
                             (extra_idx ? sizeof(int) * extra_idx->size() : 0) + sizeof(uint32_t) * border.size() +
-                            sizeof(uint32_t) * korder.size() + 12 * 256 +
-                            (dg ? sizeof(double) * (dg->qb.size() + dg->qk.size()) +
-                                      sizeof(int32_t) * (dg->shb.size() + dg->shk.size())
-                                : 0);
+                            sizeof(uint32_t) * korder.size() + 12 * 256;
   if ((st = stage_begin(c, stage_need))) return st;
   size_t used = 0;
   if ((st = stage_copy(c, d_ppb, ppb.data(), sizeof(PrimPair) * ppb.size(), s, &used)) ||
@@ -673,11 +715,6 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
       (st = stage_copy(c, d_korder, korder.data(), sizeof(uint32_t) * korder.size(), s, &used)))
     return st;
   if (extra_idx && (st = stage_copy(c, *d_extra_idx, extra_idx->data(), sizeof(int) * extra_idx->size(), s, &used)))
-    return st;
-  if (dg && ((st = stage_copy(c, d_qb, dg->qb.data(), sizeof(double) * dg->qb.size(), s, &used)) ||
-             (st = stage_copy(c, d_qk, dg->qk.data(), sizeof(double) * dg->qk.size(), s, &used)) ||
-             (st = stage_copy(c, d_shb, dg->shb.data(), sizeof(int32_t) * dg->shb.size(), s, &used)) ||
-             (st = stage_copy(c, d_shk, dg->shk.data(), sizeof(int32_t) * dg->shk.size(), s, &used))))
     return st;
   if ((st = stage_end(c, s))) return st;
 
@@ -694,7 +731,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   pa.N_pad = Nb_pad;
   pa.ket_sign = 0;
   pa.one_centre = 0;
-  pa.deriv = grad ? 1 : 0;
+  pa.deriv = 0;
   pa.order = (const uint32_t *)d_border;
   pa.G = (double *)d_Gb;
   pa.H = (double *)d_Hb;
@@ -731,7 +768,8 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   ea.Nk_pad = Nk_pad;
   ea.npt = npt;
   ea.nps = nps;
-  ea.nct = Nk_pad / 16;
+  ea.nct = pl.nct;
+  ea.nslab = pl.nslab;
   ea.dbuf = dbuf;
   ea.S1 = S1;
   ea.S2 = S2;
@@ -748,41 +786,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   ea.ket_H = (const double *)d_Hk;
   ea.tab = c->tab;
   ea.V = V;
-  if (dg) {
-    ea.kx = grad ? nullptr : dg->kx;
-    ea.grad = grad ? dg->grad : nullptr;
-    ea.atom = grad ? dg->atom : nullptr;
-    ea.dm = dg->dm;
-    ea.nao = dg->nao;
-    ea.tau = dg->tau;
-    ea.same_list = (!grad && &bra == &ket) ? 1 : 0;
-    ea.bra_q = (const double *)d_qb;
-    ea.ket_q = (const double *)d_qk;
-    ea.bra_sh = (const int *)d_shb;
-    ea.ket_sh = (const int *)d_shk;
-    ea.ao_off = bra.b->dev.ao_off;
-    ea.nsa = nsph(la);
-    ea.nsb = nsph(lb);
-    ea.nsc = nsph(lc);
-    ea.nsd = nsph(ld);
-  }
-  if (c->timing) {
-    if (c->ev_free.empty()) {
-      std::pair<hipEvent_t, hipEvent_t> e;
-      HIP_TRY(hipEventCreate(&e.first));
-      HIP_TRY(hipEventCreate(&e.second));
-      c->ev_free.push_back(e);
-    }
-    const auto e = c->ev_free.back();
-    c->ev_free.pop_back();
-    c->ev_used.push_back(e);
-    HIP_TRY(hipEventRecord(e.first, s));
-    HIP_TRY(launch_eri4(ea, s));
-    HIP_TRY(hipEventRecord(e.second, s));
-  } else {
-    HIP_TRY(launch_eri4(ea, s));
-  }
-  return MDERI_OK;
+  return launch_eri4_timed(c, ea, s);
 }
 
 // Validates single shells of one l and expands them into primitives.
@@ -922,24 +926,6 @@ mderi_status select_pairs(mderi_ctx *c, mderi_basis *b, double tau, hipStream_t 
   return MDERI_OK;
 }
 
-// Fills the per-pair screening data of a (bra class, ket class) block.
-void digest_block(const PairSets &ps, int c1, int c2, Digest &dg) {
-  dg.qb.clear();
-  dg.qk.clear();
-  dg.shb.clear();
-  dg.shk.clear();
-  for (int p : ps.cls[c1]) {
-    dg.qb.push_back(ps.q[p]);
-    dg.shb.push_back(ps.pairs[2 * p]);
-    dg.shb.push_back(ps.pairs[2 * p + 1]);
-  }
-  for (int p : ps.cls[c2]) {
-    dg.qk.push_back(ps.q[p]);
-    dg.shk.push_back(ps.pairs[2 * p]);
-    dg.shk.push_back(ps.pairs[2 * p + 1]);
-  }
-}
-
 mderi_status check_density(const char *fn, mderi_ctx *c, mderi_basis *b, const double *D, int nao,
                            const mderi_opts *opts) {
   if (!c || !b) return fail(MDERI_EINVAL, "%s: NULL context or basis", fn);
@@ -950,6 +936,11 @@ mderi_status check_density(const char *fn, mderi_ctx *c, mderi_basis *b, const d
   return MDERI_OK;
 }
 
+}  // namespace
+
+namespace {
+mderi_status run_pair_blocks(mderi_ctx *c, mderi_basis *b, const PairSets &ps, const Digest &dg, bool grad,
+                             hipStream_t s);
 }  // namespace
 
 extern "C" mderi_status mderi_kbuild(mderi_ctx_t c, mderi_basis_t b, const double *D, double *K, int nao,
@@ -970,19 +961,8 @@ extern "C" mderi_status mderi_kbuild(mderi_ctx_t c, mderi_basis_t b, const doubl
   dg.dm = D;
   dg.nao = nao;
   dg.tau = tau;
-  const int ncls = (int)ps.cls.size();
   // unordered class blocks; inside a diagonal block the kernel keeps ij >= kl
-  for (int c1 = 0; c1 < ncls; ++c1) {
-    if (ps.cls[c1].empty()) continue;
-    for (int c2 = c1; c2 < ncls; ++c2) {
-      if (ps.cls[c2].empty()) continue;
-      if ((double)ps.cls[c1].size() * ps.cls[c2].size() > 2.0e9)
-        return fail(MDERI_EUNSUPPORTED, "mderi_kbuild: class block of %zu x %zu pairs is too large",
-                    ps.cls[c1].size(), ps.cls[c2].size());
-      digest_block(ps, c1, c2, dg);
-      if ((st = run_class_batch(c, ps.sides[c1], ps.sides[c2], 0, nullptr, nullptr, nullptr, s, &dg))) return st;
-    }
-  }
+  if ((st = run_pair_blocks(c, b, ps, dg, false, s))) return st;
   HIP_TRY(launch_symmetrize(nao, (const double *)d_kt, K, s));
   return MDERI_OK;
 }
@@ -1008,21 +988,9 @@ extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, const 
   dg.tau = tau;
   dg.grad = grad;
   dg.atom = b->dev.atom;
-  const int ncls = (int)ps.cls.size();
   // every ordered (bra class, ket class) block: each visit supplies the
   // bra-centre derivatives, its swapped visit the ket-centre ones
-  for (int c1 = 0; c1 < ncls; ++c1) {
-    if (ps.cls[c1].empty()) continue;
-    for (int c2 = 0; c2 < ncls; ++c2) {
-      if (ps.cls[c2].empty()) continue;
-      if ((double)ps.cls[c1].size() * ps.cls[c2].size() > 2.0e9)
-        return fail(MDERI_EUNSUPPORTED, "mderi_kbuild_grad: class block of %zu x %zu pairs is too large",
-                    ps.cls[c1].size(), ps.cls[c2].size());
-      digest_block(ps, c1, c2, dg);
-      if ((st = run_class_batch(c, ps.sides[c1], ps.sides[c2], 0, nullptr, nullptr, nullptr, s, &dg))) return st;
-    }
-  }
-  return MDERI_OK;
+  return run_pair_blocks(c, b, ps, dg, true, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1080,9 +1048,10 @@ struct Image {
 std::vector<std::array<int, 3>> block_candidates(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad,
                                                  int maxpp) {
   std::vector<std::array<int, 3>> out;
-  int npt = 0, nps = 0, dbuf = 0;
-  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, false, &npt, &nps, &dbuf)) return out;
-  out.push_back({npt, nps, dbuf});
+  Eri4Plan pl{};
+  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, false, false, &pl)) return out;
+  const int dbuf = pl.dbuf;
+  out.push_back({pl.npt, pl.nps, pl.dbuf});
   const int need = (Nhb + 15) / 16, nct = (Nk + 15) / 16;
   const int tiles[] = {1, 2, 3, 4, 6};
   for (int parts = 1; parts <= 4; ++parts) {
@@ -1279,9 +1248,9 @@ extern "C" mderi_status mderi_eri3_batch(mderi_ctx_t c, mderi_basis_t b, mderi_b
       a.Nhk_pad = ad.Nh_pad;
       a.Nk_pad = ad.N_pad;
       a.nct = ad.N_pad / 16;
-      a.S1 = d.S1;
-      a.S2 = d.S2;
-      a.cube_sz = (L * d.S1 + 2) & ~1;
+      a.nslab = 1;
+      choose_cube(L, Lb, &a.S1, &a.S2);  // the block's own L (small cubes for small l_P)
+      a.cube_sz = (L * a.S1 + 2) & ~1;
       a.maxpp = maxb + ad.maxpp;
       a.ld = nrow;
       bp.cands = block_candidates(a.Nhb, a.Nb, a.Nk, L, a.cube_sz, a.Nhk_pad, a.maxpp);
@@ -1511,3 +1480,191 @@ extern "C" mderi_status mderi_eri3_batch(mderi_ctx_t c, mderi_basis_t b, mderi_b
     HIP_TRY(launch_eri4_tasks(g.d_blocks, g.d_tasks, g.ntask, g.npt, g.Lmax, g.waves, g.lds, g.grid, s));
   return MDERI_OK;
 }
+
+// ---------------------------------------------------------------------------
+// K build and gradient: all class blocks of a call from one upload
+// ---------------------------------------------------------------------------
+namespace {
+
+// Pair data is computed once per class (once in the bra role, with the
+// class's bank-spread row order and strides that fit its largest L, and once
+// in the ket role), all metadata goes up in one staged copy, and the blocks
+// are launched back to back without host synchronisation.
+mderi_status run_pair_blocks(mderi_ctx *c, mderi_basis *b, const PairSets &ps, const Digest &dg, bool grad,
+                             hipStream_t s) {
+  struct Cls {
+    int la, lb, Lbb, Lk, Nb, Nb_pad, Nhb, Nhk, Nhk_pad, npp, maxpp, S1 = 0, S2 = 0, Lmax = 0, nh_alloc = 0;
+    size_t o_pp, o_off, o_q, o_sh, o_order, o_Gb, o_Hb, o_Gk, o_Hk;
+  };
+  struct Blk {
+    int c1, c2, L, npt, nps, dbuf, cube_sz, maxpp, S1, S2;
+  };
+  std::map<int, Cls> C;
+  for (size_t ci = 0; ci < ps.cls.size(); ++ci) {
+    if (ps.cls[ci].empty()) continue;
+    const Side &sd = ps.sides[ci];
+    Cls k{};
+    k.la = sd.la;
+    k.lb = sd.lb;
+    k.Lbb = sd.la + sd.lb + (grad ? 1 : 0);
+    k.Lk = sd.la + sd.lb;
+    k.Nb = nsph(sd.la) * nsph(sd.lb);
+    k.Nb_pad = round16(k.Nb);
+    k.Nhb = ntil(k.Lbb);
+    k.Nhk = ntil(k.Lk);
+    k.Nhk_pad = (k.Nhk + 7) & ~7;
+    k.npp = (int)sd.pp.size();
+    for (size_t i = 0; i + 1 < sd.off.size(); ++i) k.maxpp = std::max(k.maxpp, sd.off[i + 1] - sd.off[i]);
+    C[(int)ci] = k;
+  }
+  std::vector<Blk> blocks;
+  for (auto &x : C)
+    for (auto &y : C) {
+      if (!grad && y.first < x.first) continue;
+      if ((double)ps.cls[x.first].size() * ps.cls[y.first].size() > 2.0e9)
+        return fail(MDERI_EUNSUPPORTED, "class block of %zu x %zu pairs is too large", ps.cls[x.first].size(),
+                    ps.cls[y.first].size());
+      Blk bk{};
+      bk.c1 = x.first;
+      bk.c2 = y.first;
+      bk.L = x.second.Lbb + y.second.Lk;
+      x.second.Lmax = std::max(x.second.Lmax, bk.L);
+      blocks.push_back(bk);
+    }
+  for (auto &x : C) choose_cube(x.second.Lmax, x.second.Lbb, &x.second.S1, &x.second.S2);
+  for (Blk &bk : blocks) {
+    Cls &x = C[bk.c1], &y = C[bk.c2];
+    // strides for the block's own L keep small blocks' cubes small; the
+    // class's row order follows the strides of its largest block
+    choose_cube(bk.L, x.Lbb, &bk.S1, &bk.S2);
+    bk.cube_sz = (bk.L * bk.S1 + 2) & ~1;
+    bk.maxpp = x.maxpp + y.maxpp;
+    Eri4Plan pl{};
+    const bool ok = eri4_plan(x.Nhb, x.Nb, y.Nb, bk.L, bk.cube_sz, y.Nhk_pad, bk.maxpp, grad, false, &pl);
+    bk.npt = pl.npt;
+    bk.nps = pl.nps;
+    bk.dbuf = pl.dbuf;
+    if (!ok)
+      return fail(MDERI_EUNSUPPORTED, "class (%d%d|%d%d)%s is beyond the fused kernel's tiles", x.la, x.lb, y.la, y.lb,
+                  grad ? " (gradient)" : "");
+    x.nh_alloc = std::max(x.nh_alloc, 16 * bk.npt * bk.nps);
+  }
+  Image img;
+  const int mats = grad ? 6 : 1;
+  for (auto &x : C) {
+    Cls &k = x.second;
+    const Side &sd = ps.sides[x.first];
+    std::vector<double> q;
+    std::vector<int32_t> sh;
+    for (int p : ps.cls[x.first]) {
+      q.push_back(ps.q[p]);
+      sh.push_back(ps.pairs[2 * p]);
+      sh.push_back(ps.pairs[2 * p + 1]);
+    }
+    std::vector<uint32_t> order = bra_row_order(k.Lbb, k.S1, k.S2, round16(k.Nhb));
+    while ((int)order.size() < k.nh_alloc) order.push_back(order[0] | kPadRow);
+    k.o_pp = img.add(sd.pp.data(), sizeof(PrimPair) * sd.pp.size());
+    k.o_off = img.add(sd.off.data(), sizeof(int) * sd.off.size());
+    k.o_q = img.add(q.data(), sizeof(double) * q.size());
+    k.o_sh = img.add(sh.data(), sizeof(int32_t) * sh.size());
+    k.o_order = img.add(order.data(), sizeof(uint32_t) * order.size());
+  }
+  const size_t meta_bytes = img.bytes.size();
+  for (auto &x : C) {
+    Cls &k = x.second;
+    k.o_Gb = img.add(nullptr, sizeof(double) * 4 * k.npp);
+    k.o_Hb = img.add(nullptr, sizeof(double) * mats * (size_t)k.nh_alloc * k.Nb_pad * k.npp);
+    k.o_Gk = img.add(nullptr, sizeof(double) * 4 * k.npp);
+    k.o_Hk = img.add(nullptr, sizeof(double) * (size_t)k.Nhk_pad * k.Nb_pad * k.npp);
+  }
+  mderi_status st;
+  void *dmem;
+  if ((st = ws_get(c, WS_PAIRS, img.bytes.size(), &dmem))) return st;
+  char *base = (char *)dmem;
+  auto dev = [&](size_t off) { return (void *)(base + off); };
+  if ((st = stage_begin(c, meta_bytes))) return st;
+  size_t used = 0;
+  if ((st = stage_copy(c, base, img.bytes.data(), meta_bytes, s, &used))) return st;
+  if ((st = stage_end(c, s))) return st;
+  for (auto &x : C) {
+    const Cls &k = x.second;
+    PairArgs pa{};
+    pa.basis = b->dev;
+    pa.tab = c->tab;
+    pa.npp = k.npp;
+    pa.pp = (const PrimPair *)dev(k.o_pp);
+    pa.la = k.la;
+    pa.lb = k.lb;
+    pa.Nh = k.Nhb;
+    pa.N = k.Nb;
+    pa.Nh_pad = k.nh_alloc;
+    pa.N_pad = k.Nb_pad;
+    pa.deriv = grad ? 1 : 0;
+    pa.order = (const uint32_t *)dev(k.o_order);
+    pa.G = (double *)dev(k.o_Gb);
+    pa.H = (double *)dev(k.o_Hb);
+    HIP_TRY(launch_pairs(pa, s));
+    pa.Nh = k.Nhk;
+    pa.Nh_pad = k.Nhk_pad;
+    pa.ket_sign = 1;
+    pa.deriv = 0;
+    pa.order = nullptr;
+    pa.G = (double *)dev(k.o_Gk);
+    pa.H = (double *)dev(k.o_Hk);
+    HIP_TRY(launch_pairs(pa, s));
+  }
+  for (const Blk &bk : blocks) {
+    const Cls &x = C.at(bk.c1), &y = C.at(bk.c2);
+    Eri4Args ea{};
+    ea.nbra = (int)ps.cls[bk.c1].size();
+    ea.nket = (int)ps.cls[bk.c2].size();
+    ea.L = bk.L;
+    ea.Nhb = x.Nhb;
+    ea.Nhk = y.Nhk;
+    ea.Nb = x.Nb;
+    ea.Nk = y.Nb;
+    ea.Nhb_pad = 16 * bk.npt * bk.nps;
+    ea.Hb_rows = x.nh_alloc;
+    ea.Nhk_pad = y.Nhk_pad;
+    ea.Nb_pad = x.Nb_pad;
+    ea.Nk_pad = y.Nb_pad;
+    ea.npt = bk.npt;
+    ea.nps = bk.nps;
+    ea.nct = y.Nb_pad / 16;
+    ea.nslab = 1;
+    ea.dbuf = bk.dbuf;
+    ea.S1 = bk.S1;
+    ea.S2 = bk.S2;
+    ea.cube_sz = bk.cube_sz;
+    ea.maxpp = bk.maxpp;
+    ea.border = (const uint32_t *)dev(x.o_order);
+    ea.korder = nullptr;
+    ea.bra_off = (const int *)dev(x.o_off);
+    ea.ket_off = (const int *)dev(y.o_off);
+    ea.bra_G = (const double *)dev(x.o_Gb);
+    ea.ket_G = (const double *)dev(y.o_Gk);
+    ea.bra_H = (const double *)dev(x.o_Hb);
+    ea.ket_H = (const double *)dev(y.o_Hk);
+    ea.tab = c->tab;
+    ea.kx = grad ? nullptr : dg.kx;
+    ea.grad = grad ? dg.grad : nullptr;
+    ea.atom = grad ? dg.atom : nullptr;
+    ea.dm = dg.dm;
+    ea.nao = dg.nao;
+    ea.tau = dg.tau;
+    ea.same_list = (!grad && bk.c1 == bk.c2) ? 1 : 0;
+    ea.bra_q = (const double *)dev(x.o_q);
+    ea.ket_q = (const double *)dev(y.o_q);
+    ea.bra_sh = (const int *)dev(x.o_sh);
+    ea.ket_sh = (const int *)dev(y.o_sh);
+    ea.ao_off = b->dev.ao_off;
+    ea.nsa = nsph(x.la);
+    ea.nsb = nsph(x.lb);
+    ea.nsc = nsph(y.la);
+    ea.nsd = nsph(y.lb);
+    if ((st = launch_eri4_timed(c, ea, s))) return st;
+  }
+  return MDERI_OK;
+}
+
+}  // namespace

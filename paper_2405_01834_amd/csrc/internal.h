@@ -94,7 +94,8 @@ struct Eri4Args {
   int Hb_rows;   // rows allocated per bra transform matrix (>= Nhb_pad; its stride)
   int npt;       // p tiles held by a consumer wave
   int nps;       // bra Hermite rows split over nps waves (Nhb_pad = 16 npt nps)
-  int nct;       // ket column tiles (Nk_pad = 16 nct)
+  int nct;       // ket column tiles per workgroup
+  int nslab;     // workgroups per quartet (ket column slabs of nct tiles; Nk_pad >= 16 nct nslab)
   int dbuf;      // double-buffered [r] cube
   int S1, S2;    // [r] cube strides: [r] sits at t*S1 + u*S2 + v
   int cube_sz;   // doubles per cube
@@ -139,11 +140,19 @@ hipError_t launch_schwarz_reduce(int npair, int Nab, const double *D, const int 
 hipError_t launch_symmetrize(int n, const double *in, double *out, hipStream_t s);
 // x[0..n) = 0 with a plain kernel (no memset node, capture-safe).
 hipError_t launch_zero(size_t n, double *x, hipStream_t s);
-// Chooses the consumer register tile npt, the row split nps and the
-// cube buffering of the 4-centre kernel; false if the class does not fit.
-// grad admits 7-tile consumer waves (built only for gradient mode).
-bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int maxpp, bool grad, int *npt, int *nps,
-               int *dbuf);
+// Work split of the fused kernel for one class.
+struct Eri4Plan {
+  int npt;    // bra row tiles per consumer wave
+  int nps;    // bra row parts (waves per column tile)
+  int dbuf;   // double-buffered [r] cube
+  int nct;    // ket column tiles per workgroup
+  int nslab;  // workgroups per quartet (column slabs)
+};
+// Chooses the split of the 4-centre kernel; false if the class does not
+// fit.  grad admits 7-tile consumer waves (built only for gradient mode);
+// slabs admits splitting the ket columns over workgroups (plain output only).
+bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int maxpp, bool grad, bool slabs,
+               Eri4Plan *p);
 // Persistent task-list launch over class blocks that share npt and the
 // producer length bucket of Lmax: d_blocks[nblk] device copies of the blocks'
 // arguments, d_tasks[ntask] = (block, ij + nbra kl); the workgroup has

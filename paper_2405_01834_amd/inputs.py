@@ -10,6 +10,11 @@ Sec. 6, none of which ship with the paper):
   * class_pairs  -- candidate shell pairs of one class for the l-class batches:
                     centres U[0,20)^3, exponents log-uniform in [0.05, 500],
                     coefficients U[0.1, 1], K primitives per shell.
+  * eri3_batch   -- 3-centre task list: `npair` primary pairs with l_a, l_b
+                    uniform in 0..3 and K uniform in 1..5 per shell, `naux`
+                    auxiliary shells with l_P uniform in 0..6 and K=1; centres
+                    U[0,20)^3, exponents log-uniform in [0.05, 500],
+                    coefficients U[0.1, 1].
   * cluster      -- atoms at least 2 bohr apart, drawn uniformly in a box
                     whose side scales as 30 bohr x (natom / 150)^(1/3) (the
                     density of a 150-atom cluster in a 30-bohr box); per atom
@@ -130,3 +135,13 @@ def cluster(seed: int, natom: int, min_dist: float = 2.0, rank: int = 100):
     nao = int(np.sum(2 * ls + 1))
     C = rng.normal(size=(nao, min(rank, nao))) / np.sqrt(nao)
     return sh, atom, pos, C @ C.T
+
+
+def eri3_batch(seed: int, npair: int = 512, naux: int = 512):
+    """Mixed-class 3-centre workload.  Returns (primary shells, aux shells, pairs, aux indices)."""
+    rng = np.random.default_rng(seed)
+    ls = rng.integers(0, 4, 2 * npair)
+    Ks = rng.integers(1, 6, 2 * npair)
+    prim = random_shells(rng, ls, Ks, 20.0, 0.05, 500.0)
+    aux = random_shells(rng, rng.integers(0, 7, naux), 1, 20.0, 0.05, 500.0)
+    return prim, aux, np.arange(2 * npair, dtype=np.int32).reshape(-1, 2), np.arange(naux, dtype=np.int32)

@@ -46,6 +46,12 @@ def eri4_flops(la: int, lb: int, lc: int, ld: int, kbra: int, kket: int) -> floa
     return K * (t["r"][2] + t["pq"][2] + t["ket"][2]) + kbra * t["bra"][2]
 
 
+def eri3_flops(la: int, lb: int, lP: int, kbra: int, kaux: int) -> float:
+    """Model FLOPs of one contracted 3-centre shellset (ab|P): the rows of
+    Table md-scheme with the ket a single shell (l_c = l_P, l_d = 0)."""
+    return eri4_flops(la, lb, lP, 0, kbra, kaux)
+
+
 def eri4_outputs(la: int, lb: int, lc: int, ld: int) -> int:
     return nsph(la) * nsph(lb) * nsph(lc) * nsph(ld)
 

@@ -109,3 +109,31 @@ def test_schwarz_factors_mixed_classes(ctx):
     torch.cuda.synchronize()
     ref = oracle.schwarz(oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, 1), pairs)
     np.testing.assert_allclose(Q.cpu().numpy(), ref, rtol=1e-12, atol=1e-14)
+
+
+HIGH_L = [((5, 5, 5, 5), 1, 3, 2), ((6, 6, 6, 6), 1, 2, 2), ((6, 5, 4, 4), 1, 2, 2), ((5, 5, 5, 5), 2, 1, 2),
+          ((6, 6, 3, 2), 1, 2, 3)]
+
+
+@pytest.mark.parametrize("cls,K,nbra,nket", HIGH_L)
+def test_high_l_parity(ctx, cls, K, nbra, nket):
+    """[hh|hh] and [ii|ii]-type classes, whose quartets the kernel splits into
+    ket-column slabs over several workgroups, against the matrix-form
+    assembly of the oracle's pinned building blocks (tests/ref/md_matrix)."""
+    import torch
+    from tests.ref import md_matrix
+    la, lb, lc, ld = cls
+    rng = np.random.default_rng(1000 + 7 * la + lc + K)
+    n = nbra + nket
+    ls = [la, lb] * nbra + [lc, ld] * nket
+    sh = inputs.random_shells(rng, ls, K, 4.0, 0.1, 30.0)
+    pairs = np.arange(2 * n, dtype=np.int32).reshape(-1, 2)
+    bra, ket = pairs[:nbra], pairs[nbra:]
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    V = ctx.eri4(b, bra, ket)
+    torch.cuda.synchronize()
+    got = V.cpu().numpy()
+    for i, (p0, p1) in enumerate(bra):
+        for k, (q0, q1) in enumerate(ket):
+            ref = md_matrix.shellset(sh, p0, p1, q0, q1)
+            _assert_close(got[i, :, :, k], ref, f"{cls} K={K} quartet ({i},{k})")

@@ -490,3 +490,17 @@ def test_exchange_gradient_finite_difference():
             pm[a, x] -= h
             fd = (energy(pp) - energy(pm)) / (2 * h)
             assert abs(fd - g[a, x]) < 1e-6 * np.max(np.abs(g)), (a, x, fd, g[a, x])
+
+
+def test_matrix_form_reference_matches_oracle():
+    """The matrix-form assembly used for l = 5, 6 parity (tests/ref/md_matrix)
+    equals the sum-form oracle where both run: contracted, mixed classes."""
+    from paper_2405_01834_amd import inputs
+    from tests.ref import md_matrix
+    rng = np.random.default_rng(31)
+    sh = inputs.random_shells(rng, [2, 1, 3, 0, 2, 2], [2, 1, 1, 3, 1, 2], 3.0, 0.1, 20.0)
+    ob = oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, 1)
+    for q in ((0, 1, 2, 3), (4, 5, 0, 2), (2, 0, 5, 1)):
+        ref = oracle.eri4(ob, [q[:2]], [q[2:]])[0, :, :, 0]
+        got = md_matrix.shellset(sh, *q)
+        assert np.max(np.abs(got - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))), q
