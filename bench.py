@@ -185,6 +185,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-wall", type=float, default=2.5, help="oracle wall seconds per class")
     ap.add_argument("--classes", default="", help="subset, e.g. 4:3,2:1 (l:K)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the per-class autotuning of the 4-centre batches")
     ap.add_argument("--eri3", default="graph+autotune", choices=["graph+autotune", "graph", "plain", "off"],
                     help="mode of the 3-centre task-list measurement")
     ap.add_argument("--cluster-atoms", type=int, default=12,
@@ -231,6 +232,14 @@ def main():
             if events is not None:
                 events[i][1].record()
 
+    if not args.no_tune:
+        # autotune: the first call of each class times its work-split variants
+        from paper_2405_01834_amd.mderi import FLAG_AUTOTUNE
+        t = time.perf_counter()
+        for (l, K), (sh, basis, bra, ket, _) in batches.items():
+            ctx.eri4(basis, bra, ket, out=outs[(l, K)], flags=FLAG_AUTOTUNE)
+        torch.cuda.synchronize()
+        log(f"autotune: {time.perf_counter() - t:.1f} s")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -284,7 +293,7 @@ def main():
         "config": {"workload": "4-centre class batches [dd|dd],[ff|ff],[gg|gg] x K=1,3 per shell; 256x256 "
                                "Schwarz-admitted pairs (65,536 quartets) each; 20-bohr cube, exponents "
                                "log-U[0.05,500], coefficients U[0.1,1]", "quartets_per_class": NPAIR * NPAIR,
-                   "classes": [f"{NAMES[l]}K{K}" for l, K in classes]},
+                   "classes": [f"{NAMES[l]}K{K}" for l, K in classes], "autotuned": not args.no_tune},
         "per_class": per_class,
         "roofline": {"bound": "mfma", "kernel": f"eri4_kernel {dom}", "kernel_ms": dom_ms, "achieved": achieved,
                      "peak": model.FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / model.FP64_PEAK_TFLOPS,

@@ -105,6 +105,10 @@ int mderi_basis_nao(mderi_basis_t basis);
  * ab = m_a*N(l_b) + m_b, cd = m_c*N(l_d) + m_d (0-based component indices,
  * N(l) = 2l+1).  V_elems is the capacity of V_dev in doubles and must be at
  * least nbra*Nab*Ncd*nket.  Contracted over all primitive quartets in FP64.
+ * opts->flags may hold MDERI_FLAG_AUTOTUNE: the first call of a class
+ * signature (l_a, l_b, l_c, l_d and the largest primitive-pair counts) times
+ * every work split the kernel supports on this batch, synchronising the
+ * stream, and keeps the fastest in the context for later calls.
  */
 mderi_status mderi_eri4(mderi_ctx_t ctx, mderi_basis_t basis, int nbra, const int32_t *bra_host, int nket,
                         const int32_t *ket_host, double *V_dev, size_t V_elems, const mderi_opts *opts,

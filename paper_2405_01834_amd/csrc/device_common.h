@@ -69,8 +69,8 @@ __device__ __forceinline__ void rr_step(double (&a)[LM + 1], double (&b)[LM + 1]
   b[LM] = 0.0;
 }
 
-// Size (doubles) of the work area of build_R_chains for total L.
-__host__ __device__ constexpr int rr_work_size(int L) { return (L + 1) + (L + 1) * (L + 1) + ntil(L); }
+// Size (doubles) of the work area of build_R_chains_packed for total L.
+__host__ __device__ constexpr int rr_work_size_packed(int L) { return (L + 1) + (L + 1) * (L + 1) + ntil(L); }
 
 // Offset of the (u, v) m-vector in the packed y-stage buffer (pairs ordered
 // by u, then v; the vector of (u, v) has L-u-v+1 entries).
@@ -80,6 +80,9 @@ __device__ __forceinline__ int uv_base(int L, int u, int v) {
   return tet + v * (L - u + 1) - v * (v - 1) / 2;
 }
 
+// Packed-buffer variant of build_R_chains (below) for the long m-vectors of
+// L > 18, where fixed-size slots would not fit in LDS beside the cube: the
+// m-vectors are stored with their valid lengths only (predicated stores).
 // Builds [r]^(0) for all |r| <= L (Eqs. (0m) and (r)) in the LDS cube
 // cube[t*S1 + u*S2 + v] (S2 > L, S1 > L*S2) with a single wave and
 // wave-local synchronisation, so the other waves of the workgroup keep
@@ -89,10 +92,10 @@ __device__ __forceinline__ int uv_base(int L, int u, int v) {
 // one lane per v, x-chains [tuv]^(m) with one lane per (u, v); each lane
 // keeps its m-vector in registers (LM >= L at compile time).
 //   p, P: bra Hermite exponent and centre; q, Q: ket.
-//   work: rr_work_size(L) doubles of LDS; uv: (u | v << 8) of the pairs
+//   work: rr_work_size_packed(L) doubles of LDS; uv: (u | v << 8) of the pairs
 //         u+v <= L ordered by u+v (longest chains first).
 template <int LM>
-__device__ __forceinline__ void build_R_chains(int L, double p, const double *P, double q, const double *Q,
+__device__ __forceinline__ void build_R_chains_packed(int L, double p, const double *P, double q, const double *Q,
                                                double *cube, int S1, int S2, double *work, const uint32_t *uv,
                                                const double *boys, int lane) {
   const double pq = p + q;
@@ -180,6 +183,125 @@ __device__ __forceinline__ void build_R_chains(int L, double p, const double *P,
           rr_step<LM>(b, a, (double)(t + 1), X);
           cc[(t + 2) * S1] = a[0];
         }
+      }
+    }
+  }
+  lds_wave_sync();
+}
+
+// Register length of the producer's m-vectors for total L (the kernels are
+// instantiated for these buckets).
+__host__ __device__ constexpr int rr_lm_bucket(int L) {
+  return L <= 8 ? 8 : L <= 10 ? 10 : L <= 16 ? 16 : L <= 18 ? 18 : L <= 26 ? 26 : -1;
+}
+
+// Size (doubles) of the work area of build_R_chains for total L: [0]^(m),
+// then one (LM+1)-slot m-vector per z level and per (u, v) pair.
+__host__ __device__ constexpr int rr_work_size(int L) {
+  return rr_lm_bucket(L) > 18 ? rr_work_size_packed(L)
+                              : (L + 1) + ((L + 1) + (L + 1) * (L + 2) / 2) * (rr_lm_bucket(L) + 1);
+}
+
+// Builds [r]^(0) for all |r| <= L (Eqs. (0m) and (r)) in the LDS cube
+// cube[t*S1 + u*S2 + v] (offsets additive and injective on |r| <= L) with a
+// single wave and wave-local synchronisation, so the other waves of the
+// workgroup keep issuing matrix-core work meanwhile.  Eq. (r) is applied
+// direction by direction (the same choice of direction as raising the first
+// non-zero component of r): z-chain [00v]^(m) on one lane, y-chains [0uv]^(m)
+// with one lane per v, x-chains [tuv]^(m) with one lane per (u, v); each lane
+// keeps its m-vector in registers (LM = rr_lm_bucket(L) at compile time;
+// LM > 18 uses the packed variant above).  The m-vectors pass between the stages through fixed (LM+1)-slot LDS
+// buffers written and read whole: entries past a vector's valid m range hold
+// finite junk that only ever feeds other junk entries, and no store or load
+// depends on a run-time m bound (no branches in the chains).
+//   p, P: bra Hermite exponent and centre; q, Q: ket.
+//   work: rr_work_size(L) doubles of LDS; uv: (u | v << 8) of the pairs
+//         u+v <= L ordered by u+v (longest chains first).
+template <int LM>
+__device__ __forceinline__ void build_R_chains(int L, double p, const double *P, double q, const double *Q,
+                                               double *cube, int S1, int S2, double *work, const uint32_t *uv,
+                                               const double *boys, int lane) {
+  if constexpr (LM > 18) {
+    build_R_chains_packed<LM>(L, p, P, q, Q, cube, S1, S2, work, uv, boys, lane);
+    return;
+  }
+  constexpr int W = LM + 1;
+  const double pq = p + q;
+  const double rho = p * q / pq;
+  const double X = P[0] - Q[0], Y = P[1] - Q[1], Z = P[2] - Q[2];
+  const double T = rho * (X * X + Y * Y + Z * Z);
+  double *f0 = work;              // [0]^(m), m = 0..L
+  double *zb = f0 + (L + 1);      // [00v]^(m) at v*W + m
+  double *yb = zb + (L + 1) * W;  // [0uv]^(m) at slot(u, v)*W + m, pairs ordered by u, then v
+  if (lane <= L) {
+    double f = 2.0 * 17.493418327624862 / (p * q * sqrt(pq));  // Eq. (0m), 17.49.. = pi^{5/2}
+    const double m2r = -2.0 * rho;
+    for (int j = 0; j < lane; ++j) f *= m2r;
+    f0[lane] = f * boys_m(lane, T, boys);
+  }
+  lds_wave_sync();
+  double a[W], b[W];
+  if (lane == 0) {  // z chain
+#pragma unroll
+    for (int m = 0; m < W; ++m) {
+      a[m] = m <= L ? f0[m] : 0.0;
+      b[m] = 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < W; ++m) zb[m] = a[m];
+    for (int v = 0; v < L; v += 2) {
+      rr_step<LM>(a, b, (double)v, Z);  // b = level v+1
+#pragma unroll
+      for (int m = 0; m < W; ++m) zb[(v + 1) * W + m] = b[m];
+      rr_step<LM>(b, a, (double)(v + 1), Z);  // a = level v+2 (unused when v+2 > L)
+      if (v + 2 <= L) {
+#pragma unroll
+        for (int m = 0; m < W; ++m) zb[(v + 2) * W + m] = a[m];
+      }
+    }
+  }
+  lds_wave_sync();
+  if (lane <= L) {  // y chains, lane = v; (u, v) at slot u (L + 1) - u (u - 1) / 2 + v
+    const int v = lane, M = L - v;
+#pragma unroll
+    for (int m = 0; m < W; ++m) {
+      a[m] = zb[v * W + m];
+      b[m] = 0.0;
+    }
+    int slot = v;
+#pragma unroll
+    for (int m = 0; m < W; ++m) yb[slot * W + m] = a[m];
+    for (int u = 0; u < M; u += 2) {
+      rr_step<LM>(a, b, (double)u, Y);
+      slot += L - u + 1;  // (u+1, v)
+#pragma unroll
+      for (int m = 0; m < W; ++m) yb[slot * W + m] = b[m];
+      rr_step<LM>(b, a, (double)(u + 1), Y);
+      if (u + 1 < M) {
+        slot += L - u;  // (u+2, v)
+#pragma unroll
+        for (int m = 0; m < W; ++m) yb[slot * W + m] = a[m];
+      }
+    }
+  }
+  lds_wave_sync();
+  const int npair = (L + 1) * (L + 2) / 2;
+  for (int pi = lane; pi - lane < npair; pi += 64) {  // x chains, lane = (u, v)
+    if (pi < npair) {
+      const int u = uv[pi] & 0xff, v = (uv[pi] >> 8) & 0xff, M = L - u - v;
+      const int slot = u * (L + 1) - u * (u - 1) / 2 + v;
+#pragma unroll
+      for (int m = 0; m < W; ++m) {
+        a[m] = yb[slot * W + m];
+        b[m] = 0.0;
+      }
+      double *cc = cube + u * S2 + v;
+      cc[0] = a[0];
+      for (int t = 0; t < M; t += 2) {
+        rr_step<LM>(a, b, (double)t, X);
+        cc[(t + 1) * S1] = b[0];
+        rr_step<LM>(b, a, (double)(t + 1), X);
+        if (t + 1 < M) cc[(t + 2) * S1] = a[0];
       }
     }
   }

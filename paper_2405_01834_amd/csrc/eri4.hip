@@ -145,6 +145,9 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
 
   if (wave == ncons) {
     // ---------------- producer: [r] one primitive quartet ahead ----------------
+    // the producer shares its SIMD with consumer waves that keep the matrix
+    // core busy; top issue priority keeps its VALU chains from being starved
+    __builtin_amdgcn_s_setprio(3);
     auto build = [&](int n, double *cube) {
       const int ib = n / nkp, ik = n - ib * nkp;
       const double *Gb = gsh + 4 * ib;
@@ -162,6 +165,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
       __syncthreads();  // [r] of step n published
       if (a.dbuf && n + 1 < nsteps) build(n + 1, ((n + 1) & 1) ? cube1 : cube0);
     }
+    __builtin_amdgcn_s_setprio(0);
   } else if (wave > ncons) {
     // ---------------- surplus waves: barriers only ----------------
     for (int n = 0; n < nsteps; ++n) {
@@ -194,46 +198,55 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
 #pragma unroll
         for (int pt = 0; pt < NPT; ++pt) xacc[pt] = d4{0.0, 0.0, 0.0, 0.0};
       }
-      // ket transform: X[p][cd] += sum_q [p+q] H_ket[q][cd]; the LDS gathers
-      // and the H_ket load of k-step ks+1 are issued before the MFMAs of ks
+      // ket transform: X[p][cd] += sum_q [p+q] H_ket[q][cd].  Two register
+      // sets of LDS gathers ping-pong one k-step ahead of the MFMAs (the
+      // scheduling barriers keep that order); the H_ket values come from
+      // global memory and are loaded two k-steps further ahead (hC, hD) so
+      // an L2 or last-level-cache round trip hides behind two k-steps of
+      // MFMAs.  Prefetch indices are clamped so every load is unconditional;
+      // nks is even (Nhk_pad is a multiple of 8).
       const double *Hk = a.ket_H + (size_t)(kp0 + ik) * a.Nhk_pad * a.Nk_pad;
-      // Two register sets ping-pong: the LDS gathers and the H_ket load of
-      // k-step ks+1 are issued before the MFMAs of ks (scheduling barriers
-      // keep that order); prefetch indices are clamped so every load is
-      // unconditional.  nks is even (Nhk_pad is a multiple of 8).
       double aA[NPT], aB[NPT];
-      double bA, bB;
+      double hA, hB, hC, hD;
+      // ket offsets of the k-steps ks+1, ks+2 sit in registers; those of the
+      // next iteration are read from LDS before this iteration's MFMAs, so
+      // the gathers never wait on a just-issued LDS read
+      int oq1, oq2;
       {
         const int oq = offq[g];
 #pragma unroll
         for (int pt = 0; pt < NPT; ++pt) aA[pt] = cube[offp[pt] + oq];
-        bA = Hk[klo];
+        oq1 = offq[4 * min(1, nks - 1) + g];
+        oq2 = offq[4 * min(2, nks - 1) + g];
+        hA = Hk[klo];
+        hB = Hk[(size_t)min(1, nks - 1) * kstep + klo];
+        hC = Hk[(size_t)min(2, nks - 1) * kstep + klo];
+        hD = Hk[(size_t)min(3, nks - 1) * kstep + klo];
       }
 #pragma unroll 1
       for (int ks = 0; ks < nks; ks += 2) {
-        {
-          const int oq = offq[4 * (ks + 1) + g];
 #pragma unroll
-          for (int pt = 0; pt < NPT; ++pt) aB[pt] = cube[offp[pt] + oq];
-          bB = Hk[(size_t)(ks + 1) * kstep + klo];
-        }
+        for (int pt = 0; pt < NPT; ++pt) aB[pt] = cube[offp[pt] + oq1];
+        const int on1 = offq[4 * min(ks + 3, nks - 1) + g];
+        const int on2 = offq[4 * min(ks + 4, nks - 1) + g];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int pt = 0; pt < NPT; ++pt)
-          xacc[pt] = GRAD ? mfma16x16x4(bA, aA[pt], xacc[pt]) : mfma16x16x4(aA[pt], bA, xacc[pt]);
+          xacc[pt] = GRAD ? mfma16x16x4(hA, aA[pt], xacc[pt]) : mfma16x16x4(aA[pt], hA, xacc[pt]);
         __builtin_amdgcn_sched_barrier(0);
-        {
-          const int ks2 = min(ks + 2, nks - 1);
-          const int oq = offq[4 * ks2 + g];
 #pragma unroll
-          for (int pt = 0; pt < NPT; ++pt) aA[pt] = cube[offp[pt] + oq];
-          bA = Hk[(size_t)ks2 * kstep + klo];
-        }
+        for (int pt = 0; pt < NPT; ++pt) aA[pt] = cube[offp[pt] + oq2];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int pt = 0; pt < NPT; ++pt)
-          xacc[pt] = GRAD ? mfma16x16x4(bB, aB[pt], xacc[pt]) : mfma16x16x4(aB[pt], bB, xacc[pt]);
+          xacc[pt] = GRAD ? mfma16x16x4(hB, aB[pt], xacc[pt]) : mfma16x16x4(aB[pt], hB, xacc[pt]);
         __builtin_amdgcn_sched_barrier(0);
+        oq1 = on1;
+        oq2 = on2;
+        hA = hC;
+        hB = hD;
+        hC = Hk[(size_t)min(ks + 4, nks - 1) * kstep + klo];
+        hD = Hk[(size_t)min(ks + 5, nks - 1) * kstep + klo];
       }
       if (GRAD && ik == nkp - 1) {
         // Gradient mode keeps X transposed (the ket step above swaps the MFMA
@@ -581,7 +594,7 @@ hipError_t launch_eri4(const Eri4Args &a, hipStream_t s) {
   return a.grad ? launch_g<true>(a, s) : launch_g<false>(a, s);
 }
 
-int eri4_lm_bucket(int L) { return L <= 8 ? 8 : L <= 10 ? 10 : L <= 16 ? 16 : L <= 18 ? 18 : L <= 26 ? 26 : -1; }
+int eri4_lm_bucket(int L) { return rr_lm_bucket(L); }
 
 hipError_t launch_eri4_tasks(const Eri4Args *d_blocks, const int2 *d_tasks, int ntask, int npt, int Lmax, int waves,
                              size_t lds, int grid, hipStream_t s) {

@@ -201,6 +201,7 @@ struct mderi_ctx {
   std::vector<TaskPlan *> plans;
   std::map<std::array<int, 6>, std::array<int, 3>> tune;
   hipStream_t cap_stream = nullptr;  // stream used to capture graphs
+  std::vector<hipStream_t> side;     // side streams of concurrent task-list groups
   uint64_t next_serial = 1;
 };
 
@@ -328,6 +329,7 @@ extern "C" void mderi_destroy(mderi_ctx_t c) {
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
   for (TaskPlan *p : c->plans) free_plan(p);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (hipStream_t x : c->side) (void)hipStreamDestroy(x);
   for (auto *v : {&c->ev_used, &c->ev_free})
     for (auto &e : *v) {
       (void)hipEventDestroy(e.first);
@@ -660,8 +662,11 @@ mderi_status launch_eri4_timed(mderi_ctx *c, const Eri4Args &ea, hipStream_t s) 
   return MDERI_OK;
 }
 
+std::vector<std::array<int, 3>> block_candidates(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad,
+                                                 int maxpp);
+
 mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int diag, double *V,
-                             const std::vector<int> *extra_idx, void **d_extra_idx, hipStream_t s) {
+                             const std::vector<int> *extra_idx, void **d_extra_idx, hipStream_t s, int flags = 0) {
   const int nbra = (int)bra.off.size() - 1, nket = (int)ket.off.size() - 1;
   const int la = bra.la, lb = bra.lb, lc = ket.la, ld = ket.one_centre ? 0 : ket.lb;
   const int Lb = la + lb, Lk = lc + ld, L = Lb + Lk;
@@ -680,10 +685,24 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   Eri4Plan pl{};
   if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, false, diag == 0, &pl))
     return fail(MDERI_EUNSUPPORTED, "class (%d%d|%d%d) is beyond the fused kernel's tiles", la, lb, lc, ld);
-  const int npt = pl.npt, nps = pl.nps, dbuf = pl.dbuf;
+  // tile variants: the tuned choice for this class signature, or all of
+  // them timed on this batch when autotuning (single-slab classes only)
+  std::vector<std::array<int, 3>> cands = {{pl.npt, pl.nps, pl.dbuf}};
+  const std::array<int, 6> sig = {la, lb, lc, ket.one_centre ? -1 : ld, maxb, maxk};
+  if (!diag && pl.nslab == 1) {
+    std::vector<std::array<int, 3>> all = block_candidates(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp);
+    auto it = c->tune.find(sig);
+    if (it != c->tune.end() && std::find(all.begin(), all.end(), it->second) != all.end()) cands = {it->second};
+    else if ((flags & MDERI_FLAG_AUTOTUNE) && !all.empty()) cands = all;
+  }
+  int Hb_rows = 0;
+  for (auto &cd : cands) Hb_rows = std::max(Hb_rows, 16 * cd[0] * cd[1]);
+  const int npt = cands[0][0], nps = cands[0][1], dbuf = cands[0][2];
   const int Nhb_pad = 16 * npt * nps, Nb_pad = round16(Nb);
   const int Nk_pad = std::max(round16(Nk), 16 * pl.nct * pl.nslab);  // slabs read whole tiles
-  const std::vector<uint32_t> border = bra_row_order(Lb, S1, S2, Nhb_pad);
+  // bank-spread order over the class's own tiles, zero rows up to Hb_rows
+  std::vector<uint32_t> border = bra_row_order(Lb, S1, S2, round16(Nhb));
+  while ((int)border.size() < Hb_rows) border.push_back(border[0] | kPadRow);
   const std::vector<PrimPair> &ppb = bra.pp, &ppk = ket.pp;
   const std::vector<int> &offb = bra.off, &offk = ket.off;
   mderi_status st;
@@ -695,7 +714,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
       (st = ws_get(c, WS_OFF_KET, sizeof(int) * offk.size(), &d_offk)) ||
       (st = ws_get(c, WS_G_BRA, sizeof(double) * 4 * ppb.size(), &d_Gb)) ||
       (st = ws_get(c, WS_G_KET, sizeof(double) * 4 * ppk.size(), &d_Gk)) ||
-      (st = ws_get(c, WS_H_BRA, sizeof(double) * (size_t)Nhb_pad * Nb_pad * ppb.size(), &d_Hb)) ||
+      (st = ws_get(c, WS_H_BRA, sizeof(double) * (size_t)Hb_rows * Nb_pad * ppb.size(), &d_Hb)) ||
       (st = ws_get(c, WS_H_KET, sizeof(double) * (size_t)Nhk_pad * Nk_pad * ppk.size(), &d_Hk)))
     return st;
   if (!korder.empty() && (st = ws_get(c, WS_KORDER, sizeof(uint32_t) * korder.size(), &d_korder))) return st;
@@ -727,7 +746,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   pa.lb = lb;
   pa.Nh = Nhb;
   pa.N = Nb;
-  pa.Nh_pad = Nhb_pad;
+  pa.Nh_pad = Hb_rows;
   pa.N_pad = Nb_pad;
   pa.ket_sign = 0;
   pa.one_centre = 0;
@@ -762,7 +781,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   ea.Nb = Nb;
   ea.Nk = Nk;
   ea.Nhb_pad = Nhb_pad;
-  ea.Hb_rows = Nhb_pad;
+  ea.Hb_rows = Hb_rows;
   ea.Nhk_pad = Nhk_pad;
   ea.Nb_pad = Nb_pad;
   ea.Nk_pad = Nk_pad;
@@ -786,6 +805,40 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   ea.ket_H = (const double *)d_Hk;
   ea.tab = c->tab;
   ea.V = V;
+  if (cands.size() > 1) {
+    // autotune: time each variant on this batch (the second of two runs)
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    std::array<int, 3> bestc = cands[0];
+    for (auto &cd : cands) {
+      Eri4Args t = ea;
+      t.npt = cd[0];
+      t.nps = cd[1];
+      t.dbuf = cd[2];
+      t.Nhb_pad = 16 * cd[0] * cd[1];
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2; ++rep) {
+        HIP_TRY(hipEventRecord(e0, s));
+        HIP_TRY(launch_eri4(t, s));
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      }
+      if (ms < best) {
+        best = ms;
+        bestc = cd;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->tune[sig] = bestc;
+    ea.npt = bestc[0];
+    ea.nps = bestc[1];
+    ea.dbuf = bestc[2];
+    ea.Nhb_pad = 16 * bestc[0] * bestc[1];
+  }
   return launch_eri4_timed(c, ea, s);
 }
 
@@ -822,8 +875,10 @@ extern "C" mderi_status mderi_eri4(mderi_ctx_t c, mderi_basis_t b, int nbra, con
   const size_t need = (size_t)nbra * nsph(sb.la) * nsph(sb.lb) * nsph(sk.la) * nsph(sk.lb) * nket;
   if (!V) return fail(MDERI_EINVAL, "mderi_eri4: NULL output");
   if (V_elems < need) return fail(MDERI_ESIZE, "mderi_eri4: output holds %zu doubles, needs %zu", V_elems, need);
+  const int flags = opts ? opts->flags : 0;
+  if (flags & ~MDERI_FLAG_AUTOTUNE) return fail(MDERI_EINVAL, "mderi_eri4: unsupported flags 0x%x", flags);
   HIP_TRY(hipSetDevice(c->device));
-  return run_class_batch(c, sb, sk, 0, V, nullptr, nullptr, (hipStream_t)stream);
+  return run_class_batch(c, sb, sk, 0, V, nullptr, nullptr, (hipStream_t)stream, flags);
 }
 
 extern "C" mderi_status mderi_eri3(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t aux, int npair, const int32_t *pairs,
@@ -996,6 +1051,8 @@ extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, const 
 // ---------------------------------------------------------------------------
 // task lists: mixed-class 3-centre batches in persistent launches
 // ---------------------------------------------------------------------------
+constexpr int kSideStreams = 4;  // one per hardware queue of the process
+
 struct TaskGroup {
   int npt, Lmax, waves, grid, ntask;
   size_t lds;
@@ -1011,10 +1068,16 @@ struct TaskPlan {
   std::vector<TaskGroup> groups;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // fork/join events: the groups run concurrently on the context's side
+  // streams (a captured graph keeps them as parallel branches)
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
 };
 
 void free_plan(TaskPlan *p) {
   if (!p) return;
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  for (hipEvent_t e : p->join) (void)hipEventDestroy(e);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->dmem) (void)hipFree(p->dmem);
@@ -1082,11 +1145,40 @@ int group_grid(size_t lds, int waves, long ntask) {
   return (int)std::max(1L, std::min(g, ntask));
 }
 
+// Task-list launches of a plan: one per kernel shape, each on its own side
+// stream after a fork from s and joined back into s, so that small groups
+// fill the chip together instead of one after another.
+mderi_status launch_groups(mderi_ctx *c, TaskPlan *p, hipStream_t s) {
+  if (p->groups.size() == 1) {
+    const TaskGroup &g = p->groups[0];
+    HIP_TRY(launch_eri4_tasks(g.d_blocks, g.d_tasks, g.ntask, g.npt, g.Lmax, g.waves, g.lds, g.grid, s));
+    return MDERI_OK;
+  }
+  for (int i = (int)c->side.size(); i < kSideStreams; ++i) {
+    hipStream_t x;
+    HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    c->side.push_back(x);
+  }
+  if (!p->fork) {
+    HIP_TRY(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
+    p->join.resize(p->groups.size(), nullptr);
+    for (auto &e : p->join) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  HIP_TRY(hipEventRecord(p->fork, s));
+  for (size_t i = 0; i < p->groups.size(); ++i) {
+    const TaskGroup &g = p->groups[i];
+    hipStream_t x = c->side[i % kSideStreams];
+    HIP_TRY(hipStreamWaitEvent(x, p->fork, 0));
+    HIP_TRY(launch_eri4_tasks(g.d_blocks, g.d_tasks, g.ntask, g.npt, g.Lmax, g.waves, g.lds, g.grid, x));
+    HIP_TRY(hipEventRecord(p->join[i], x));
+  }
+  for (hipEvent_t e : p->join) HIP_TRY(hipStreamWaitEvent(s, e, 0));
+  return MDERI_OK;
+}
+
 mderi_status launch_plan(mderi_ctx *c, TaskPlan *p, hipStream_t s) {
   for (const PairArgs &pa : p->pairs) HIP_TRY(launch_pairs(pa, s));
-  for (const TaskGroup &g : p->groups)
-    HIP_TRY(launch_eri4_tasks(g.d_blocks, g.d_tasks, g.ntask, g.npt, g.Lmax, g.waves, g.lds, g.grid, s));
-  return MDERI_OK;
+  return launch_groups(c, p, s);
 }
 
 }  // namespace
@@ -1476,9 +1568,7 @@ extern "C" mderi_status mderi_eri3_batch(mderi_ctx_t c, mderi_basis_t b, mderi_b
     return MDERI_OK;
   }
   // pair data was already produced on s above; run the groups
-  for (const TaskGroup &g : plan->groups)
-    HIP_TRY(launch_eri4_tasks(g.d_blocks, g.d_tasks, g.ntask, g.npt, g.Lmax, g.waves, g.lds, g.grid, s));
-  return MDERI_OK;
+  return launch_groups(c, plan, s);
 }
 
 // ---------------------------------------------------------------------------

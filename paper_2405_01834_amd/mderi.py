@@ -128,7 +128,7 @@ class Context:
     def basis(self, l, nprim, exps, coefs, centers, atom=None, normalize=1) -> "Basis":
         return Basis(self, l, nprim, exps, coefs, centers, atom, normalize)
 
-    def eri4(self, basis: "Basis", bra, ket, out=None, stream=None):
+    def eri4(self, basis: "Basis", bra, ket, out=None, stream=None, flags=0):
         """Class batch (ab|cd) -> torch float64 tensor V[ij, ab, cd, kl] (shape
         (nbra, Nab, Ncd, nket), a Fortran-order view of the flat output)."""
         import torch
@@ -142,9 +142,10 @@ class Context:
         if out is None:
             out = torch.empty(n, dtype=torch.float64, device=f"cuda:{self.device}")
         assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        opts = Opts(0, 1e-12, int(flags))
         _check(load_library().mderi_eri4(self._h, basis._h, len(bra), bra.ctypes.data_as(_ip), len(ket),
-                                         ket.ctypes.data_as(_ip), _vp(out.data_ptr()), out.numel(), None,
-                                         _stream_handle(stream)))
+                                         ket.ctypes.data_as(_ip), _vp(out.data_ptr()), out.numel(),
+                                         ctypes.byref(opts), _stream_handle(stream)))
         return out[:n].view(len(ket), ncd, nab, len(bra)).permute(3, 2, 1, 0)
 
 
