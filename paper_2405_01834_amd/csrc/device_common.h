@@ -31,15 +31,14 @@ __device__ __forceinline__ double boys_m(int m, double T, const double *__restri
     const int i = (int)(T * (double)kBoysGridPerUnit + 0.5);
     const double d = (double)i * (1.0 / kBoysGridPerUnit) - T;
     const double *row = tab + i * kBoysM + m;
-    double acc = row[7];
-    acc = row[6] + acc * d * (1.0 / 7.0);
-    acc = row[5] + acc * d * (1.0 / 6.0);
-    acc = row[4] + acc * d * (1.0 / 5.0);
-    acc = row[3] + acc * d * (1.0 / 4.0);
-    acc = row[2] + acc * d * (1.0 / 3.0);
-    acc = row[1] + acc * d * (1.0 / 2.0);
-    acc = row[0] + acc * d;
-    return acc;
+    // sum_k row[k] d^k / k!, k = 0..7, by Estrin's scheme (dependency depth
+    // 4 instead of 14 for Horner's: this runs beside matrix-core work)
+    const double d2 = d * d, d4 = d2 * d2;
+    const double p01 = fma(row[1], d, row[0]);
+    const double p23 = fma(row[3] * (1.0 / 6.0), d, row[2] * 0.5);
+    const double p45 = fma(row[5] * (1.0 / 120.0), d, row[4] * (1.0 / 24.0));
+    const double p67 = fma(row[7] * (1.0 / 5040.0), d, row[6] * (1.0 / 720.0));
+    return fma(fma(p67, d2, p45), d4, fma(p23, d2, p01));
   }
   const double emT = exp(-T);
   const double o2T = 0.5 / T;
@@ -48,9 +47,29 @@ __device__ __forceinline__ double boys_m(int m, double T, const double *__restri
   return f;
 }
 
+// x^n for 0 <= n < 32 by binary exponentiation (dependency depth 5 instead of n).
+__device__ __forceinline__ double ipow_small(double x, int n) {
+  double r = 1.0;
+#pragma unroll
+  for (int bit = 0; bit < 5; ++bit) {
+    r *= (n & 1) ? x : 1.0;
+    x *= x;
+    n >>= 1;
+  }
+  return r;
+}
+
 // Index of (t, u, .) inside the Hermite functions of total degree n, ordered
 // t descending then u descending.
 __device__ __forceinline__ int deg_index(int n, int t, int u) { return ((n - t) * (n - t + 1) >> 1) + (n - t - u); }
+
+// Value of the next lane (lane i gets lane i+1, lane 63 gets 0) by a DPP
+// wavefront shift (gfx9 wave_shl:1): a VALU move, no LDS round trip.
+__device__ __forceinline__ double lane_next(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
 
 // Makes this wave's LDS writes visible to its other lanes before they read.
 __device__ __forceinline__ void lds_wave_sync() {
@@ -107,8 +126,7 @@ __device__ __forceinline__ void build_R_chains_packed(int L, double p, const dou
   double *yb = zb + (L + 1) * (L + 1);  // [0uv]^(m) at uv_base(u, v) + m
   if (lane <= L) {
     double f = 2.0 * 17.493418327624862 / (p * q * sqrt(pq));  // Eq. (0m), 17.49.. = pi^{5/2}
-    const double m2r = -2.0 * rho;
-    for (int j = 0; j < lane; ++j) f *= m2r;
+    f *= ipow_small(-2.0 * rho, lane);
     f0[lane] = f * boys_m(lane, T, boys);
   }
   lds_wave_sync();
@@ -235,33 +253,28 @@ __device__ __forceinline__ void build_R_chains(int L, double p, const double *P,
   double *yb = zb + (L + 1) * W;  // [0uv]^(m) at slot(u, v)*W + m, pairs ordered by u, then v
   if (lane <= L) {
     double f = 2.0 * 17.493418327624862 / (p * q * sqrt(pq));  // Eq. (0m), 17.49.. = pi^{5/2}
-    const double m2r = -2.0 * rho;
-    for (int j = 0; j < lane; ++j) f *= m2r;
+    f *= ipow_small(-2.0 * rho, lane);
     f0[lane] = f * boys_m(lane, T, boys);
   }
   lds_wave_sync();
-  double a[W], b[W];
-  if (lane == 0) {  // z chain
-#pragma unroll
-    for (int m = 0; m < W; ++m) {
-      a[m] = m <= L ? f0[m] : 0.0;
-      b[m] = 0.0;
-    }
-#pragma unroll
-    for (int m = 0; m < W; ++m) zb[m] = a[m];
-    for (int v = 0; v < L; v += 2) {
-      rr_step<LM>(a, b, (double)v, Z);  // b = level v+1
-#pragma unroll
-      for (int m = 0; m < W; ++m) zb[(v + 1) * W + m] = b[m];
-      rr_step<LM>(b, a, (double)(v + 1), Z);  // a = level v+2 (unused when v+2 > L)
-      if (v + 2 <= L) {
-#pragma unroll
-        for (int m = 0; m < W; ++m) zb[(v + 2) * W + m] = a[m];
-      }
+  // z chain with one lane per m: level v+1 from levels v and v-1 at m+1,
+  // taken from the next lane by a DPP move (Eq. (r) along z)
+  {
+    double za = lane <= L ? f0[lane] : 0.0, zp = 0.0;
+    if (lane <= L) zb[lane] = za;
+    for (int v = 0; v < L; ++v) {
+      const double an = lane_next(za), pn = lane_next(zp);
+      zp = za;
+      za = fma(Z, an, (double)v * pn);
+      if (lane <= L) zb[(v + 1) * W + lane] = za;
     }
   }
   lds_wave_sync();
-  if (lane <= L) {  // y chains, lane = v; (u, v) at slot u (L + 1) - u (u - 1) / 2 + v
+  // y chains, one lane per v with the m-vector in registers (under
+  // matrix-core contention the cost follows the instruction count, which
+  // this form keeps lowest); (u, v) lands in slot u (L + 1) - u (u - 1) / 2 + v
+  double a[W], b[W];
+  if (lane <= L) {
     const int v = lane, M = L - v;
 #pragma unroll
     for (int m = 0; m < W; ++m) {
@@ -287,6 +300,9 @@ __device__ __forceinline__ void build_R_chains(int L, double p, const double *P,
   lds_wave_sync();
   const int npair = (L + 1) * (L + 2) / 2;
   for (int pi = lane; pi - lane < npair; pi += 64) {  // x chains, lane = (u, v)
+    // longest chain of this pass (pairs are ordered by u+v, so it is the
+    // pass's first): levels beyond it are skipped by the whole wave
+    const int Mmax = L - (int)((uv[pi - lane] & 0xff) + ((uv[pi - lane] >> 8) & 0xff));
     if (pi < npair) {
       const int u = uv[pi] & 0xff, v = (uv[pi] >> 8) & 0xff, M = L - u - v;
       const int slot = u * (L + 1) - u * (u - 1) / 2 + v;
@@ -297,11 +313,21 @@ __device__ __forceinline__ void build_R_chains(int L, double p, const double *P,
       }
       double *cc = cube + u * S2 + v;
       cc[0] = a[0];
-      for (int t = 0; t < M; t += 2) {
-        rr_step<LM>(a, b, (double)t, X);
-        cc[(t + 1) * S1] = b[0];
-        rr_step<LM>(b, a, (double)(t + 1), X);
-        if (t + 1 < M) cc[(t + 2) * S1] = a[0];
+      // level t+1 is valid for m <= M - t - 1 <= LM - t - 1, so the fully
+      // unrolled levels shrink (half the FP64 work of full-length steps; on
+      // this chip vector FP64 shares the datapath with the consumers' FP64
+      // matrix work)
+#pragma unroll
+      for (int t = 0; t < LM; t += 2) {
+        if (t >= Mmax) break;
+#pragma unroll
+        for (int m = 0; m < LM - t; ++m) b[m] = fma(X, a[m + 1], (double)t * b[m + 1]);
+        if (t < M) cc[(t + 1) * S1] = b[0];
+        if (t + 1 < LM) {
+#pragma unroll
+          for (int m = 0; m < LM - t - 1; ++m) a[m] = fma(X, b[m + 1], (double)(t + 1) * a[m + 1]);
+          if (t + 1 < M) cc[(t + 2) * S1] = a[0];
+        }
       }
     }
   }
