@@ -53,12 +53,18 @@ typedef enum {
 typedef struct mderi_ctx *mderi_ctx_t;
 typedef struct mderi_basis *mderi_basis_t;
 
+/* Arithmetic of the Hermite->solid transforms (mderi_opts.precision). */
+#define MDERI_FP64 0       /* everything in FP64 */
+#define MDERI_SPLIT_BF16 1 /* bra transform on the BF16 matrix cores with operands split into 7-bit
+                              integer slices (see mderi_eri4); all else FP64 */
+
 /* Options shared by the compute calls; NULL means defaults. */
 typedef struct {
-  int precision;      /* 0 = FP64 (only value supported by the FP64 entry points) */
+  int precision;      /* MDERI_FP64 (all entry points) or MDERI_SPLIT_BF16 (mderi_eri4) */
   double schwarz_tau; /* screening threshold for the K build (default 1e-12) */
-  int flags;          /* MDERI_FLAG_* (used by mderi_eri3_batch) */
-  int reserved[3];
+  int flags;          /* MDERI_FLAG_* (mderi_eri3_batch; mderi_eri4 takes MDERI_FLAG_AUTOTUNE) */
+  int split_slices;   /* MDERI_SPLIT_BF16: 7-bit slices per operand, 5..7 (0 = default 6) */
+  int reserved[2];
 } mderi_opts;
 
 #define MDERI_FLAG_GRAPH 1    /* capture the call's launches in a hipGraph, replay it on identical calls */
@@ -105,6 +111,16 @@ int mderi_basis_nao(mderi_basis_t basis);
  * ab = m_a*N(l_b) + m_b, cd = m_c*N(l_d) + m_d (0-based component indices,
  * N(l) = 2l+1).  V_elems is the capacity of V_dev in doubles and must be at
  * least nbra*Nab*Ncd*nket.  Contracted over all primitive quartets in FP64.
+ * opts->precision = MDERI_SPLIT_BF16 runs the bra transform (Eq.
+ * bra-from-hermite) on the BF16 matrix cores: the rows of H_bra and [p|ket]
+ * are balanced by powers of two, both operands are scaled by a power of two
+ * per column and split into S = opts->split_slices 7-bit integer slices;
+ * the slice products are exact in BF16, their FP32 sums over 32-row blocks
+ * are exact, products of total order above S+1 are dropped (7S-bit
+ * operands) and the rest is combined in FP64.  Boys, R, the ket transform
+ * and the accumulation of V stay FP64.  The error per shellset relative to
+ * its largest element grows with the cancellation in the bra sum (see the
+ * split-precision tests for measured bounds per class and S).
  * opts->flags may hold MDERI_FLAG_AUTOTUNE: the first call of a class
  * signature (l_a, l_b, l_c, l_d and the largest primitive-pair counts) times
  * every work split the kernel supports on this batch, synchronising the

@@ -19,6 +19,23 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+// D(16x16, FP32) += A(16x32) * B(32x16) in BF16 on the matrix cores.  Operand
+// layout (wave64): lane l holds A[l % 16][8 (l / 16) + e] and
+// B[8 (l / 16) + e][l % 16] for e = 0..7; register r of lane l holds
+// D[4 (l / 16) + r][l % 16].
+__device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Eight consecutive BF16 values (16-byte aligned) as an MFMA operand.
+__device__ __forceinline__ bf8 load_bf8(const uint16_t *p) {
+  return __builtin_bit_cast(bf8, *(const u4 *)p);
+}
+
 // Boys function F_m(T), Eq. (boys), for one m per lane.
 //  T < 40: 8-term Taylor expansion about the nearest grid point T_i (spacing
 //          1/16, |T - T_i| <= 1/32) using dF_m/dT = -F_{m+1}:

@@ -81,8 +81,11 @@ __device__ __forceinline__ void kdigest(const Eri4Args &a, const double *v, int 
 // One shell quartet (ij, kl) by the whole workgroup.  Waves beyond the
 // block's nct * nps consumers and its producer (a task-list launch sizes the
 // workgroup for its largest block) only take part in the barriers.
-template <int NPT, int LM, bool GRAD>
+template <int NPT, int LM, int MODE>
 __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, int slab, double *smem) {
+  constexpr bool GRAD = MODE == 1;   // gradient mode (see the derivative step)
+  constexpr bool SPLIT = MODE >= 2;  // split-precision bra transform with S = MODE + 3 slices
+  constexpr int S = MODE + 3;
   const int L = a.L;
   // column slab: this workgroup owns ket columns [c0, c0 + 16 nct); V keeps
   // only those columns (row stride vstride) when the quartet is split
@@ -291,7 +294,78 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
               }
           }
         }
-      } else if (ik == nkp - 1) {
+      } else if (SPLIT && ik == nkp - 1) {
+        // Split-precision bra transform on the BF16 matrix cores.  After row
+        // balancing, with a power-of-two exponent per column of X over this
+        // wave's rows (fx)
+        // and per column ab of H over all rows (pair data), both scaled
+        // operands are sums of S slices of 7-bit integers,
+        // X 2^-fx = sum_j x_j 128^-j, H 2^-E = sum_i h_i 128^-i.  Every
+        // BF16 product h_i x_j is an integer of at most 2^14 and the FP32
+        // accumulation of one level i+j over a 32-row block stays below
+        // 2^24, so the matrix cores add exactly; levels i+j > S+1 are
+        // dropped (35-bit operands), the levels are combined in FP64.
+        // rows balanced with the pair data's row exponents (X row p times
+        // 2^k_p, H row p times 2^-k_p: products unchanged)
+        const int *Kr = a.bra_Hrow + (size_t)(bp0 + ib) * a.Hs_rows + ph * NPT * 16 + g;
+        double mx = 0.0;
+#pragma unroll
+        for (int pt = 0; pt < NPT; ++pt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            xacc[pt][r] = ldexp(xacc[pt][r], Kr[pt * 16 + 4 * r]);
+            mx = fmax(mx, fabs(xacc[pt][r]));
+          }
+        mx = fmax(mx, __shfl_xor(mx, 16));
+        mx = fmax(mx, __shfl_xor(mx, 32));
+        int fx = 0;
+        if (mx > 0.0) (void)frexp(mx, &fx);
+        // B operands: k slot 8 g + e of block b = row 4 (e % 4) + g of tile
+        // 2 b + e / 4; one 32-row block at a time (slices of one block live)
+        constexpr int NB = NPT / 2;
+        const uint16_t *Hs =
+            a.bra_Hs + (size_t)(bp0 + ib) * S * a.Nb_pad * a.Hs_rows + (size_t)(ph * NB) * 32 + 8 * g;
+        const int *Ex = a.bra_Hexp + (size_t)(bp0 + ib) * a.Nb_pad;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          bf8 xb[S];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            double rr = ldexp(xacc[2 * b + (e >> 2)][e & 3], -fx);
+#pragma unroll
+            for (int sl = 0; sl < S; ++sl) {
+              const double v = rr * 128.0;
+              const double t = rint(v);
+              rr = v - t;
+              xb[sl][e] = (__bf16)(float)t;
+            }
+          }
+#pragma unroll 1
+          for (int at = 0; at < nat; ++at) {
+            f4 acc[S];
+#pragma unroll
+            for (int l = 0; l < S; ++l) acc[l] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+              const bf8 ha = load_bf8(Hs + ((size_t)i * a.Nb_pad + at * 16 + c) * a.Hs_rows + b * 32);
+#pragma unroll
+              for (int j = 0; i + j < S; ++j) acc[i + j] = mfma_bf16(ha, xb[j], acc[i + j]);
+            }
+            if (col < a.Nk) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int ab = at * 16 + 4 * g + r;  // D[4 g + r][c] in register r
+                if (ab < a.Nb) {
+                  double v = 0.0;
+#pragma unroll
+                  for (int l = S - 1; l >= 0; --l) v = fma(v, 1.0 / 128.0, (double)acc[l][r]);
+                  atomicAdd(&vsh[ab * vstride + (col - c0)], ldexp(v, Ex[ab] + fx - 14));  // level l: 128^-(l+2)
+                }
+              }
+            }
+          }
+        }
+      } else if (!SPLIT && ik == nkp - 1) {
         // bra transform: V[ab][cd] += sum_p H_bra[p][ab] X[p][cd], one ab tile
         // at a time (two accumulators), summed into the LDS copy of V
         const double *Hb = a.bra_H + (size_t)(bp0 + ib) * a.Hb_rows * a.Nb_pad + (size_t)ph * NPT * 16 * a.Nb_pad;
@@ -376,8 +450,9 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
 }
 
 // One workgroup per quartet of one class batch.
-template <int NPT, int LM, bool GRAD>
+template <int NPT, int LM, int MODE>
 __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
+  constexpr bool GRAD = MODE == 1;
   extern __shared__ double smem[];
   const long G = (a.diag ? (long)a.nbra : (long)a.nbra * a.nket) * a.nslab;
   const long v0 = xcd_remap(blockIdx.x, G);
@@ -390,7 +465,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
     if (a.bra_q[ij] * a.ket_q[kl] < a.tau || (a.same_list && ij < kl)) return;
   }
   if (GRAD && a.bra_q[ij] * a.ket_q[kl] < a.tau) return;
-  eri4_quartet<NPT, LM, GRAD>(a, ij, kl, slab, smem);
+  eri4_quartet<NPT, LM, MODE>(a, ij, kl, slab, smem);
 }
 
 // Persistent task-list kernel: the workgroups stride over tasks (block id,
@@ -417,23 +492,23 @@ __global__ void __launch_bounds__(64 * kMaxWaves)
 #endif
     const int ij = q % a.nbra, kl = q / a.nbra;
     __syncthreads();  // the previous task is done with LDS
-    eri4_quartet<NPT, LM, false>(a, ij, kl, 0, smem);
+    eri4_quartet<NPT, LM, 0>(a, ij, kl, 0, smem);
   }
 }
 
-template <int NPT, int LM, bool GRAD>
+template <int NPT, int LM, int MODE>
 hipError_t launch_t(const Eri4Args &a, hipStream_t s) {
   const int waves = a.nct * a.nps + 1;
   const size_t lds = eri4_lds_bytes(a);
   const long G = (a.diag ? (long)a.nbra : (long)a.nbra * a.nket) * a.nslab;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)eri4_kernel<NPT, LM, GRAD>,
+    hipError_t e = hipFuncSetAttribute((const void *)eri4_kernel<NPT, LM, MODE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((eri4_kernel<NPT, LM, GRAD>), dim3((unsigned)G), dim3(64 * waves), lds, s, a);
+  hipLaunchKernelGGL((eri4_kernel<NPT, LM, MODE>), dim3((unsigned)G), dim3(64 * waves), lds, s, a);
   return hipGetLastError();
 }
 
@@ -536,18 +611,27 @@ bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int max
   return false;
 }
 
-template <int LM, bool GRAD>
+template <int LM, int MODE>
 hipError_t launch_lm(const Eri4Args &a, hipStream_t s) {
-  switch (a.npt) {
-    case 1: return launch_t<1, LM, GRAD>(a, s);
-    case 2: return launch_t<2, LM, GRAD>(a, s);
-    case 3: return launch_t<3, LM, GRAD>(a, s);
-    case 4: return launch_t<4, LM, GRAD>(a, s);
-    case 6: return launch_t<6, LM, GRAD>(a, s);
-    case 7:
-      if constexpr (GRAD) return launch_t<7, LM, GRAD>(a, s);
-      return hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
+  if constexpr (MODE >= 2) {  // split precision pairs row tiles: even npt only
+    switch (a.npt) {
+      case 2: return launch_t<2, LM, MODE>(a, s);
+      case 4: return launch_t<4, LM, MODE>(a, s);
+      case 6: return launch_t<6, LM, MODE>(a, s);
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (a.npt) {
+      case 1: return launch_t<1, LM, MODE>(a, s);
+      case 2: return launch_t<2, LM, MODE>(a, s);
+      case 3: return launch_t<3, LM, MODE>(a, s);
+      case 4: return launch_t<4, LM, MODE>(a, s);
+      case 6: return launch_t<6, LM, MODE>(a, s);
+      case 7:
+        if constexpr (MODE == 1) return launch_t<7, LM, MODE>(a, s);
+        return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
   }
 }
 
@@ -577,21 +661,30 @@ hipError_t launch_tasks_lm(const Eri4Args *b, const int2 *t, int n, int npt, int
   }
 }
 
-template <bool GRAD>
+template <int MODE>
 hipError_t launch_g(const Eri4Args &a, hipStream_t s) {
   // register length of the producer's m-vectors: smallest bound >= L
-  if (a.L <= 8) return launch_lm<8, GRAD>(a, s);
-  if (a.L <= 10) return launch_lm<10, GRAD>(a, s);
-  if (a.L <= 16) return launch_lm<16, GRAD>(a, s);
-  if (a.L <= 18) return launch_lm<18, GRAD>(a, s);
-  if (a.L <= 26) return launch_lm<26, GRAD>(a, s);
+  if (a.L <= 8) return launch_lm<8, MODE>(a, s);
+  if (a.L <= 10) return launch_lm<10, MODE>(a, s);
+  if (a.L <= 16) return launch_lm<16, MODE>(a, s);
+  if (a.L <= 18) return launch_lm<18, MODE>(a, s);
+  if (a.L <= 26) return launch_lm<26, MODE>(a, s);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_eri4(const Eri4Args &a, hipStream_t s) {
   if (a.nbra <= 0 || a.nket <= 0) return hipSuccess;
   if (a.nct * a.nps + 1 > kMaxWaves) return hipErrorInvalidValue;
-  return a.grad ? launch_g<true>(a, s) : launch_g<false>(a, s);
+  if (a.grad) return launch_g<1>(a, s);
+  if (a.bra_Hs) {
+    switch (a.split) {  // mode = slices - 3
+      case 5: return launch_g<2>(a, s);
+      case 6: return launch_g<3>(a, s);
+      case 7: return launch_g<4>(a, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return launch_g<0>(a, s);
 }
 
 int eri4_lm_bucket(int L) { return rr_lm_bucket(L); }

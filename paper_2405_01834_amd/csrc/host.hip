@@ -176,7 +176,7 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 // ---------------------------------------------------------------------------
 enum WsSlot {
   WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_ORDER,
-  WS_KORDER, WS_KTMP, WS_QALL, WS_PAIRS, WS_COUNT
+  WS_KORDER, WS_KTMP, WS_QALL, WS_PAIRS, WS_HS, WS_HEXP, WS_HROW, WS_COUNT
 };
 
 struct TaskPlan;
@@ -666,7 +666,8 @@ std::vector<std::array<int, 3>> block_candidates(int Nhb, int Nb, int Nk, int L,
                                                  int maxpp);
 
 mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int diag, double *V,
-                             const std::vector<int> *extra_idx, void **d_extra_idx, hipStream_t s, int flags = 0) {
+                             const std::vector<int> *extra_idx, void **d_extra_idx, hipStream_t s, int flags = 0,
+                             int precision = 0, int slices = kSplitDefault) {
   const int nbra = (int)bra.off.size() - 1, nket = (int)ket.off.size() - 1;
   const int la = bra.la, lb = bra.lb, lc = ket.la, ld = ket.one_centre ? 0 : ket.lb;
   const int Lb = la + lb, Lk = lc + ld, L = Lb + Lk;
@@ -687,9 +688,11 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
     return fail(MDERI_EUNSUPPORTED, "class (%d%d|%d%d) is beyond the fused kernel's tiles", la, lb, lc, ld);
   // tile variants: the tuned choice for this class signature, or all of
   // them timed on this batch when autotuning (single-slab classes only)
+  const bool split = precision == MDERI_SPLIT_BF16;
+  if (split && (pl.npt & 1)) ++pl.npt;  // the BF16 operands pair 16-row tiles
   std::vector<std::array<int, 3>> cands = {{pl.npt, pl.nps, pl.dbuf}};
   const std::array<int, 6> sig = {la, lb, lc, ket.one_centre ? -1 : ld, maxb, maxk};
-  if (!diag && pl.nslab == 1) {
+  if (!diag && pl.nslab == 1 && !split) {
     std::vector<std::array<int, 3>> all = block_candidates(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp);
     auto it = c->tune.find(sig);
     if (it != c->tune.end() && std::find(all.begin(), all.end(), it->second) != all.end()) cands = {it->second};
@@ -697,6 +700,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   }
   int Hb_rows = 0;
   for (auto &cd : cands) Hb_rows = std::max(Hb_rows, 16 * cd[0] * cd[1]);
+  const int Hs_rows = (Hb_rows + 31) & ~31;
   const int npt = cands[0][0], nps = cands[0][1], dbuf = cands[0][2];
   const int Nhb_pad = 16 * npt * nps, Nb_pad = round16(Nb);
   const int Nk_pad = std::max(round16(Nk), 16 * pl.nct * pl.nslab);  // slabs read whole tiles
@@ -718,6 +722,11 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
       (st = ws_get(c, WS_H_KET, sizeof(double) * (size_t)Nhk_pad * Nk_pad * ppk.size(), &d_Hk)))
     return st;
   if (!korder.empty() && (st = ws_get(c, WS_KORDER, sizeof(uint32_t) * korder.size(), &d_korder))) return st;
+  void *d_Hs = nullptr, *d_Hexp = nullptr, *d_Hrow = nullptr;
+  if (split && ((st = ws_get(c, WS_HS, sizeof(uint16_t) * slices * (size_t)Nb_pad * Hs_rows * ppb.size(), &d_Hs)) ||
+                (st = ws_get(c, WS_HEXP, sizeof(int) * (size_t)Nb_pad * ppb.size(), &d_Hexp)) ||
+                (st = ws_get(c, WS_HROW, sizeof(int) * (size_t)Hs_rows * ppb.size(), &d_Hrow))))
+    return st;
   if (extra_idx && (st = ws_get(c, WS_IDX, sizeof(int) * extra_idx->size(), d_extra_idx))) return st;
   const size_t stage_need = sizeof(PrimPair) * (ppb.size() + ppk.size()) + sizeof(int) * (offb.size() + offk.size()) +
                             (extra_idx ? sizeof(int) * extra_idx->size() : 0) + sizeof(uint32_t) * border.size() +
@@ -751,6 +760,11 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   pa.ket_sign = 0;
   pa.one_centre = 0;
   pa.deriv = 0;
+  pa.split = split ? slices : 0;
+  pa.Hs = (uint16_t *)d_Hs;
+  pa.Hexp = (int *)d_Hexp;
+  pa.Hrow = (int *)d_Hrow;
+  pa.Hs_rows = Hs_rows;
   pa.order = (const uint32_t *)d_border;
   pa.G = (double *)d_Gb;
   pa.H = (double *)d_Hb;
@@ -767,6 +781,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   pa.ket_sign = 1;
   pa.one_centre = ket.one_centre ? 1 : 0;
   pa.deriv = 0;
+  pa.split = 0;
   pa.order = (const uint32_t *)d_korder;
   pa.G = (double *)d_Gk;
   pa.H = (double *)d_Hk;
@@ -805,6 +820,13 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   ea.ket_H = (const double *)d_Hk;
   ea.tab = c->tab;
   ea.V = V;
+  if (split) {
+    ea.bra_Hs = (const uint16_t *)d_Hs;
+    ea.bra_Hexp = (const int *)d_Hexp;
+    ea.bra_Hrow = (const int *)d_Hrow;
+    ea.Hs_rows = Hs_rows;
+    ea.split = slices;
+  }
   if (cands.size() > 1) {
     // autotune: time each variant on this batch (the second of two runs)
     hipEvent_t e0, e1;
@@ -867,7 +889,12 @@ extern "C" mderi_status mderi_eri4(mderi_ctx_t c, mderi_basis_t b, int nbra, con
                                    void *stream) {
   if (!c || !b) return fail(MDERI_EINVAL, "mderi_eri4: NULL context or basis");
   if (b->ctx != c) return fail(MDERI_EINVAL, "mderi_eri4: basis belongs to another context");
-  if (opts && opts->precision != 0) return fail(MDERI_EUNSUPPORTED, "mderi_eri4: precision %d", opts->precision);
+  const int precision = opts ? opts->precision : 0;
+  if (precision != MDERI_FP64 && precision != MDERI_SPLIT_BF16)
+    return fail(MDERI_EUNSUPPORTED, "mderi_eri4: precision %d", precision);
+  const int slices = (opts && opts->split_slices) ? opts->split_slices : kSplitDefault;
+  if (precision == MDERI_SPLIT_BF16 && (slices < kSplitMin || slices > kSplitMax))
+    return fail(MDERI_EINVAL, "mderi_eri4: split_slices %d outside [%d,%d]", slices, kSplitMin, kSplitMax);
   Side sb{b, 0, 0, false, {}, {}}, sk{b, 0, 0, false, {}, {}};
   mderi_status st;
   if ((st = expand_pairs(b, nbra, bra, "bra", &sb.la, &sb.lb, sb.pp, sb.off)) != MDERI_OK) return st;
@@ -878,7 +905,7 @@ extern "C" mderi_status mderi_eri4(mderi_ctx_t c, mderi_basis_t b, int nbra, con
   const int flags = opts ? opts->flags : 0;
   if (flags & ~MDERI_FLAG_AUTOTUNE) return fail(MDERI_EINVAL, "mderi_eri4: unsupported flags 0x%x", flags);
   HIP_TRY(hipSetDevice(c->device));
-  return run_class_batch(c, sb, sk, 0, V, nullptr, nullptr, (hipStream_t)stream, flags);
+  return run_class_batch(c, sb, sk, 0, V, nullptr, nullptr, (hipStream_t)stream, flags, precision, slices);
 }
 
 extern "C" mderi_status mderi_eri3(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t aux, int npair, const int32_t *pairs,

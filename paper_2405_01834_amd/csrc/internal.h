@@ -11,6 +11,7 @@ namespace mderi {
 
 constexpr int kLmax = MDERI_LMAX;       // largest shell l
 constexpr int kLshell = kLmax + 1;      // l+1 shells appear in derivatives
+constexpr int kSplitMin = 5, kSplitMax = 7, kSplitDefault = 6;  // 7-bit slices per operand in split precision
 constexpr int kLtotMax = 4 * kLshell;   // largest total L = la+lb+lc+ld
 constexpr int kNtilMax = (kLtotMax + 1) * (kLtotMax + 2) * (kLtotMax + 3) / 6;
 
@@ -79,6 +80,14 @@ struct PairArgs {
   int one_centre;  // single shells (lb ignored): Eqs. (E1rr)-(E1-aa), zeta_p = zeta_a, P = A
   int deriv;       // write the six centre-derivative matrices d/dA_x, d/dB_x (see pairs.hip)
                    // transposed, H[6][N_pad][Nh_pad]; rows then span |p| <= la+lb+1
+  // split precision: also write the matrix as `split` BF16 slices of
+  // 7-bit integers relative to a power-of-two exponent per column ab (see
+  // pairs.hip), rows in the k order of the BF16 matrix-core operand
+  int split;      // 0, or the number of slices (kSplitMin..kSplitMax)
+  uint16_t *Hs;   // [npp][split][N_pad][Hs_rows] (BF16 bit patterns)
+  int *Hexp;      // [npp][N_pad] column exponents
+  int *Hrow;      // [npp][Hs_rows] row balancing exponents
+  int Hs_rows;    // Nh_pad rounded up to 32
   const uint32_t *order;  // row order (Nh_pad packed (t,u,v); kPadRow set = zero row), or
                           // nullptr for the global Hermite order with Nh real rows
   Tables tab;
@@ -127,6 +136,12 @@ struct Eri4Args {
   const int *bra_off, *ket_off;  // [n+1] primitive-pair offsets per shell pair
   const double *bra_G, *ket_G;
   const double *bra_H, *ket_H;
+  // split-precision bra transform (precision 1): BF16 slices of the bra
+  // matrices and their per-ab exponents (PairArgs::Hs, Hexp)
+  const uint16_t *bra_Hs;
+  const int *bra_Hexp, *bra_Hrow;
+  int Hs_rows;
+  int split;     // number of slices (kernel mode follows it)
   Tables tab;
   double *V;
 };

@@ -145,6 +145,55 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
     }
     H[e] = h;
   }
+  if (!a.split) return;
+  // Split precision.  Rows are balanced first: row p of H is scaled by
+  // 2^-k_p (k_p: exponent of its largest |H[p][ab]|) and the fused kernel
+  // scales row p of [p|ket] by 2^+k_p, which leaves the products unchanged
+  // and exact.  Then per column ab an exponent E with |H~[p][ab]| < 2^E over
+  // all rows, and H~ 2^-E = sum_s h_s 128^-s with integers |h_1| <= 128 and
+  // |h_s| <= 64 (s > 1), each exact in BF16.  Slices are stored in the k
+  // order of the BF16 16x16x32 operand: position 32 b + 8 g + e of a column
+  // holds row 32 b + 16 (e / 4) + 4 (e % 4) + g (two 16-row tiles per block;
+  // lane group g of the consumer wave holds rows 4 r + g of each tile).
+  __syncthreads();  // H of this primitive pair written by the whole workgroup
+  int *Kr = a.Hrow + (size_t)pp * a.Hs_rows;
+  for (int ph = tid; ph < a.Hs_rows; ph += kPairThreads) {
+    double mx = 0.0;
+    if (ph < a.Nh_pad)
+      for (int ab = 0; ab < a.N_pad; ++ab) mx = fmax(mx, fabs(H[(size_t)ph * a.N_pad + ab]));
+    // mx = f 2^ex, f in [0.5, 1); a zero row (padding, or a Hermite function
+    // the pair does not use) sends its [p|ket] row to zero (2^-2000 underflows)
+    // so that it cannot set the column exponents of the kernel's operand
+    int ex = -2000;
+    if (mx > 0.0) (void)frexp(mx, &ex);
+    Kr[ph] = ex;
+  }
+  __syncthreads();
+  int *Ex = a.Hexp + (size_t)pp * a.N_pad;
+  for (int ab = tid; ab < a.N_pad; ab += kPairThreads) {
+    double mx = 0.0;
+    for (int ph = 0; ph < a.Nh_pad; ++ph) mx = fmax(mx, fabs(ldexp(H[(size_t)ph * a.N_pad + ab], -Kr[ph])));
+    int ex = 0;
+    if (mx > 0.0) (void)frexp(mx, &ex);
+    Ex[ab] = ex;
+  }
+  __syncthreads();
+  uint16_t *Hs = a.Hs + (size_t)pp * a.split * a.N_pad * a.Hs_rows;
+  for (int e = tid; e < a.N_pad * a.Hs_rows; e += kPairThreads) {
+    const int ab = e / a.Hs_rows, pos = e - ab * a.Hs_rows;
+    const int blk = pos >> 5, g = (pos >> 3) & 3, ee = pos & 7;
+    const int row = 32 * blk + 16 * (ee >> 2) + 4 * (ee & 3) + g;
+    double r = row < a.Nh_pad ? ldexp(H[(size_t)row * a.N_pad + ab], -Kr[row] - Ex[ab]) : 0.0;
+    for (int sl = 0; sl < a.split; ++sl) {
+      const double v = r * 128.0;
+      const double t = rint(v);
+      r = v - t;
+      // |t| <= 128: an integer of at most 8 significant bits, exact in BF16
+      // (the upper half of its FP32 pattern)
+      const float tf = (float)t;
+      Hs[((size_t)sl * a.N_pad + ab) * a.Hs_rows + pos] = (uint16_t)(__float_as_uint(tf) >> 16);
+    }
+  }
 }
 
 }  // namespace

@@ -27,11 +27,13 @@ def lib_path() -> str:
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("schwarz_tau", ctypes.c_double), ("flags", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("split_slices", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 FLAG_GRAPH = 1
 FLAG_AUTOTUNE = 2
+FP64 = 0
+SPLIT_BF16 = 1
 
 
 _vp = ctypes.c_void_p
@@ -128,7 +130,7 @@ class Context:
     def basis(self, l, nprim, exps, coefs, centers, atom=None, normalize=1) -> "Basis":
         return Basis(self, l, nprim, exps, coefs, centers, atom, normalize)
 
-    def eri4(self, basis: "Basis", bra, ket, out=None, stream=None, flags=0):
+    def eri4(self, basis: "Basis", bra, ket, out=None, stream=None, flags=0, precision=0, slices=0):
         """Class batch (ab|cd) -> torch float64 tensor V[ij, ab, cd, kl] (shape
         (nbra, Nab, Ncd, nket), a Fortran-order view of the flat output)."""
         import torch
@@ -142,7 +144,7 @@ class Context:
         if out is None:
             out = torch.empty(n, dtype=torch.float64, device=f"cuda:{self.device}")
         assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
-        opts = Opts(0, 1e-12, int(flags))
+        opts = Opts(int(precision), 1e-12, int(flags), int(slices))
         _check(load_library().mderi_eri4(self._h, basis._h, len(bra), bra.ctypes.data_as(_ip), len(ket),
                                          ket.ctypes.data_as(_ip), _vp(out.data_ptr()), out.numel(),
                                          ctypes.byref(opts), _stream_handle(stream)))
