@@ -106,6 +106,56 @@ def cpu_baseline(batches, wall_per_class=2.5):
                       " quartets of each class batch; full-step time extrapolated per class"}
 
 
+def mixed_precision(ctx, steps):
+    """[gg|gg], [hh|hh], [ii|ii], K=1, 128 x 128 Schwarz-admitted pairs (16,384
+    quartets) each: FP64 against the split-precision bra transform with 5, 6
+    and 7 slices; error per shellset (max |dV| - 1e-14) / max |V| against the
+    FP64 result (max and RMS over shellsets)."""
+    import torch
+    from paper_2405_01834_amd import model
+    from paper_2405_01834_amd.mderi import SPLIT_BF16
+    out = {}
+    for l in (4, 5, 6):
+        sh, basis, bra, ket, frac = make_batch(ctx, l, 1, seed=4, npair=128)
+        n = len(bra) * len(ket) * (2 * l + 1) ** 4
+        ref = torch.empty(n, dtype=torch.float64, device="cuda")
+        tmp = torch.empty(n, dtype=torch.float64, device="cuda")
+        flops = len(bra) * len(ket) * model.eri4_flops(l, l, l, l, 1, 1)
+
+        def timed(buf, **kw):
+            ctx.eri4(basis, bra, ket, out=buf, **kw)  # warm-up (pair data, caches)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                ctx.eri4(basis, bra, ket, out=buf, **kw)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / steps
+
+        t64 = timed(ref)
+        Vr = ref.view(len(ket), (2 * l + 1) ** 2, (2 * l + 1) ** 2, len(bra))
+        mref = Vr.abs().amax(dim=(1, 2))
+        name = f"[{NAMES[l]}|{NAMES[l]}] K=1"
+        rec = {"fp64_ms": t64, "fp64_frac_peak": flops / (t64 * 1e-3) / 1e12 / model.FP64_PEAK_TFLOPS,
+               "quartets": len(bra) * len(ket)}
+        for S in (5, 6, 7):
+            ts = timed(tmp, precision=SPLIT_BF16, slices=S)
+            Vs = tmp.view_as(Vr)
+            d = (Vs - Vr).abs().amax(dim=(1, 2))
+            e = torch.clamp(d - 1e-14, min=0.0) / torch.clamp(mref, min=1e-300)
+            rec[f"S{S}"] = {"ms": ts, "speedup": t64 / ts, "err_max": float(e.max()),
+                            "err_rms": float(torch.sqrt((e * e).mean()))}
+            log(f"{name}: FP64 {t64:.2f} ms; split S={S} {ts:.2f} ms (x{t64 / ts:.2f}), per-shellset error "
+                f"max {float(e.max()):.2e} rms {float(torch.sqrt((e * e).mean())):.2e}")
+        out[name] = rec
+        basis.close()
+        del ref, tmp, Vr
+        torch.cuda.empty_cache()
+    return {"classes": out,
+            "workload": "[gg|gg],[hh|hh],[ii|ii] K=1, 128x128 Schwarz-admitted pairs each; error vs the FP64 "
+                        "result per shellset, (max|dV| - 1e-14)/max|V|"}
+
+
 def eri3_task_list(ctx, steps, flags):
     """512 mixed primary pairs x 512 auxiliary shells (262,144 triplets) in one
     task-list call; the first call builds, tunes and captures the plan."""
@@ -185,6 +235,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-wall", type=float, default=2.5, help="oracle wall seconds per class")
     ap.add_argument("--classes", default="", help="subset, e.g. 4:3,2:1 (l:K)")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
     ap.add_argument("--no-tune", action="store_true", help="skip the per-class autotuning of the 4-centre batches")
     ap.add_argument("--eri3", default="graph+autotune", choices=["graph+autotune", "graph", "plain", "off"],
                     help="mode of the 3-centre task-list measurement")
@@ -300,6 +351,8 @@ def main():
                      "traffic": measured_traffic(f"eri4_kernel {dom}"), "traffic_unit": "B"},
         "wall_s": wall,
     }
+    if not args.no_split:
+        rec["mixed_precision"] = mixed_precision(ctx, max(args.steps, 2))
     if args.eri3 != "off":
         rec["eri3_batch"] = eri3_task_list(ctx, max(args.steps, 3), args.eri3)
     if args.cluster_atoms > 0:

@@ -430,7 +430,11 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     return;
   }
   if (a.diag) {
-    for (int ab = tid; ab < a.Nb; ab += blockDim.x) a.V[(size_t)ij * a.Nb + ab] = vsh[ab * a.Nk + ab];
+    // (ab|ab) for the ab that fall in this workgroup's column slab
+    for (int cl = tid; cl < vcols; cl += blockDim.x) {
+      const int ab = c0 + cl;
+      if (ab < a.Nb) a.V[(size_t)ij * a.Nb + ab] = vsh[ab * vstride + cl];
+    }
     return;
   }
   if (a.orow) {

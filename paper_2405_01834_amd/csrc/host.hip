@@ -684,7 +684,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   for (int i = 0; i < nket; ++i) maxk = std::max(maxk, ket.off[i + 1] - ket.off[i]);
   const int maxpp = maxb + maxk;
   Eri4Plan pl{};
-  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, false, diag == 0, &pl))
+  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, false, true, &pl))
     return fail(MDERI_EUNSUPPORTED, "class (%d%d|%d%d) is beyond the fused kernel's tiles", la, lb, lc, ld);
   // tile variants: the tuned choice for this class signature, or all of
   // them timed on this batch when autotuning (single-slab classes only)

@@ -137,3 +137,20 @@ def test_high_l_parity(ctx, cls, K, nbra, nket):
         for k, (q0, q1) in enumerate(ket):
             ref = md_matrix.shellset(sh, p0, p1, q0, q1)
             _assert_close(got[i, :, :, k], ref, f"{cls} K={K} quartet ({i},{k})")
+
+
+def test_schwarz_high_l(ctx):
+    """Schwarz factors of [hh| and [ii| pairs, whose diagonal quartets run in
+    column slabs, against the matrix-form reference."""
+    import torch
+    from tests.ref import md_matrix
+    rng = np.random.default_rng(77)
+    sh = inputs.random_shells(rng, [5, 5, 6, 6, 6, 5], 1, 4.0, 0.1, 30.0)
+    pairs = np.array([[0, 1], [2, 3], [4, 5]], dtype=np.int32)
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    Q = ctx.schwarz(b, pairs).cpu().numpy()
+    torch.cuda.synchronize()
+    for n, (i, j) in enumerate(pairs):
+        V = md_matrix.shellset(sh, i, j, i, j)
+        ref = np.sqrt(np.max(np.abs(np.diag(V))))
+        assert abs(Q[n] - ref) <= 1e-12 * ref, (n, Q[n], ref)
