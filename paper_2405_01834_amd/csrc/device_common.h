@@ -230,11 +230,145 @@ __host__ __device__ constexpr int rr_lm_bucket(int L) {
   return L <= 8 ? 8 : L <= 10 ? 10 : L <= 16 ? 16 : L <= 18 ? 18 : L <= 26 ? 26 : -1;
 }
 
-// Size (doubles) of the work area of build_R_chains for total L: [0]^(m),
-// then one (LM+1)-slot m-vector per z level and per (u, v) pair.
+// Layout of the y stage of build_R_chains for total L.  The m-vectors
+// [0uv]^(m) are computed with one lane per (v, m): the lanes of one v form a
+// block of L-v+1 consecutive lanes, blocks are packed whole into groups of at
+// most 64 lanes (a group is one register of the wave), and all blocks of a
+// group take len = L - (smallest v of the group) steps along u.  The buffer
+// is v-major: the vector of (u, v) sits in slot vbase(v) + u (L+1 doubles per
+// slot), and every v reserves len + 1 slots of its group, so a lane stores
+// level u+1 at a fixed offset from level u whether or not (u+1, v) exists.
+//   Returns the number of slots; when v >= 0, *vbase_out = vbase(v).
+__host__ __device__ constexpr int ylayout(int L, int v = -1, int *vbase_out = nullptr) {
+  int used = 64, len = 0, vb = 0;
+  for (int w = 0; w <= L; ++w) {
+    const int need = L - w + 1;
+    if (used + need > 64) {
+      used = 0;
+      len = L - w;
+    }
+    used += need;
+    if (w == v && vbase_out) *vbase_out = vb;
+    vb += len + 1;
+  }
+  return vb;
+}
+
+__host__ __device__ constexpr int yvbase(int L, int v) {
+  int vb = 0;
+  (void)ylayout(L, v, &vb);
+  return vb;
+}
+
+// Number of lane groups of the y stage for total L, and the step count of group j.
+__host__ __device__ constexpr int ygroups(int L) {
+  int used = 64, ng = 0;
+  for (int w = 0; w <= L; ++w) {
+    const int need = L - w + 1;
+    if (used + need > 64) {
+      used = 0;
+      ++ng;
+    }
+    used += need;
+  }
+  return ng;
+}
+__host__ __device__ constexpr int ygroup_len(int L, int j) {
+  int used = 64, g = -1;
+  for (int w = 0; w <= L; ++w) {
+    const int need = L - w + 1;
+    if (used + need > 64) {
+      used = 0;
+      if (++g == j) return L - w;
+    }
+    used += need;
+  }
+  return 0;
+}
+
+// Lane groups the fixed-slot builder provides registers for (every L of the
+// bucket fits: ygroups(L) <= 1, 2, 3, 4 for L <= 8, 10, 16, 18).
+template <int LM>
+__host__ __device__ constexpr int ygroup_regs() {
+  return LM <= 9 ? 1 : LM <= 10 ? 2 : LM <= 16 ? 3 : 4;
+}
+
+// Size (doubles) of the work area of build_R_chains for total L: the y-stage
+// buffer (ylayout slots of L+1 doubles; level u = 0 holds the z chain), then
+// a scratch row for the lanes a y group does not use (64 + L (L+1) doubles).
 __host__ __device__ constexpr int rr_work_size(int L) {
-  return rr_lm_bucket(L) > 18 ? rr_work_size_packed(L)
-                              : (L + 1) + ((L + 1) + (L + 1) * (L + 2) / 2) * (rr_lm_bucket(L) + 1);
+  return rr_lm_bucket(L) > 18 ? rr_work_size_packed(L) : (ylayout(L) + L) * (L + 1) + 64;
+}
+
+// Per-lane state of the y stage, set once per kernel by ylanes_init.
+template <int LM>
+struct YLanes {
+  int addr[ygroup_regs<LM>()];  // slot vbase(v) (L+1) + m of this lane's (v, m) in group j, else scratch row
+};
+
+template <int LM>
+__device__ __forceinline__ void ylanes_init(int L, int lane, YLanes<LM> &y) {
+  constexpr int NG = ygroup_regs<LM>();
+  const int W = L + 1;
+#pragma unroll
+  for (int j = 0; j < NG; ++j) y.addr[j] = ylayout(L) * W + lane;
+  int used = 64, g = -1, len = 0, vb = 0;
+  for (int w = 0; w <= L; ++w) {
+    const int need = L - w + 1;
+    if (used + need > 64) {
+      used = 0;
+      ++g;
+      len = L - w;
+    }
+    if (lane >= used && lane < used + need) {
+#pragma unroll
+      for (int j = 0; j < NG; ++j)
+        if (g == j) y.addr[j] = vb * W + (lane - used);
+    }
+    used += need;
+    vb += len + 1;
+  }
+}
+
+// x chains of the pairs p0 .. p0+63 (ordered by u+v, so the pass's first
+// pair has the longest chain, M0 = L - (u+v of pair p0)): level t+1 of a
+// lane's m-vector is valid for m <= M - t - 1 <= M0 - t - 1, so the levels
+// shrink; lanes store level t+1 while t < M.
+template <int L, int P0>
+__device__ __forceinline__ void x_pass(double X, double *cube, int S1, int S2, const double *yb, const uint32_t *uv,
+                                       int lane) {
+  constexpr int W = L + 1, NPAIR = (L + 1) * (L + 2) / 2;
+  if constexpr (P0 < NPAIR) {
+    constexpr int S0 = [] {
+      int s = 0;
+      while ((s + 1) * (s + 2) / 2 <= P0) ++s;
+      return s;
+    }();
+    constexpr int M0 = L - S0;
+    const int pi = P0 + lane;
+    if (P0 + 64 <= NPAIR || pi < NPAIR) {
+      const uint32_t e = uv[pi];
+      const int u = e & 0xff, v = (e >> 8) & 0xff, M = L - u - v;
+      const double *ys = yb + (e >> 16) * W;
+      double a[M0 + 1], b[M0 + 1];
+#pragma unroll
+      for (int m = 0; m <= M0; ++m) a[m] = ys[m];
+      double *cc = cube + u * S2 + v;
+      cc[0] = a[0];
+#pragma unroll
+      for (int t = 0; t < M0; t += 2) {
+#pragma unroll
+        for (int m = 0; m < M0 - t; ++m) b[m] = t == 0 ? X * a[m + 1] : fma(X, a[m + 1], (double)t * b[m + 1]);
+        if (t < M) cc[(t + 1) * S1] = b[0];
+        if (t + 1 < M0) {
+#pragma unroll
+          for (int m = 0; m < M0 - t - 1; ++m) a[m] = fma(X, b[m + 1], (double)(t + 1) * a[m + 1]);
+          if (t + 1 < M) cc[(t + 2) * S1] = a[0];
+        }
+      }
+    }
+    x_pass<L, P0 + 64>(X, cube, S1, S2, yb, uv, lane);
+  }
 }
 
 // Builds [r]^(0) for all |r| <= L (Eqs. (0m) and (r)) in the LDS cube
@@ -242,113 +376,99 @@ __host__ __device__ constexpr int rr_work_size(int L) {
 // single wave and wave-local synchronisation, so the other waves of the
 // workgroup keep issuing matrix-core work meanwhile.  Eq. (r) is applied
 // direction by direction (the same choice of direction as raising the first
-// non-zero component of r): z-chain [00v]^(m) on one lane, y-chains [0uv]^(m)
-// with one lane per v, x-chains [tuv]^(m) with one lane per (u, v); each lane
-// keeps its m-vector in registers (LM = rr_lm_bucket(L) at compile time;
-// LM > 18 uses the packed variant above).  The m-vectors pass between the stages through fixed (LM+1)-slot LDS
-// buffers written and read whole: entries past a vector's valid m range hold
-// finite junk that only ever feeds other junk entries, and no store or load
-// depends on a run-time m bound (no branches in the chains).
+// non-zero component of r), with L fixed at compile time so every loop is
+// unrolled and every LDS offset is an immediate:
+//   * [0]^(m) (Eq. (0m)) and the z chain [00v]^(m): one lane per m, the m+1
+//     neighbour taken from the next lane by a DPP move;
+//   * y chains [0uv]^(m): one lane per (v, m) in the lane groups of ylayout,
+//     again with DPP moves, the groups' chains interleaved;
+//   * x chains [tuv]^(m): one lane per (u, v) with the m-vector in
+//     registers, 64 pairs per pass (x_pass).
+// Entries past a vector's valid m range carry junk that only ever feeds
+// other junk entries and is never stored in the cube.
 //   p, P: bra Hermite exponent and centre; q, Q: ket.
-//   work: rr_work_size(L) doubles of LDS; uv: (u | v << 8) of the pairs
-//         u+v <= L ordered by u+v (longest chains first).
-template <int LM>
-__device__ __forceinline__ void build_R_chains(int L, double p, const double *P, double q, const double *Q,
-                                               double *cube, int S1, int S2, double *work, const uint32_t *uv,
-                                               const double *boys, int lane) {
-  if constexpr (LM > 18) {
-    build_R_chains_packed<LM>(L, p, P, q, Q, cube, S1, S2, work, uv, boys, lane);
-    return;
-  }
-  constexpr int W = LM + 1;
+//   work: rr_work_size(L) doubles of LDS; uv: (u | v << 8 | (vbase(v)+u) << 16)
+//         of the pairs u+v <= L ordered by u+v (longest chains first).
+template <int L, int LM>
+__device__ __forceinline__ void build_R_exact(double p, const double *P, double q, const double *Q, double *cube,
+                                              int S1, int S2, double *work, const uint32_t *uv, const double *boys,
+                                              int lane, const YLanes<LM> &yl) {
+  constexpr int W = L + 1, NG = ygroups(L);
   const double pq = p + q;
   const double rho = p * q / pq;
   const double X = P[0] - Q[0], Y = P[1] - Q[1], Z = P[2] - Q[2];
   const double T = rho * (X * X + Y * Y + Z * Z);
-  double *f0 = work;              // [0]^(m), m = 0..L
-  double *zb = f0 + (L + 1);      // [00v]^(m) at v*W + m
-  double *yb = zb + (L + 1) * W;  // [0uv]^(m) at slot(u, v)*W + m, pairs ordered by u, then v
+  double *yb = work;  // [0uv]^(m) at (vbase(v) + u) W + m
+  // [0]^(m) in lane m, then the z chain: level v+1 from levels v and v-1 at
+  // m+1; the level-v-1 neighbour is the previous step's DPP result.  Lanes
+  // past L sit out (their DPP reads return 0).
   if (lane <= L) {
     double f = 2.0 * 17.493418327624862 / (p * q * sqrt(pq));  // Eq. (0m), 17.49.. = pi^{5/2}
     f *= ipow_small(-2.0 * rho, lane);
-    f0[lane] = f * boys_m(lane, T, boys);
-  }
-  lds_wave_sync();
-  // z chain with one lane per m: level v+1 from levels v and v-1 at m+1,
-  // taken from the next lane by a DPP move (Eq. (r) along z)
-  {
-    double za = lane <= L ? f0[lane] : 0.0, zp = 0.0;
-    if (lane <= L) zb[lane] = za;
+    double za = f * boys_m(lane, T, boys), zp = 0.0;
+    double *zl = yb + lane;
+    zl[0] = za;  // vbase(0) = 0
+#pragma unroll
     for (int v = 0; v < L; ++v) {
-      const double an = lane_next(za), pn = lane_next(zp);
-      zp = za;
-      za = fma(Z, an, (double)v * pn);
-      if (lane <= L) zb[(v + 1) * W + lane] = za;
+      const double an = lane_next(za);
+      za = v == 0 ? Z * an : fma(Z, an, (double)v * zp);
+      zp = an;
+      zl[yvbase(L, v + 1) * W] = za;
     }
   }
   lds_wave_sync();
-  // y chains, one lane per v with the m-vector in registers (under
-  // matrix-core contention the cost follows the instruction count, which
-  // this form keeps lowest); (u, v) lands in slot u (L + 1) - u (u - 1) / 2 + v
-  double a[W], b[W];
-  if (lane <= L) {
-    const int v = lane, M = L - v;
+  // y chains: lane (v, m) of group j holds [0uv]^(m); level u+1 lands W
+  // doubles after level u
+  {
+    double ya[NG], yp[NG];
 #pragma unroll
-    for (int m = 0; m < W; ++m) {
-      a[m] = zb[v * W + m];
-      b[m] = 0.0;
+    for (int j = 0; j < NG; ++j) {
+      ya[j] = yb[yl.addr[j]];
+      yp[j] = 0.0;
     }
-    int slot = v;
 #pragma unroll
-    for (int m = 0; m < W; ++m) yb[slot * W + m] = a[m];
-    for (int u = 0; u < M; u += 2) {
-      rr_step<LM>(a, b, (double)u, Y);
-      slot += L - u + 1;  // (u+1, v)
+    for (int u = 0; u < L; ++u) {
 #pragma unroll
-      for (int m = 0; m < W; ++m) yb[slot * W + m] = b[m];
-      rr_step<LM>(b, a, (double)(u + 1), Y);
-      if (u + 1 < M) {
-        slot += L - u;  // (u+2, v)
-#pragma unroll
-        for (int m = 0; m < W; ++m) yb[slot * W + m] = a[m];
-      }
-    }
-  }
-  lds_wave_sync();
-  const int npair = (L + 1) * (L + 2) / 2;
-  for (int pi = lane; pi - lane < npair; pi += 64) {  // x chains, lane = (u, v)
-    // longest chain of this pass (pairs are ordered by u+v, so it is the
-    // pass's first): levels beyond it are skipped by the whole wave
-    const int Mmax = L - (int)((uv[pi - lane] & 0xff) + ((uv[pi - lane] >> 8) & 0xff));
-    if (pi < npair) {
-      const int u = uv[pi] & 0xff, v = (uv[pi] >> 8) & 0xff, M = L - u - v;
-      const int slot = u * (L + 1) - u * (u - 1) / 2 + v;
-#pragma unroll
-      for (int m = 0; m < W; ++m) {
-        a[m] = yb[slot * W + m];
-        b[m] = 0.0;
-      }
-      double *cc = cube + u * S2 + v;
-      cc[0] = a[0];
-      // level t+1 is valid for m <= M - t - 1 <= LM - t - 1, so the fully
-      // unrolled levels shrink (half the FP64 work of full-length steps; on
-      // this chip vector FP64 shares the datapath with the consumers' FP64
-      // matrix work)
-#pragma unroll
-      for (int t = 0; t < LM; t += 2) {
-        if (t >= Mmax) break;
-#pragma unroll
-        for (int m = 0; m < LM - t; ++m) b[m] = fma(X, a[m + 1], (double)t * b[m + 1]);
-        if (t < M) cc[(t + 1) * S1] = b[0];
-        if (t + 1 < LM) {
-#pragma unroll
-          for (int m = 0; m < LM - t - 1; ++m) a[m] = fma(X, b[m + 1], (double)(t + 1) * a[m + 1]);
-          if (t + 1 < M) cc[(t + 2) * S1] = a[0];
+      for (int j = 0; j < NG; ++j) {
+        if (u < ygroup_len(L, j)) {
+          const double an = lane_next(ya[j]);
+          ya[j] = u == 0 ? Y * an : fma(Y, an, (double)u * yp[j]);
+          yp[j] = an;
+          yb[yl.addr[j] + (u + 1) * W] = ya[j];
         }
       }
     }
   }
   lds_wave_sync();
+  x_pass<L, 0>(X, cube, S1, S2, yb, uv, lane);
+  lds_wave_sync();
+}
+
+template <int LO, int HI, int LM>
+__device__ __forceinline__ void build_R_dispatch(int L, double p, const double *P, double q, const double *Q,
+                                                 double *cube, int S1, int S2, double *work, const uint32_t *uv,
+                                                 const double *boys, int lane, const YLanes<LM> &yl) {
+  if constexpr (HI >= LO) {
+    if (L == HI) {
+      build_R_exact<HI, LM>(p, P, q, Q, cube, S1, S2, work, uv, boys, lane, yl);
+      return;
+    }
+    build_R_dispatch<LO, HI - 1, LM>(L, p, P, q, Q, cube, S1, S2, work, uv, boys, lane, yl);
+  }
+}
+
+// [r]^(0) for |r| <= L: the exact-L builder of the bucket LM (L <= 18), the
+// packed builder above for larger L.
+template <int LM>
+__device__ __forceinline__ void build_R_chains(int L, double p, const double *P, double q, const double *Q,
+                                               double *cube, int S1, int S2, double *work, const uint32_t *uv,
+                                               const double *boys, int lane, const YLanes<LM> &yl) {
+  if constexpr (LM > 18) {
+    build_R_chains_packed<LM>(L, p, P, q, Q, cube, S1, S2, work, uv, boys, lane);
+  } else {
+    constexpr int LO = LM <= 8 ? 0 : LM <= 10 ? 9 : LM <= 16 ? 11 : 17;
+    build_R_dispatch<LO, LM, LM>(L, p, P, q, Q, cube, S1, S2, work, uv, boys, lane, yl);
+  }
 }
 
 // Workgroup id -> work item such that consecutive items land on the same XCD

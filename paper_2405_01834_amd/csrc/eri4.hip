@@ -4,8 +4,12 @@
 //   * one producer wave that builds [r]^(0) (Eqs. (0m), (r)) for the primitive
 //     quartets one after another into a double-buffered LDS cube, one quartet
 //     ahead of the consumers, and
-//   * nct * nps consumer waves: wave (ct, ph) owns the 16 ket components
-//     cd in [16 ct, 16 ct + 16) and the bra Hermite rows p of part ph.
+//   * nct * nps consumer waves: each owns the 16 ket components cd in
+//     [16 ct, 16 ct + 16) of one column tile ct and the bra Hermite rows p of
+//     one part (up to npt 16-row tiles).  Waves run on SIMD (wave mod 4), and
+//     on MI355X a wave that issues FP64 MFMAs back to back holds off every
+//     VALU instruction of the other waves of its SIMD, so the parts with the
+//     fewest tiles go to the producer's SIMD (eri4_fill_wtask).
 // For each bra primitive pair a consumer computes
 //   X[p][cd]  = sum_{ket prims} sum_q [p|q] H_ket[q][cd]        Eq. (ket-from-hermite)
 //   V[ab][cd] += sum_p H_bra[p][ab] X[p][cd]                      Eq. (bra-from-hermite)
@@ -18,14 +22,34 @@
 // 16-row ab tile at a time and adds it into an LDS copy of V[ab][cd]
 // (FP64 LDS atomics, since the nps row parts share columns), which is written
 // to V[ij,ab,cd,kl] (Sec. 3, ij fastest) at the end.
+#include <algorithm>
+#include <vector>
+
 #include "device_common.h"
 
 namespace mderi {
 
 namespace {
 
-constexpr int kMaxWaves = 16;
+constexpr int kMaxWaves = kMaxWavesArgs;
 constexpr int kBufferWord3 = 0x00020000;  // buffer resource word 3 for gfx9-family raw loads
+
+template <int N>
+struct Tiles {
+  static constexpr int value = N;
+};
+
+// Calls f(Tiles<n>) for the run-time tile count 1 <= n <= NPT (nothing for 0).
+template <int NPT, class F>
+__device__ __forceinline__ void with_tiles(int n, F &f) {
+  if constexpr (NPT >= 1) {
+    if (n == NPT) {
+      f(Tiles<NPT>{});
+      return;
+    }
+    with_tiles<NPT - 1>(n, f);
+  }
+}
 
 // Exchange digestion of one shellset (ab|cd) held in LDS as v[ab][cd]
 // (Sec. 6, K = sum (ab|cd) D): with K_ac = sum_bd (ab|cd) D_bd, the eight
@@ -82,7 +106,7 @@ __device__ __forceinline__ void kdigest(const Eri4Args &a, const double *v, int 
 // block's nct * nps consumers and its producer (a task-list launch sizes the
 // workgroup for its largest block) only take part in the barriers.
 template <int NPT, int LM, int MODE>
-__device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, int slab, double *smem) {
+__device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, int slab, double *smem, uint32_t tk) {
   constexpr bool GRAD = MODE == 1;   // gradient mode (see the derivative step)
   constexpr bool SPLIT = MODE >= 2;  // split-precision bra transform with S = MODE + 3 slices
   constexpr int S = MODE + 3;
@@ -100,7 +124,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
   double *gsh = work + rr_work_size(L);              // G of this quartet's bra then ket primitive pairs
   double *gsum = gsh + 4 * a.maxpp;                  // 8 gradient partial sums
   double *vsh = gsum + 8;                            // V[ab][cd] (or the weights W) of this quartet
-  uint32_t *uvsh = (uint32_t *)(vsh + a.Nb * vstride);  // (u, v) pairs, u+v <= L, by u+v
+  uint32_t *uvsh = (uint32_t *)(vsh + a.Nb * vstride);  // (u, v, y slot) of the pairs u+v <= L, by u+v
   int *offq = (int *)(uvsh + (L + 1) * (L + 2) / 2);
 
   const int tid = threadIdx.x;
@@ -119,8 +143,10 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     // e-th pair in the order s = u+v ascending, u ascending
     int s = 0;
     while ((s + 1) * (s + 2) / 2 <= e) ++s;
-    const int u = e - s * (s + 1) / 2;
-    uvsh[e] = (uint32_t)u | ((uint32_t)(s - u) << 8);
+    const int u = e - s * (s + 1) / 2, v = s - u;
+    int vb = 0;
+    (void)ylayout(L, v, &vb);
+    uvsh[e] = (uint32_t)u | ((uint32_t)v << 8) | ((uint32_t)(vb + u) << 16);
   }
   if (GRAD) {
     // W[ab][cd] = D_ac D_bd + D_ad D_bc (the two distinct pairings of E = tr(D K))
@@ -151,22 +177,22 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     // the producer shares its SIMD with consumer waves that keep the matrix
     // core busy; top issue priority keeps its VALU chains from being starved
     __builtin_amdgcn_s_setprio(3);
+    YLanes<LM> yl;
+    if constexpr (LM <= 18) ylanes_init<LM>(L, lane, yl);
     auto build = [&](int n, double *cube) {
       const int ib = n / nkp, ik = n - ib * nkp;
       const double *Gb = gsh + 4 * ib;
       const double *Gk = gsh + 4 * (nbp + ik);
       const double P[3] = {Gb[1], Gb[2], Gb[3]};
       const double Q[3] = {Gk[1], Gk[2], Gk[3]};
-      build_R_chains<LM>(L, Gb[0], P, Gk[0], Q, cube, S1, S2, work, uvsh, a.tab.boys, lane);
+      build_R_chains<LM>(L, Gb[0], P, Gk[0], Q, cube, S1, S2, work, uvsh, a.tab.boys, lane, yl);
     };
-    if (nsteps > 0) build(0, cube0);
+    // one build site: step n is built while the consumers work on step n-1
+    // (two cubes) or after they are done with the single cube
     for (int n = 0; n < nsteps; ++n) {
-      if (!a.dbuf && n > 0) {
-        __syncthreads();  // consumers are done with the single cube
-        build(n, cube0);
-      }
+      if (!a.dbuf && n > 0) __syncthreads();  // consumers are done with the single cube
+      build(n, (a.dbuf && (n & 1)) ? cube1 : cube0);
       __syncthreads();  // [r] of step n published
-      if (a.dbuf && n + 1 < nsteps) build(n + 1, ((n + 1) & 1) ? cube1 : cube0);
     }
     __builtin_amdgcn_s_setprio(0);
   } else if (wave > ncons) {
@@ -177,13 +203,16 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     }
   } else {
     // ---------------- consumers ----------------
-    const int ct = wave % a.nct, ph = wave / a.nct;
+    // this wave's ket column tile ct and bra row tiles [t0, t0 + ntw); the
+    // tiles t0 + ntw .. t0 + NPT - 1 are zero rows and are skipped by the ket
+    // product (their X stays zero)
+    const int ct = (int)(tk & 0xff), t0 = (int)((tk >> 8) & 0xff), ntw = (int)((tk >> 16) & 0xff);
     const int col = c0 + ct * 16 + c;  // this lane's ket column cd
     int offp[NPT];
 #pragma unroll
     for (int pt = 0; pt < NPT; ++pt) {
       // rows are permuted per class so the 16 rows of a tile sit in distinct LDS banks
-      const uint32_t h = a.border[(ph * NPT + pt) * 16 + c];
+      const uint32_t h = a.border[(t0 + pt) * 16 + c];
       offp[pt] = (int)(h & 0xff) * S1 + (int)((h >> 8) & 0xff) * S2 + (int)((h >> 16) & 0xff);
     }
     const int nks = a.Nhk_pad >> 2;  // even: Nhk_pad is a multiple of 8
@@ -209,48 +238,54 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
       // MFMAs.  Prefetch indices are clamped so every load is unconditional;
       // nks is even (Nhk_pad is a multiple of 8).
       const double *Hk = a.ket_H + (size_t)(kp0 + ik) * a.Nhk_pad * a.Nk_pad;
-      double aA[NPT], aB[NPT];
-      double hA, hB, hC, hD;
-      // ket offsets of the k-steps ks+1, ks+2 sit in registers; those of the
-      // next iteration are read from LDS before this iteration's MFMAs, so
-      // the gathers never wait on a just-issued LDS read
-      int oq1, oq2;
-      {
-        const int oq = offq[g];
+      // the product over NT = ntw row tiles (compiled for every NT <= NPT)
+      auto ket = [&](auto ntc) {
+        constexpr int NT = decltype(ntc)::value;
+        double aA[NT], aB[NT];
+        double hA, hB, hC, hD;
+        // ket offsets of the k-steps ks+1, ks+2 sit in registers; those of the
+        // next iteration are read from LDS before this iteration's MFMAs, so
+        // the gathers never wait on a just-issued LDS read
+        int oq1, oq2;
+        {
+          const int oq = offq[g];
 #pragma unroll
-        for (int pt = 0; pt < NPT; ++pt) aA[pt] = cube[offp[pt] + oq];
-        oq1 = offq[4 * min(1, nks - 1) + g];
-        oq2 = offq[4 * min(2, nks - 1) + g];
-        hA = Hk[klo];
-        hB = Hk[(size_t)min(1, nks - 1) * kstep + klo];
-        hC = Hk[(size_t)min(2, nks - 1) * kstep + klo];
-        hD = Hk[(size_t)min(3, nks - 1) * kstep + klo];
-      }
+          for (int pt = 0; pt < NT; ++pt) aA[pt] = cube[offp[pt] + oq];
+          oq1 = offq[4 * min(1, nks - 1) + g];
+          oq2 = offq[4 * min(2, nks - 1) + g];
+          hA = Hk[klo];
+          hB = Hk[(size_t)min(1, nks - 1) * kstep + klo];
+          hC = Hk[(size_t)min(2, nks - 1) * kstep + klo];
+          hD = Hk[(size_t)min(3, nks - 1) * kstep + klo];
+        }
 #pragma unroll 1
-      for (int ks = 0; ks < nks; ks += 2) {
+        for (int ks = 0; ks < nks; ks += 2) {
 #pragma unroll
-        for (int pt = 0; pt < NPT; ++pt) aB[pt] = cube[offp[pt] + oq1];
-        const int on1 = offq[4 * min(ks + 3, nks - 1) + g];
-        const int on2 = offq[4 * min(ks + 4, nks - 1) + g];
-        __builtin_amdgcn_sched_barrier(0);
+          for (int pt = 0; pt < NT; ++pt) aB[pt] = cube[offp[pt] + oq1];
+          const int on1 = offq[4 * min(ks + 3, nks - 1) + g];
+          const int on2 = offq[4 * min(ks + 4, nks - 1) + g];
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int pt = 0; pt < NPT; ++pt)
-          xacc[pt] = GRAD ? mfma16x16x4(hA, aA[pt], xacc[pt]) : mfma16x16x4(aA[pt], hA, xacc[pt]);
-        __builtin_amdgcn_sched_barrier(0);
+          for (int pt = 0; pt < NT; ++pt)
+            xacc[pt] = GRAD ? mfma16x16x4(hA, aA[pt], xacc[pt]) : mfma16x16x4(aA[pt], hA, xacc[pt]);
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int pt = 0; pt < NPT; ++pt) aA[pt] = cube[offp[pt] + oq2];
-        __builtin_amdgcn_sched_barrier(0);
+          for (int pt = 0; pt < NT; ++pt) aA[pt] = cube[offp[pt] + oq2];
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int pt = 0; pt < NPT; ++pt)
-          xacc[pt] = GRAD ? mfma16x16x4(hB, aB[pt], xacc[pt]) : mfma16x16x4(aB[pt], hB, xacc[pt]);
-        __builtin_amdgcn_sched_barrier(0);
-        oq1 = on1;
-        oq2 = on2;
-        hA = hC;
-        hB = hD;
-        hC = Hk[(size_t)min(ks + 4, nks - 1) * kstep + klo];
-        hD = Hk[(size_t)min(ks + 5, nks - 1) * kstep + klo];
-      }
+          for (int pt = 0; pt < NT; ++pt)
+            xacc[pt] = GRAD ? mfma16x16x4(hB, aB[pt], xacc[pt]) : mfma16x16x4(aB[pt], hB, xacc[pt]);
+          __builtin_amdgcn_sched_barrier(0);
+          oq1 = on1;
+          oq2 = on2;
+          hA = hC;
+          hB = hD;
+          hC = Hk[(size_t)min(ks + 4, nks - 1) * kstep + klo];
+          hD = Hk[(size_t)min(ks + 5, nks - 1) * kstep + klo];
+        }
+      };
+      if (ntw == NPT) ket(Tiles<NPT>{});
+      else with_tiles<NPT - 1>(ntw, ket);
       if (GRAD && ik == nkp - 1) {
         // Gradient mode keeps X transposed (the ket step above swaps the MFMA
         // operands): register r of lane c + 16 g holds X^T[cd][p] with
@@ -275,8 +310,8 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
             w[s4] = (abw < a.Nb && cd < a.Nk) ? vsh[abw * a.Nk + cd] : 0.0;
           }
           // this lane's element of the [mat][ab][p] derivative matrices:
-          // ab = 16 at + g (+ 4 r), p = ph NPT 16 (+ 16 pt) + c
-          const int vo = 8 * (ph * NPT * 16 + c + (at * 16 + g) * a.Hb_rows);
+          // ab = 16 at + g (+ 4 r), p = 16 t0 (+ 16 pt) + c
+          const int vo = 8 * (t0 * 16 + c + (at * 16 + g) * a.Hb_rows);
 #pragma unroll
           for (int pt = 0; pt < NPT; ++pt) {
             d4 y = d4{0.0, 0.0, 0.0, 0.0};
@@ -307,7 +342,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
         // dropped (35-bit operands), the levels are combined in FP64.
         // rows balanced with the pair data's row exponents (X row p times
         // 2^k_p, H row p times 2^-k_p: products unchanged)
-        const int *Kr = a.bra_Hrow + (size_t)(bp0 + ib) * a.Hs_rows + ph * NPT * 16 + g;
+        const int *Kr = a.bra_Hrow + (size_t)(bp0 + ib) * a.Hs_rows + t0 * 16 + g;
         double mx = 0.0;
 #pragma unroll
         for (int pt = 0; pt < NPT; ++pt)
@@ -324,7 +359,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
         // 2 b + e / 4; one 32-row block at a time (slices of one block live)
         constexpr int NB = NPT / 2;
         const uint16_t *Hs =
-            a.bra_Hs + (size_t)(bp0 + ib) * S * a.Nb_pad * a.Hs_rows + (size_t)(ph * NB) * 32 + 8 * g;
+            a.bra_Hs + (size_t)(bp0 + ib) * S * a.Nb_pad * a.Hs_rows + (size_t)(t0 / 2) * 32 + 8 * g;
         const int *Ex = a.bra_Hexp + (size_t)(bp0 + ib) * a.Nb_pad;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
@@ -368,7 +403,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
       } else if (!SPLIT && ik == nkp - 1) {
         // bra transform: V[ab][cd] += sum_p H_bra[p][ab] X[p][cd], one ab tile
         // at a time (two accumulators), summed into the LDS copy of V
-        const double *Hb = a.bra_H + (size_t)(bp0 + ib) * a.Hb_rows * a.Nb_pad + (size_t)ph * NPT * 16 * a.Nb_pad;
+        const double *Hb = a.bra_H + (size_t)(bp0 + ib) * a.Hb_rows * a.Nb_pad + (size_t)t0 * 16 * a.Nb_pad;
 #pragma unroll 1
         for (int at = 0; at < nat; ++at) {
           const double *Ht = Hb + at * 16 + blo;
@@ -469,7 +504,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
     if (a.bra_q[ij] * a.ket_q[kl] < a.tau || (a.same_list && ij < kl)) return;
   }
   if (GRAD && a.bra_q[ij] * a.ket_q[kl] < a.tau) return;
-  eri4_quartet<NPT, LM, MODE>(a, ij, kl, slab, smem);
+  eri4_quartet<NPT, LM, MODE>(a, ij, kl, slab, smem, a.wtask[threadIdx.x >> 6]);
 }
 
 // Persistent task-list kernel: the workgroups stride over tasks (block id,
@@ -491,12 +526,14 @@ __global__ void __launch_bounds__(64 * kMaxWaves)
 #if defined(__HIP_DEVICE_COMPILE__)
     typedef __attribute__((address_space(4))) const Eri4Args ConstArgs;
     const Eri4Args a = ((ConstArgs *)(blocks))[bi];
+    const uint32_t tk = blocks[bi].wtask[threadIdx.x >> 6];
 #else
     const Eri4Args a = blocks[bi];  // host pass: the kernel is never run there
+    const uint32_t tk = 0;
 #endif
     const int ij = q % a.nbra, kl = q / a.nbra;
     __syncthreads();  // the previous task is done with LDS
-    eri4_quartet<NPT, LM, 0>(a, ij, kl, 0, smem);
+    eri4_quartet<NPT, LM, 0>(a, ij, kl, 0, smem, tk);
   }
 }
 
@@ -572,6 +609,50 @@ static size_t side_bytes(int L, int maxpp, int Nhk_pad, int Nb, int Nk) {
 size_t eri4_lds_bytes(const Eri4Args &a) {
   const int vcols = a.nslab > 1 ? a.nct * 16 : a.Nk;
   return cube_region(a.cube_sz, a.dbuf ? 2 : 1) + side_bytes(a.L, a.maxpp, a.Nhk_pad, a.Nb, vcols);
+}
+
+void eri4_fill_wtask(Eri4Args &a) {
+  // parts of the bra row tiles that hold real rows: part ph covers tiles
+  // [ph npt, ph npt + npt) of which the first min(npt, need - ph npt) are
+  // computed (split precision pairs tiles and computes all of them)
+  const int need = round16(a.Nhb) / 16, ncons = a.nct * a.nps;
+  struct Task {
+    int ct, t0, nt;
+  };
+  std::vector<Task> tasks;
+  for (int ph = 0; ph < a.nps; ++ph)
+    for (int ct = 0; ct < a.nct; ++ct) {
+      const int t0 = ph * a.npt;
+      tasks.push_back({ct, t0, a.bra_Hs ? a.npt : std::max(0, std::min(a.npt, need - t0))});
+    }
+  // the waves sharing the producer's SIMD take the lightest parts, the other
+  // SIMDs the rest, heaviest first onto the least loaded SIMD
+  std::stable_sort(tasks.begin(), tasks.end(), [](const Task &x, const Task &y) { return x.nt < y.nt; });
+  const int psimd = ncons % 4;
+  std::vector<int> slot_of(ncons, -1);  // task index per wave
+  size_t next = 0;
+  for (int w = psimd; w < ncons; w += 4) slot_of[w] = (int)(next++);
+  int load[4] = {0, 0, 0, 0};
+  for (size_t k = ncons; k-- > next;) {
+    int best = -1;
+    for (int sm = 0; sm < 4; ++sm) {
+      if (sm == psimd) continue;
+      bool free = false;
+      for (int w = sm; w < ncons; w += 4) free = free || slot_of[w] < 0;
+      if (free && (best < 0 || load[sm] < load[best])) best = sm;
+    }
+    for (int w = best; w < ncons; w += 4)
+      if (slot_of[w] < 0) {
+        slot_of[w] = (int)k;
+        break;
+      }
+    load[best] += tasks[k].nt;
+  }
+  for (int w = 0; w < kMaxWaves; ++w) a.wtask[w] = 0;
+  for (int w = 0; w < ncons; ++w) {
+    const Task &t = tasks[slot_of[w]];
+    a.wtask[w] = (uint32_t)t.ct | ((uint32_t)t.t0 << 8) | ((uint32_t)t.nt << 16);
+  }
 }
 
 bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int maxpp, bool grad, bool slabs,
@@ -676,9 +757,11 @@ hipError_t launch_g(const Eri4Args &a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_eri4(const Eri4Args &a, hipStream_t s) {
-  if (a.nbra <= 0 || a.nket <= 0) return hipSuccess;
-  if (a.nct * a.nps + 1 > kMaxWaves) return hipErrorInvalidValue;
+hipError_t launch_eri4(const Eri4Args &a0, hipStream_t s) {
+  if (a0.nbra <= 0 || a0.nket <= 0) return hipSuccess;
+  if (a0.nct * a0.nps + 1 > kMaxWaves) return hipErrorInvalidValue;
+  Eri4Args a = a0;
+  eri4_fill_wtask(a);
   if (a.grad) return launch_g<1>(a, s);
   if (a.bra_Hs) {
     switch (a.split) {  // mode = slices - 3

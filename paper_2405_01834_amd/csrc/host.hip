@@ -1548,6 +1548,7 @@ extern "C" mderi_status mderi_eri3_batch(mderi_ctx_t c, mderi_basis_t b, mderi_b
     for (int bi : gkv.second) {
       const BlockPlan &bp = blocks[bi];
       dblocks[bslot] = bp.a;
+      eri4_fill_wtask(dblocks[bslot]);
       g.Lmax = std::max(g.Lmax, bp.a.L);
       g.waves = std::max(g.waves, bp.a.nct * bp.a.nps + 1);
       g.lds = std::max(g.lds, block_lds(bp.a));

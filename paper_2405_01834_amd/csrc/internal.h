@@ -32,6 +32,9 @@ __host__ __device__ constexpr int nsph(int l) { return 2 * l + 1; }
 __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 __host__ __device__ constexpr int round16(int n) { return (n + 15) & ~15; }
 
+// Waves per workgroup of the 4-centre kernels (consumers + producer + idle).
+constexpr int kMaxWavesArgs = 16;
+
 // Packed Hermite / Cartesian triple.
 __host__ __device__ inline uint32_t pack3(int t, int u, int v) {
   return (uint32_t)t | ((uint32_t)u << 8) | ((uint32_t)v << 16);
@@ -144,6 +147,9 @@ struct Eri4Args {
   int split;     // number of slices (kernel mode follows it)
   Tables tab;
   double *V;
+  // work of consumer wave w (set by eri4_fill_wtask): ket column tile
+  // (bits 0-7), first bra row tile (bits 8-15), row tiles computed (bits 16-23)
+  uint32_t wtask[kMaxWavesArgs];
 };
 
 // Launchers (defined in the .hip files).
@@ -179,5 +185,7 @@ hipError_t launch_eri4_tasks(const Eri4Args *d_blocks, const int2 *d_tasks, int 
 int eri4_lm_bucket(int L);
 // LDS bytes needed by one 4-centre workgroup.
 size_t eri4_lds_bytes(const Eri4Args &a);
+// Fills a.wtask from nct, nps, npt, Nhb and split (see eri4.hip).
+void eri4_fill_wtask(Eri4Args &a);
 
 }  // namespace mderi
