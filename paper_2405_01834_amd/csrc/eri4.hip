@@ -238,6 +238,15 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
       // MFMAs.  Prefetch indices are clamped so every load is unconditional;
       // nks is even (Nhk_pad is a multiple of 8).
       const double *Hk = a.ket_H + (size_t)(kp0 + ik) * a.Nhk_pad * a.Nk_pad;
+      // H_ket reads as buffer loads: the lane part of the offset sits in a
+      // VGPR set once, the k-step part in an SGPR, so the loop spends no
+      // vector instructions on addresses (and never rewrites a register an
+      // in-flight MFMA still has to read)
+      const __amdgpu_buffer_rsrc_t hks = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)Hk, (short)0, a.Nhk_pad * a.Nk_pad * 8, kBufferWord3);
+      auto hload = [&](int k) -> double {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(hks, klo * 8, k * kstep * 8, 0));
+      };
       // the product over NT = ntw row tiles (compiled for every NT <= NPT)
       auto ket = [&](auto ntc) {
         constexpr int NT = decltype(ntc)::value;
@@ -253,13 +262,22 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
           for (int pt = 0; pt < NT; ++pt) aA[pt] = cube[offp[pt] + oq];
           oq1 = offq[4 * min(1, nks - 1) + g];
           oq2 = offq[4 * min(2, nks - 1) + g];
-          hA = Hk[klo];
-          hB = Hk[(size_t)min(1, nks - 1) * kstep + klo];
-          hC = Hk[(size_t)min(2, nks - 1) * kstep + klo];
-          hD = Hk[(size_t)min(3, nks - 1) * kstep + klo];
+          hA = hload(0);
+          hB = hload(min(1, nks - 1));
+          hC = hload(min(2, nks - 1));
+          hD = hload(min(3, nks - 1));
         }
+        // The matrix core of a SIMD serves its waves oldest first, so without
+        // help the first wave finishes well before the last, which then runs
+        // alone and cannot keep the pipe busy through its load latencies.
+        // Issue priority falls with progress (2, 1, 0 over the thirds of the
+        // k range), so the waves of a SIMD finish close together.
+        const int k1 = (nks / 3) & ~1, k2 = (2 * nks / 3) & ~1;
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll 1
         for (int ks = 0; ks < nks; ks += 2) {
+          if (ks == k1) __builtin_amdgcn_s_setprio(1);
+          if (ks == k2) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
           for (int pt = 0; pt < NT; ++pt) aB[pt] = cube[offp[pt] + oq1];
           const int on1 = offq[4 * min(ks + 3, nks - 1) + g];
@@ -280,8 +298,8 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
           oq2 = on2;
           hA = hC;
           hB = hD;
-          hC = Hk[(size_t)min(ks + 4, nks - 1) * kstep + klo];
-          hD = Hk[(size_t)min(ks + 5, nks - 1) * kstep + klo];
+          hC = hload(min(ks + 4, nks - 1));
+          hD = hload(min(ks + 5, nks - 1));
         }
       };
       if (ntw == NPT) ket(Tiles<NPT>{});
