@@ -39,9 +39,9 @@ TAU = 1e-12
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2) and
 # WRITE_SIZE (x1) counters (profiles/eri4_ggK3_hbm_counters.md), valid only for
 # the kernel sources they were taken with.
-TRAFFIC = {"kernel": "eri4_kernel [gg|gg] K=3", "bytes": 1.0050e11,
-           "sources": {"eri4.hip": "24cd59de11ba2c23", "device_common.h": "431e93c9e6828c7c",
-                       "internal.h": "f3168382833ca801"}}
+TRAFFIC = {"kernel": "eri4_kernel [gg|gg] K=3", "bytes": 1.1405e11,
+           "sources": {"eri4.hip": "c5eacb2fd1d17fa4", "device_common.h": "f3f0431310d8e033",
+                       "internal.h": "b9a58da583c000a1"}}
 
 
 def measured_traffic(kernel):
