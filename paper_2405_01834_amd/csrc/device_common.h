@@ -36,13 +36,40 @@ __device__ __forceinline__ bf8 load_bf8(const uint16_t *p) {
   return __builtin_bit_cast(bf8, *(const u4 *)p);
 }
 
+// 1/x and 1/sqrt(x) for x > 0 (normal): the hardware estimate refined by two
+// Newton steps (relative error about one unit in the last place), shorter
+// chains than the correctly rounded division and square root.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+
+// x^n for 0 <= n < 32 by binary exponentiation (dependency depth 5 instead of n).
+__device__ __forceinline__ double ipow_small(double x, int n) {
+  double r = 1.0;
+#pragma unroll
+  for (int bit = 0; bit < 5; ++bit) {
+    r *= (n & 1) ? x : 1.0;
+    x *= x;
+    n >>= 1;
+  }
+  return r;
+}
+
 // Boys function F_m(T), Eq. (boys), for one m per lane.
-//  T < 40: 8-term Taylor expansion about the nearest grid point T_i (spacing
+//  T < 100: 8-term Taylor expansion about the nearest grid point T_i (spacing
 //          1/16, |T - T_i| <= 1/32) using dF_m/dT = -F_{m+1}:
 //          F_m(T) = sum_k F_{m+k}(T_i) (T_i - T)^k / k!  (truncation < 3e-17 F_m).
-//  T >= 40: F_0 = (1/2) sqrt(pi/T) (erf(sqrt T) rounds to 1) and the upward
-//          recursion F_{j+1} = ((2j+1) F_j - e^{-T}) / (2T), stable for
-//          2j+1 < 2T.
+//  T >= 100: F_m = (2m-1)!! / (2T)^m F_0 with F_0 = (1/2) sqrt(pi/T): the
+//          terms in e^{-T} of the exact upward recursion are below 1e-18 of
+//          F_m there for every m <= 26.
 __device__ __forceinline__ double boys_m(int m, double T, const double *__restrict__ tab) {
   if (T < kBoysTmax) {
     const int i = (int)(T * (double)kBoysGridPerUnit + 0.5);
@@ -57,24 +84,10 @@ __device__ __forceinline__ double boys_m(int m, double T, const double *__restri
     const double p67 = fma(row[7] * (1.0 / 5040.0), d, row[6] * (1.0 / 720.0));
     return fma(fma(p67, d2, p45), d4, fma(p23, d2, p01));
   }
-  const double emT = exp(-T);
-  const double o2T = 0.5 / T;
-  double f = 0.5 * sqrt(3.14159265358979323846 / T);
-  for (int j = 0; j < m; ++j) f = ((2 * j + 1) * f - emT) * o2T;
-  return f;
+  const double f0 = 0.88622692545275801 * rsqrt_nr(T);  // (1/2) sqrt(pi) = 0.886..
+  return f0 * tab[kBoysNgrid * kBoysM + m] * ipow_small(0.5 * rcp_nr(T), m);
 }
 
-// x^n for 0 <= n < 32 by binary exponentiation (dependency depth 5 instead of n).
-__device__ __forceinline__ double ipow_small(double x, int n) {
-  double r = 1.0;
-#pragma unroll
-  for (int bit = 0; bit < 5; ++bit) {
-    r *= (n & 1) ? x : 1.0;
-    x *= x;
-    n >>= 1;
-  }
-  return r;
-}
 
 // Index of (t, u, .) inside the Hermite functions of total degree n, ordered
 // t descending then u descending.
@@ -135,14 +148,14 @@ __device__ __forceinline__ void build_R_chains_packed(int L, double p, const dou
                                                double *cube, int S1, int S2, double *work, const uint32_t *uv,
                                                const double *boys, int lane) {
   const double pq = p + q;
-  const double rho = p * q / pq;
+  const double rho = p * q * rcp_nr(pq);
   const double X = P[0] - Q[0], Y = P[1] - Q[1], Z = P[2] - Q[2];
   const double T = rho * (X * X + Y * Y + Z * Z);
   double *f0 = work;                 // [0]^(m), m = 0..L
   double *zb = f0 + (L + 1);         // [00v]^(m) at v*(L+1) + m
   double *yb = zb + (L + 1) * (L + 1);  // [0uv]^(m) at uv_base(u, v) + m
   if (lane <= L) {
-    double f = 2.0 * 17.493418327624862 / (p * q * sqrt(pq));  // Eq. (0m), 17.49.. = pi^{5/2}
+    double f = 2.0 * 17.493418327624862 * rcp_nr(p * q) * rsqrt_nr(pq);  // Eq. (0m), 17.49.. = pi^{5/2}
     f *= ipow_small(-2.0 * rho, lane);
     f0[lane] = f * boys_m(lane, T, boys);
   }
@@ -395,7 +408,7 @@ __device__ __forceinline__ void build_R_exact(double p, const double *P, double 
                                               int lane, const YLanes<LM> &yl) {
   constexpr int W = L + 1, NG = ygroups(L);
   const double pq = p + q;
-  const double rho = p * q / pq;
+  const double rho = p * q * rcp_nr(pq);
   const double X = P[0] - Q[0], Y = P[1] - Q[1], Z = P[2] - Q[2];
   const double T = rho * (X * X + Y * Y + Z * Z);
   double *yb = work;  // [0uv]^(m) at (vbase(v) + u) W + m
@@ -403,7 +416,7 @@ __device__ __forceinline__ void build_R_exact(double p, const double *P, double 
   // m+1; the level-v-1 neighbour is the previous step's DPP result.  Lanes
   // past L sit out (their DPP reads return 0).
   if (lane <= L) {
-    double f = 2.0 * 17.493418327624862 / (p * q * sqrt(pq));  // Eq. (0m), 17.49.. = pi^{5/2}
+    double f = 2.0 * 17.493418327624862 * rcp_nr(p * q) * rsqrt_nr(pq);  // Eq. (0m), 17.49.. = pi^{5/2}
     f *= ipow_small(-2.0 * rho, lane);
     double za = f * boys_m(lane, T, boys), zp = 0.0;
     double *zl = yb + lane;

@@ -134,7 +134,15 @@ std::vector<std::vector<Poly>> solid_harmonics(int lmax) {
 // m, F_m(T) = e^{-T} sum_k (2T)^k / [(2m+1)(2m+3)...(2m+2k+1)], then the
 // downward recursion F_m = (2T F_{m+1} + e^{-T}) / (2m+1).
 std::vector<double> boys_table() {
-  std::vector<double> tab((size_t)kBoysNgrid * kBoysM);
+  std::vector<double> tab((size_t)(kBoysNgrid + 1) * kBoysM);
+  // last row: (2m-1)!! for F_m(T) = (2m-1)!! / (2T)^m F_0(T), T >= kBoysTmax
+  {
+    long double df = 1.0L;
+    for (int m = 0; m < kBoysM; ++m) {
+      tab[(size_t)kBoysNgrid * kBoysM + m] = (double)df;
+      df *= 2 * m + 1;
+    }
+  }
   const int M = kBoysM - 1;
   for (int i = 0; i < kBoysNgrid; ++i) {
     const long double T = (long double)i / kBoysGridPerUnit;

@@ -15,14 +15,15 @@ constexpr int kSplitMin = 5, kSplitMax = 7, kSplitDefault = 6;  // 7-bit slices 
 constexpr int kLtotMax = 4 * kLshell;   // largest total L = la+lb+lc+ld
 constexpr int kNtilMax = (kLtotMax + 1) * (kLtotMax + 2) * (kLtotMax + 3) / 6;
 
-// Boys-function interpolation table: F_m(T_i), T_i = i/16 for i = 0..640
-// (T <= 40), m = 0..33, stored row-major [i][m].  Evaluated on the host in
+// Boys-function interpolation table: F_m(T_i), T_i = i/16 for i = 0..1600
+// (T <= 100), m = 0..33, stored row-major [i][m], then one row holding the
+// double factorials (2m-1)!! of the large-T form.  Evaluated on the host in
 // long double from the positive-term series of F_mmax and downward
 // recursion; see boys_table() in host.hip.
 constexpr int kBoysM = 34;
 constexpr int kBoysGridPerUnit = 16;
-constexpr double kBoysTmax = 40.0;
-constexpr int kBoysNgrid = 641;
+constexpr double kBoysTmax = 100.0;
+constexpr int kBoysNgrid = 1601;
 constexpr int kBoysTaylor = 8;  // Taylor terms around the nearest grid point
 
 // Number of Hermite functions of total degree <= l.
@@ -45,7 +46,7 @@ constexpr uint32_t kPadRow = 0x80000000u;
 
 // Constant device tables owned by a context.
 struct Tables {
-  double *boys = nullptr;        // [kBoysNgrid][kBoysM]
+  double *boys = nullptr;        // [kBoysNgrid + 1][kBoysM]
   uint32_t *herm = nullptr;      // [kNtilMax] (t,u,v), ordered by degree, then t desc, then u desc
   int *solid_start = nullptr;    // [(kLshell+1)*(2*kLshell+1) + 1]: nonzeros of (l, m) start at
                                  //   solid_start[l*(2*kLshell+1) + (m+l)]
