@@ -473,7 +473,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
       const int neq = (si == sj) + (sk == sl);
       const double w = neq == 0 ? 4.0 : neq == 1 ? 2.0 : 1.0;
       const int at = a.atom[tid < 3 ? si : sj];
-      atomicAdd(&a.grad[3 * at + (tid % 3)], w * gsum[tid]);
+      atomicAdd(&a.grad[(size_t)(blockIdx.x % a.gcopies) * a.gstride + 3 * at + (tid % 3)], w * gsum[tid]);
     }
     return;
   }
@@ -590,6 +590,14 @@ __global__ void symmetrize_kernel(int n, const double *__restrict__ in, double *
   out[e] = in[e] + in[c * n + r];
 }
 
+__global__ void sum_copies_kernel(int n, int copies, const double *__restrict__ in, double *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int c = 0; c < copies; ++c) acc += in[(size_t)c * n + i];
+  out[i] = acc;
+}
+
 __global__ void zero_kernel(size_t n, double *__restrict__ x) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
     x[e] = 0.0;
@@ -601,6 +609,12 @@ hipError_t launch_symmetrize(int n, const double *in, double *out, hipStream_t s
   const size_t tot = (size_t)n * n;
   if (!tot) return hipSuccess;
   hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_copies(int n, int copies, const double *in, double *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sum_copies_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, copies, in, out);
   return hipGetLastError();
 }
 

@@ -184,7 +184,7 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 // ---------------------------------------------------------------------------
 enum WsSlot {
   WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_ORDER,
-  WS_KORDER, WS_KTMP, WS_QALL, WS_PAIRS, WS_HS, WS_HEXP, WS_HROW, WS_COUNT
+  WS_KORDER, WS_KTMP, WS_QALL, WS_PAIRS, WS_HS, WS_HEXP, WS_HROW, WS_GPART, WS_COUNT
 };
 
 struct TaskPlan;
@@ -646,6 +646,8 @@ struct Digest {
   // derivatives of sum W (ab|cd) to grad[atom][xyz] (bra pair data in
   // derivative form, Hermite rows up to l_a+l_b+1)
   double *grad = nullptr;
+  int gcopies = 1;  // grad holds gcopies partial copies of 3 natom values
+  int gstride = 0;
   const int *atom = nullptr;
 };
 
@@ -1070,17 +1072,27 @@ extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, const 
   hipStream_t s = (hipStream_t)stream;
   PairSets ps;
   if ((st = select_pairs(c, b, tau, s, ps))) return st;
-  HIP_TRY(launch_zero((size_t)natom * 3, grad, s));
+  // the workgroups add into kGradCopies partial gradients (spread by
+  // workgroup id, so the atomics of many small quartets do not queue on the
+  // same 3 natom addresses), summed into grad at the end
+  constexpr int kGradCopies = 512;
+  void *d_gpart = nullptr;
+  if ((st = ws_get(c, WS_GPART, sizeof(double) * (size_t)kGradCopies * 3 * natom, &d_gpart))) return st;
+  HIP_TRY(launch_zero((size_t)kGradCopies * 3 * natom, (double *)d_gpart, s));
   Digest dg;
   dg.kx = nullptr;
   dg.dm = D;
   dg.nao = nao;
   dg.tau = tau;
-  dg.grad = grad;
+  dg.grad = (double *)d_gpart;
+  dg.gcopies = kGradCopies;
+  dg.gstride = 3 * natom;
   dg.atom = b->dev.atom;
   // every ordered (bra class, ket class) block: each visit supplies the
   // bra-centre derivatives, its swapped visit the ket-centre ones
-  return run_pair_blocks(c, b, ps, dg, true, s);
+  if ((st = run_pair_blocks(c, b, ps, dg, true, s))) return st;
+  HIP_TRY(launch_sum_copies(3 * natom, kGradCopies, (const double *)d_gpart, grad, s));
+  return MDERI_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1774,6 +1786,8 @@ mderi_status run_pair_blocks(mderi_ctx *c, mderi_basis *b, const PairSets &ps, c
     ea.tab = c->tab;
     ea.kx = grad ? nullptr : dg.kx;
     ea.grad = grad ? dg.grad : nullptr;
+    ea.gcopies = dg.gcopies;
+    ea.gstride = dg.gstride;
     ea.atom = grad ? dg.atom : nullptr;
     ea.dm = dg.dm;
     ea.nao = dg.nao;

@@ -132,6 +132,7 @@ struct Eri4Args {
   // per bra primitive pair, the bra rows span |p| <= l_a+l_b+1, and the
   // workgroup adds sum W d(ab|cd)/dA, dB to grad[atom][xyz] (see kgrad)
   double *grad;
+  int gcopies, gstride;           // grad holds gcopies copies of gstride values; workgroup b adds to copy b % gcopies
   const int *atom;                // atom of every shell
   // matrix output (orow != nullptr): (ab, cd) of quartet (ij, kl) goes to
   // V[orow[ij] + ab + ld * (ocol[kl] + cd)] instead of the class-batch layout
@@ -162,6 +163,8 @@ hipError_t launch_schwarz_reduce(int npair, int Nab, const double *D, const int 
 hipError_t launch_symmetrize(int n, const double *in, double *out, hipStream_t s);
 // x[0..n) = 0 with a plain kernel (no memset node, capture-safe).
 hipError_t launch_zero(size_t n, double *x, hipStream_t s);
+// out[i] = sum_c in[c n + i] for i < n, c < copies.
+hipError_t launch_sum_copies(int n, int copies, const double *in, double *out, hipStream_t s);
 // Work split of the fused kernel for one class.
 struct Eri4Plan {
   int npt;    // bra row tiles per consumer wave
