@@ -154,3 +154,38 @@ def test_schwarz_high_l(ctx):
         V = md_matrix.shellset(sh, i, j, i, j)
         ref = np.sqrt(np.max(np.abs(np.diag(V))))
         assert abs(Q[n] - ref) <= 1e-12 * ref, (n, Q[n], ref)
+
+
+def _class_of_total(L):
+    """A class (la lb|lc ld) with la+lb+lc+ld = L, each l <= 6, bra-heavy."""
+    ls = []
+    for _ in range(4):
+        ls.append(min(6, L - sum(ls)))
+    return tuple(ls)
+
+
+@pytest.mark.parametrize("L", list(range(0, 19)))
+def test_every_total_l(ctx, L):
+    """One class for every total L the compiled-per-L [r] builder handles
+    (0..18: its y-stage lane groups and x-chain passes differ per L), with
+    ragged bra/ket counts and mixed contraction, against the matrix-form
+    assembly of the oracle's pinned building blocks."""
+    import torch
+    from tests.ref import md_matrix
+    la, lb, lc, ld = _class_of_total(L)
+    rng = np.random.default_rng(5000 + L)
+    nbra, nket = 2, 3
+    n = nbra + nket
+    ls = [la, lb] * nbra + [lc, ld] * nket
+    K = [1 + (i % 2) for i in range(2 * n)]
+    sh = inputs.random_shells(rng, ls, K, 4.0, 0.1, 30.0)
+    pairs = np.arange(2 * n, dtype=np.int32).reshape(-1, 2)
+    bra, ket = pairs[:nbra], pairs[nbra:]
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    V = ctx.eri4(b, bra, ket)
+    torch.cuda.synchronize()
+    got = V.cpu().numpy()
+    for i, (p0, p1) in enumerate(bra):
+        for k, (q0, q1) in enumerate(ket):
+            ref = md_matrix.shellset(sh, p0, p1, q0, q1)
+            _assert_close(got[i, :, :, k], ref, f"L={L} {(la, lb, lc, ld)} quartet ({i},{k})")
