@@ -58,7 +58,11 @@ __device__ __forceinline__ void with_tiles(int n, F &f) {
 // and their transposes; the transposes are added once at the end
 // (K = K' + K'^T).  A quartet stands for its whole permutation orbit, so
 // every image carries w = 2^-(#coincidences among i=j, k=l, ij=kl).
-__device__ __forceinline__ void kdigest(const Eri4Args &a, const double *v, int ij, int kl, int tid) {
+// The four density blocks are first staged in LDS (one round of global
+// loads for the whole workgroup instead of one per image) in dst, the [r]
+// region, which is free once V is complete; dcap is its size in doubles.
+__device__ __forceinline__ void kdigest(const Eri4Args &a, const double *v, int ij, int kl, int tid, double *dst,
+                                        int dcap) {
   const int si = a.bra_sh[2 * ij], sj = a.bra_sh[2 * ij + 1];
   const int sk = a.ket_sh[2 * kl], sl = a.ket_sh[2 * kl + 1];
   const int na = a.nsa, nb = a.nsb, nc = a.nsc, nd = a.nsd;
@@ -66,14 +70,31 @@ __device__ __forceinline__ void kdigest(const Eri4Args &a, const double *v, int 
   int neq = (si == sj) + (sk == sl) + (a.same_list && ij == kl);
   const double w = neq == 0 ? 1.0 : neq == 1 ? 0.5 : neq == 2 ? 0.25 : 0.125;
   const int Nk = a.Nk;  // nc * nd
-  const double *D = a.dm;
   const size_t n = (size_t)a.nao;
+  // the staged block holds D_ac, D_ad, D_bc and D_bd: rows r < na are AOs
+  // oi + r, rows na.. are oj + (r - na); columns q < nc are ok + q, columns
+  // nc.. are ol + (q - nc)
+  const int nab = na + nb, ncd = nc + nd;
+  const bool staged = nab * ncd <= dcap;
+  if (staged) {
+    for (int e = tid; e < nab * ncd; e += blockDim.x) {
+      const int r = e / ncd, q = e - r * ncd;
+      const int row = r < na ? oi + r : oj + (r - na), colm = q < nc ? ok + q : ol + (q - nc);
+      dst[e] = a.dm[(size_t)row * n + colm];
+    }
+    __syncthreads();
+  }
+  auto Dab = [&](int r, int q) -> double {
+    if (staged) return dst[r * ncd + q];
+    const int row = r < na ? oi + r : oj + (r - na), colm = q < nc ? ok + q : ol + (q - nc);
+    return a.dm[(size_t)row * n + colm];
+  };
   // K_ac += sum_bd v[ab][cd] D_bd
   for (int e = tid; e < na * nc; e += blockDim.x) {
     const int x = e / nc, c = e - x * nc;
     double s = 0.0;
     for (int b = 0; b < nb; ++b)
-      for (int d = 0; d < nd; ++d) s += v[(x * nb + b) * Nk + c * nd + d] * D[(oj + b) * n + ol + d];
+      for (int d = 0; d < nd; ++d) s += v[(x * nb + b) * Nk + c * nd + d] * Dab(na + b, nc + d);
     atomicAdd(&a.kx[(oi + x) * n + ok + c], w * s);
   }
   // K_bc += sum_ad v[ab][cd] D_ad
@@ -81,7 +102,7 @@ __device__ __forceinline__ void kdigest(const Eri4Args &a, const double *v, int 
     const int b = e / nc, c = e - b * nc;
     double s = 0.0;
     for (int x = 0; x < na; ++x)
-      for (int d = 0; d < nd; ++d) s += v[(x * nb + b) * Nk + c * nd + d] * D[(oi + x) * n + ol + d];
+      for (int d = 0; d < nd; ++d) s += v[(x * nb + b) * Nk + c * nd + d] * Dab(x, nc + d);
     atomicAdd(&a.kx[(oj + b) * n + ok + c], w * s);
   }
   // K_ad += sum_bc v[ab][cd] D_bc
@@ -89,7 +110,7 @@ __device__ __forceinline__ void kdigest(const Eri4Args &a, const double *v, int 
     const int x = e / nd, d = e - x * nd;
     double s = 0.0;
     for (int b = 0; b < nb; ++b)
-      for (int c = 0; c < nc; ++c) s += v[(x * nb + b) * Nk + c * nd + d] * D[(oj + b) * n + ok + c];
+      for (int c = 0; c < nc; ++c) s += v[(x * nb + b) * Nk + c * nd + d] * Dab(na + b, c);
     atomicAdd(&a.kx[(oi + x) * n + ol + d], w * s);
   }
   // K_bd += sum_ac v[ab][cd] D_ac
@@ -97,7 +118,7 @@ __device__ __forceinline__ void kdigest(const Eri4Args &a, const double *v, int 
     const int b = e / nd, d = e - b * nd;
     double s = 0.0;
     for (int x = 0; x < na; ++x)
-      for (int c = 0; c < nc; ++c) s += v[(x * nb + b) * Nk + c * nd + d] * D[(oi + x) * n + ok + c];
+      for (int c = 0; c < nc; ++c) s += v[(x * nb + b) * Nk + c * nd + d] * Dab(x, c);
     atomicAdd(&a.kx[(oj + b) * n + ol + d], w * s);
   }
 }
@@ -149,17 +170,9 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     uvsh[e] = (uint32_t)u | ((uint32_t)v << 8) | ((uint32_t)(vb + u) << 16);
   }
   if (GRAD) {
-    // W[ab][cd] = D_ac D_bd + D_ad D_bc (the two distinct pairings of E = tr(D K))
-    const int si = a.bra_sh[2 * ij], sj = a.bra_sh[2 * ij + 1];
-    const int sk = a.ket_sh[2 * kl], sl = a.ket_sh[2 * kl + 1];
-    const int oi = a.ao_off[si], oj = a.ao_off[sj], ok = a.ao_off[sk], ol = a.ao_off[sl];
-    const size_t n = (size_t)a.nao;
-    for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) {
-      const int ab = e / a.Nk, cd = e - ab * a.Nk;
-      const int x = ab / a.nsb, b = ab - x * a.nsb, c = cd / a.nsd, d = cd - c * a.nsd;
-      vsh[e] = a.dm[(oi + x) * n + ok + c] * a.dm[(oj + b) * n + ol + d] +
-               a.dm[(oi + x) * n + ol + d] * a.dm[(oj + b) * n + ok + c];
-    }
+    // the weights W are gathered by the consumer waves after this barrier,
+    // while the producer builds the first [r] (they are read only in the
+    // gradient stage, after the barrier that publishes step 0)
     if (tid < 8) gsum[tid] = 0.0;
   } else {
     for (int e = tid; e < a.Nb * vstride; e += blockDim.x) vsh[e] = 0.0;
@@ -221,15 +234,22 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     const int nat = a.Nb_pad >> 4;
     d4 xacc[NPT];
     double gpart[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (GRAD) {
+      // W[ab][cd] = D_ac D_bd + D_ad D_bc (the two distinct pairings of E = tr(D K))
+      const int si = a.bra_sh[2 * ij], sj = a.bra_sh[2 * ij + 1];
+      const int sk = a.ket_sh[2 * kl], sl = a.ket_sh[2 * kl + 1];
+      const int oi = a.ao_off[si], oj = a.ao_off[sj], ok = a.ao_off[sk], ol = a.ao_off[sl];
+      const size_t n = (size_t)a.nao;
+      for (int e = tid; e < a.Nb * a.Nk; e += 64 * ncons) {
+        const int ab = e / a.Nk, cd = e - ab * a.Nk;
+        const int x = ab / a.nsb, b = ab - x * a.nsb, c = cd / a.nsd, d = cd - c * a.nsd;
+        vsh[e] = a.dm[(oi + x) * n + ok + c] * a.dm[(oj + b) * n + ol + d] +
+                 a.dm[(oi + x) * n + ol + d] * a.dm[(oj + b) * n + ok + c];
+      }
+    }
     for (int n = 0; n < nsteps; ++n) {
       if (!a.dbuf && n > 0) __syncthreads();
-      __syncthreads();
-      const double *cube = (a.dbuf && (n & 1)) ? cube1 : cube0;
       const int ib = n / nkp, ik = n - ib * nkp;
-      if (ik == 0) {
-#pragma unroll
-        for (int pt = 0; pt < NPT; ++pt) xacc[pt] = d4{0.0, 0.0, 0.0, 0.0};
-      }
       // ket transform: X[p][cd] += sum_q [p+q] H_ket[q][cd].  Two register
       // sets of LDS gathers ping-pong one k-step ahead of the MFMAs (the
       // scheduling barriers keep that order); the H_ket values come from
@@ -247,6 +267,16 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
       auto hload = [&](int k) -> double {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(hks, klo * 8, k * kstep * 8, 0));
       };
+      // the first four k-steps of H_ket do not depend on [r]: their loads
+      // are issued before the wait for the producer, which hides them
+      const double h0 = hload(0), h1 = hload(min(1, nks - 1));
+      const double h2 = hload(min(2, nks - 1)), h3 = hload(min(3, nks - 1));
+      __syncthreads();  // [r] of step n published
+      const double *cube = (a.dbuf && (n & 1)) ? cube1 : cube0;
+      if (ik == 0) {
+#pragma unroll
+        for (int pt = 0; pt < NPT; ++pt) xacc[pt] = d4{0.0, 0.0, 0.0, 0.0};
+      }
       // the product over NT = ntw row tiles (compiled for every NT <= NPT)
       auto ket = [&](auto ntc) {
         constexpr int NT = decltype(ntc)::value;
@@ -262,10 +292,10 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
           for (int pt = 0; pt < NT; ++pt) aA[pt] = cube[offp[pt] + oq];
           oq1 = offq[4 * min(1, nks - 1) + g];
           oq2 = offq[4 * min(2, nks - 1) + g];
-          hA = hload(0);
-          hB = hload(min(1, nks - 1));
-          hC = hload(min(2, nks - 1));
-          hD = hload(min(3, nks - 1));
+          hA = h0;
+          hB = h1;
+          hC = h2;
+          hD = h3;
         }
         // The matrix core of a SIMD serves its waves oldest first, so without
         // help the first wave finishes well before the last, which then runs
@@ -479,7 +509,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
   }
 
   if (a.kx) {
-    kdigest(a, vsh, ij, kl, tid);
+    kdigest(a, vsh, ij, kl, tid, smem, (int)(gsh - smem));
     return;
   }
   if (a.diag) {
