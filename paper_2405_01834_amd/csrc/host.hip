@@ -1142,12 +1142,21 @@ uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
 // Host image of the plan's device arrays: every array is appended at a
 // 256-byte aligned offset; device pointers are base + offset once the single
 // allocation exists.
+// Layout of one device allocation: regions of 256-byte aligned offsets.
+// Regions added with host data are kept in `bytes` (zeros in between) for
+// one upload of the leading bytes.size() bytes; regions the device fills
+// (src == nullptr) only advance `size`, so large pair-data regions cost no
+// host memory.
 struct Image {
   std::vector<char> bytes;
+  size_t size = 0;
   size_t add(const void *src, size_t n) {
-    const size_t off = (bytes.size() + 255) & ~(size_t)255;
-    bytes.resize(off + ((n + 255) & ~(size_t)255), 0);
-    if (src && n) memcpy(bytes.data() + off, src, n);
+    const size_t off = (size + 255) & ~(size_t)255;
+    size = off + ((n + 255) & ~(size_t)255);
+    if (src) {
+      bytes.resize(size, 0);
+      if (n) memcpy(bytes.data() + off, src, n);
+    }
     return off;
   }
 };
@@ -1433,10 +1442,10 @@ extern "C" mderi_status mderi_eri3_batch(mderi_ctx_t c, mderi_basis_t b, mderi_b
   TaskPlan *plan = new TaskPlan;
   plan->key = key;
   plan->flags = flags;
-  if (hipMalloc(&plan->dmem, img.bytes.size()) != hipSuccess) {
+  if (hipMalloc(&plan->dmem, img.size) != hipSuccess) {
     (void)hipGetLastError();
     delete plan;
-    return fail(MDERI_ENOMEM, "mderi_eri3_batch: plan of %zu bytes could not be allocated", img.bytes.size());
+    return fail(MDERI_ENOMEM, "mderi_eri3_batch: plan of %zu bytes could not be allocated", img.size);
   }
   char *base = (char *)plan->dmem;
   auto dev = [&](size_t off) { return (void *)(base + off); };
@@ -1481,8 +1490,9 @@ extern "C" mderi_status mderi_eri3_batch(mderi_ctx_t c, mderi_basis_t b, mderi_b
   };
   for (auto &kv : bside) plan->pairs.push_back(pair_args(kv.second, b, false));
   for (auto &kv : aside) plan->pairs.push_back(pair_args(kv.second, aux, true));
-  // upload everything written so far (descriptors and tasks follow)
-  if (hipMemcpy(base, img.bytes.data(), o_blocks, hipMemcpyHostToDevice) != hipSuccess) {
+  // upload the host-written regions (pair lists, offsets, row orders; the
+  // descriptors and tasks follow, the pair data is written by its kernels)
+  if (hipMemcpy(base, img.bytes.data(), img.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
     free_plan(plan);
     return fail(MDERI_EDEVICE, "mderi_eri3_batch: plan upload failed");
   }
@@ -1717,7 +1727,7 @@ mderi_status run_pair_blocks(mderi_ctx *c, mderi_basis *b, const PairSets &ps, c
   }
   mderi_status st;
   void *dmem;
-  if ((st = ws_get(c, WS_PAIRS, img.bytes.size(), &dmem))) return st;
+  if ((st = ws_get(c, WS_PAIRS, img.size, &dmem))) return st;
   char *base = (char *)dmem;
   auto dev = [&](size_t off) { return (void *)(base + off); };
   if ((st = stage_begin(c, meta_bytes))) return st;
