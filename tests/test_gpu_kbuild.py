@@ -50,3 +50,30 @@ def test_kbuild_parity(ctx, seed, natom, shells, spread):
     err = np.max(np.abs(got - ref))
     assert err <= 1e-12 * np.max(np.abs(ref)), (err, np.max(np.abs(ref)))
     assert np.max(np.abs(got - got.T)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_kbuild_workspace_reuse(ctx):
+    """K builds and gradients of two molecules interleaved on one context: the
+    pair-data workspace is reused with stale contents (larger, then smaller,
+    then larger again) and every K still meets the oracle's tolerance."""
+    import torch
+    specs = {"big": (11, 3, ((0, 2), (1, 1), (2, 1), (3, 1)), 3.0),
+             "small": (12, 2, ((0, 1), (1, 1)), 2.0)}
+    mols = {}
+    for name, (seed, natom, shells, spread) in specs.items():
+        sh = _molecule(seed, natom, shells, spread)
+        atom = np.repeat(np.arange(natom), len(shells))  # _molecule lists shells atom by atom
+        b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, atom=atom)
+        C = np.random.default_rng(seed + 100).normal(size=(b.nao(), 3)) / np.sqrt(b.nao())
+        D = C @ C.T
+        ref = oracle.kbuild(oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, 1), D, tau=1e-12)
+        mols[name] = (b, natom, D, ref)
+    for name in ("big", "small", "big", "small"):
+        b, natom, D, ref = mols[name]
+        Dd = torch.tensor(D, device="cuda")
+        g = ctx.kbuild_grad(b, Dd, natom, tau=1e-12)
+        K = ctx.kbuild(b, Dd, tau=1e-12)
+        torch.cuda.synchronize()
+        assert torch.isfinite(g).all()
+        err = np.max(np.abs(K.cpu().numpy() - ref))
+        assert err <= 1e-12 * np.max(np.abs(ref)), (name, err, np.max(np.abs(ref)))
