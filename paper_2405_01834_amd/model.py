@@ -46,10 +46,30 @@ def eri4_flops(la: int, lb: int, lc: int, ld: int, kbra: int, kket: int) -> floa
     return K * (t["r"][2] + t["pq"][2] + t["ket"][2]) + kbra * t["bra"][2]
 
 
+def top_degree(l: int) -> int:
+    """T(l) = (l+1)(l+2)/2 Hermite functions of degree exactly l: by Hobson's
+    theorem the only ones a single solid-harmonic Gaussian expands into."""
+    return (l + 1) * (l + 2) // 2
+
+
 def eri3_flops(la: int, lb: int, lP: int, kbra: int, kaux: int) -> float:
-    """Model FLOPs of one contracted 3-centre shellset (ab|P): the rows of
-    Table md-scheme with the ket a single shell (l_c = l_P, l_d = 0)."""
-    return eri4_flops(la, lb, lP, 0, kbra, kaux)
+    """Model FLOPs of one contracted 3-centre shellset (ab|P) in the order the
+    kernel runs it, auxiliary side first: per primitive triple R_L plus the
+    auxiliary transform over the T_P top-degree rows, [p|P] = sum_q [p|q] H_P
+    (2 Ñ_ab T_P N_P); per pair primitive the pair transform (2 N_ab Ñ_ab N_P):
+        K_ab K_P (R_L + 2 Ñ_ab T_P N_P) + K_ab 2 N_ab Ñ_ab N_P,
+    L = l_a + l_b + l_P.  The pair-first order would count
+    K_ab K_P (R_L + 2 N_ab Ñ_ab T_P) + K_P 2 N_ab T_P N_P instead."""
+    L = la + lb + lP
+    Nhab, Nab, TP, NP = ntil(la + lb), nsph(la) * nsph(lb), top_degree(lP), nsph(lP)
+    return kbra * kaux * (R_L(L) + 2 * Nhab * TP * NP) + kbra * 2 * Nab * Nhab * NP
+
+
+def eri3_flops_pair_first(la: int, lb: int, lP: int, kbra: int, kaux: int) -> float:
+    """The pair-first count of the same shellset (see eri3_flops)."""
+    L = la + lb + lP
+    Nhab, Nab, TP, NP = ntil(la + lb), nsph(la) * nsph(lb), top_degree(lP), nsph(lP)
+    return kbra * kaux * (R_L(L) + 2 * Nab * Nhab * TP) + kaux * 2 * Nab * TP * NP
 
 
 def eri4_outputs(la: int, lb: int, lc: int, ld: int) -> int:
