@@ -71,6 +71,13 @@ def _setup(L):
     L.oracle_schwarz.argtypes = basis + [ctypes.c_int, _ip, _dp, ctypes.c_int]
     L.oracle_kbuild.argtypes = basis + [_dp, ctypes.c_double, _dp, ctypes.c_int]
     L.oracle_exchange_grad.argtypes = basis + [_ip, ctypes.c_int, _dp, ctypes.c_double, _dp, ctypes.c_int]
+    L.oracle_jbuild.argtypes = basis + [_dp, ctypes.c_double, _dp, ctypes.c_int]
+    L.oracle_fock_blocks.argtypes = basis + [_dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _dp,
+                                             ctypes.c_int]
+    L.oracle_grad_pattern.argtypes = basis + [_ip, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_double, _dp,
+                                              ctypes.c_int]
+    for name in ("oracle_jbuild", "oracle_fock_blocks", "oracle_grad_pattern"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("oracle_eri4_cart", "oracle_eri4_deriv", "oracle_eri4", "oracle_eri3", "oracle_schwarz",
                  "oracle_kbuild", "oracle_exchange_grad"):
         getattr(L, name).restype = ctypes.c_int
@@ -242,4 +249,47 @@ def exchange_grad(basis: Basis, atom_of_shell, natom, D, tau=1e-12, nthreads=0) 
     g = np.zeros((natom, 3))
     _check(lib().oracle_exchange_grad(*basis.args(), aop, int(natom), Dp, float(tau), g.ctypes.data_as(_dp),
                                       nthreads), "oracle_exchange_grad")
+    return g
+
+
+def jbuild(basis: Basis, D, tau=1e-12, nthreads=0) -> np.ndarray:
+    """J_ab = sum_cd (ab|cd) D_cd by brute force over every screened ordered quartet."""
+    nao = basis.nao()
+    D, Dp = _d(D)
+    assert D.shape == (nao, nao)
+    J = np.zeros((nao, nao))
+    _check(lib().oracle_jbuild(*basis.args(), Dp, float(tau), J.ctypes.data_as(_dp), nthreads), "oracle_jbuild")
+    return J
+
+
+def fock_blocks(basis: Basis, D, blocks, which="K", tau=1e-12, nthreads=0):
+    """Shell blocks of K (which="K", block (s0, s1) = K[AOs of s0, AOs of s1])
+    or J (which="J") by the brute force restricted to the quartets feeding
+    them.  Returns a list of [N(l_s0), N(l_s1)] arrays."""
+    nao = basis.nao()
+    D, Dp = _d(D)
+    assert D.shape == (nao, nao)
+    blk, bp = _i(np.asarray(blocks).reshape(-1, 2))
+    sizes = [(nsph(int(basis.l[a])), nsph(int(basis.l[b]))) for a, b in blk]
+    out = np.zeros(max(1, sum(x * y for x, y in sizes)))
+    _check(lib().oracle_fock_blocks(*basis.args(), Dp, float(tau), {"K": 0, "J": 1}[which], len(blk), bp,
+                                    out.ctypes.data_as(_dp), nthreads), "oracle_fock_blocks")
+    res, o = [], 0
+    for x, y in sizes:
+        res.append(out[o:o + x * y].reshape(x, y).copy())
+        o += x * y
+    return res
+
+
+def grad_pattern(basis: Basis, atom_of_shell, natom, pattern, Wl, Wr, tau=1e-12, nthreads=0) -> np.ndarray:
+    """dE/dR of E = sum W_abcd (ab|cd), W = Wl_ac Wr_bd (pattern "exchange")
+    or Wl_ab Wr_cd (pattern "coulomb")."""
+    nao = basis.nao()
+    Wl, Wlp = _d(Wl)
+    Wr, Wrp = _d(Wr)
+    assert Wl.shape == Wr.shape == (nao, nao)
+    aos, aop = _i(atom_of_shell)
+    g = np.zeros((natom, 3))
+    _check(lib().oracle_grad_pattern(*basis.args(), aop, int(natom), {"exchange": 0, "coulomb": 1}[pattern], Wlp,
+                                     Wrp, float(tau), g.ctypes.data_as(_dp), nthreads), "oracle_grad_pattern")
     return g

@@ -15,6 +15,9 @@
  *   Eqs. (solid2herm-1/2): Cartesian -> real solid harmonics,
  *                     applied after contraction             -> oracle_solid
  *   Sec. 6 exchange operator, brute force                  -> oracle_kbuild
+ *   Coulomb operator (the J half of the Fock build)        -> oracle_jbuild
+ *   selected shell blocks of K or J                        -> oracle_fock_blocks
+ *   gradient of sum W (ab|cd), exchange or Coulomb weights -> oracle_grad_pattern
  * Nuclear derivatives use d/dA_x [x_A^a e^{-z r_A^2}] =
  * 2 z x_A^{a+1} e^{..} - a x_A^{a-1} e^{..} on Cartesian primitives.
  */
@@ -901,6 +904,262 @@ int oracle_exchange_grad(int nshell, const int *l, const int *nprim, const doubl
                       for (int d = 0; d < Nd; ++d)
                         acc += r[((size_t)(a * Nb + b) * Nc + c) * Nd + d] *
                                D[(size_t)(off[i] + a) * nao + off[k] + c] * D[(size_t)(off[j] + b) * nao + off[m] + d];
+                g[atoms[w] * 3 + x] += acc;
+              }
+          }
+    free(res);
+    dscratch_free(&ds);
+    scratch_free(&s);
+  }
+  memset(grad, 0, sizeof(double) * (size_t)natom * 3);
+  for (int t = 0; t < nthr; ++t)
+    for (int a = 0; a < natom * 3; ++a) grad[a] += gthr[(size_t)t * natom * 3 + a];
+  free(gthr);
+  free(Q);
+  free(off);
+  free(sh);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Coulomb matrix (the other half of the Fock build, Sec. 1 and Sec. 6), */
+/* brute force over every ordered shell quartet like oracle_kbuild:      */
+/*   J_ab = sum_cd (ab|cd) D_cd.                                         */
+/* ------------------------------------------------------------------ */
+int oracle_jbuild(int nshell, const int *l, const int *nprim, const double *exps, const double *coefs,
+                  const double *centers, int normalize, const double *D, double tau, double *J, int nthreads) {
+  oshell *sh;
+  if (build_shells(nshell, l, nprim, exps, coefs, centers, normalize, ORACLE_LMAX - 1, &sh)) return -1;
+  int *off = (int *)malloc(sizeof(int) * (size_t)(nshell > 0 ? nshell : 1));
+  const int nao = basis_offsets(nshell, sh, off);
+  double *Q = (double *)malloc(sizeof(double) * (size_t)nshell * nshell + 8);
+  all_pair_q(nshell, sh, Q, nthreads);
+  memset(J, 0, sizeof(double) * (size_t)nao * nao);
+  const size_t nmax = cart4_size(ORACLE_LMAX - 1, ORACLE_LMAX - 1, ORACLE_LMAX - 1, ORACLE_LMAX - 1);
+  /* one bra pair (i, j) per iteration: each thread owns the J block (i, j) */
+#pragma omp parallel num_threads(max_threads(nthreads))
+  {
+    scratch s;
+    scratch_init(&s);
+    double *buf = (double *)malloc(sizeof(double) * nmax);
+    double *tmp = (double *)malloc(sizeof(double) * nmax);
+    double *res = (double *)malloc(sizeof(double) * nmax);
+#pragma omp for schedule(dynamic, 1)
+    for (long ij = 0; ij < (long)nshell * nshell; ++ij) {
+      const int i = (int)(ij / nshell), j = (int)(ij % nshell);
+      for (int k = 0; k < nshell; ++k)
+        for (int m = 0; m < nshell; ++m) {
+          if (Q[(size_t)i * nshell + j] * Q[(size_t)k * nshell + m] < tau) continue;
+          shell_solid4(&sh[i], &sh[j], &sh[k], &sh[m], res, buf, tmp, &s);
+          const int Na = nsph(sh[i].l), Nb = nsph(sh[j].l), Nc = nsph(sh[k].l), Nd = nsph(sh[m].l);
+          for (int a = 0; a < Na; ++a)
+            for (int b = 0; b < Nb; ++b) {
+              double acc = 0.0;
+              for (int c = 0; c < Nc; ++c)
+                for (int d = 0; d < Nd; ++d)
+                  acc += res[((size_t)(a * Nb + b) * Nc + c) * Nd + d] * D[(size_t)(off[k] + c) * nao + off[m] + d];
+              J[(size_t)(off[i] + a) * nao + off[j] + b] += acc;
+            }
+        }
+    }
+    free(buf);
+    free(tmp);
+    free(res);
+    scratch_free(&s);
+  }
+  free(Q);
+  free(off);
+  free(sh);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Selected shell blocks of K and J, for checks on systems whose full   */
+/* brute force is out of reach.  Block n is the pair (s0, s1) =         */
+/* blocks[2n], blocks[2n+1]:                                             */
+/*   which = 0 (K): out_n[a][c] = sum_{j,m} sum_{b,d} (s0 j|s1 m)_{a b c d} D_bd, */
+/*   which = 1 (J): out_n[a][b] = sum_{k,m} sum_{c,d} (s0 s1|k m)_{a b c d} D_cd, */
+/* over the quartets with Q_ij Q_km >= tau (Q from the diagonal          */
+/* quartets, as everywhere in the oracle).  out holds the blocks one     */
+/* after another, each row-major N(l_s0) x N(l_s1).                      */
+/* ------------------------------------------------------------------ */
+int oracle_fock_blocks(int nshell, const int *l, const int *nprim, const double *exps, const double *coefs,
+                       const double *centers, int normalize, const double *D, double tau, int which, int nblk,
+                       const int *blocks, double *out, int nthreads) {
+  oshell *sh;
+  if (build_shells(nshell, l, nprim, exps, coefs, centers, normalize, ORACLE_LMAX - 1, &sh)) return -1;
+  if (which != 0 && which != 1) {
+    free(sh);
+    return -2;
+  }
+  for (int n = 0; n < nblk; ++n)
+    if (blocks[2 * n] < 0 || blocks[2 * n] >= nshell || blocks[2 * n + 1] < 0 || blocks[2 * n + 1] >= nshell) {
+      free(sh);
+      return -2;
+    }
+  int *off = (int *)malloc(sizeof(int) * (size_t)(nshell > 0 ? nshell : 1));
+  const int nao = basis_offsets(nshell, sh, off);
+  size_t *bo = (size_t *)malloc(sizeof(size_t) * (size_t)(nblk + 1));
+  bo[0] = 0;
+  for (int n = 0; n < nblk; ++n) bo[n + 1] = bo[n] + (size_t)nsph(sh[blocks[2 * n]].l) * nsph(sh[blocks[2 * n + 1]].l);
+  memset(out, 0, sizeof(double) * bo[nblk]);
+  const size_t nmax = cart4_size(ORACLE_LMAX - 1, ORACLE_LMAX - 1, ORACLE_LMAX - 1, ORACLE_LMAX - 1);
+  /* Schwarz factors of every pair that can appear: all (x, y) with x a
+   * block shell (K: both s0 and s1 lead a pair; J: s0 leads the bra pair)
+   * and, for J, all ket pairs (k, m) */
+  double *Q = (double *)malloc(sizeof(double) * (size_t)nshell * nshell + 8);
+  char *need = (char *)calloc((size_t)nshell, 1);
+  for (int n = 0; n < nblk; ++n) {
+    need[blocks[2 * n]] = 1;
+    if (which == 0) need[blocks[2 * n + 1]] = 1;
+  }
+  if (which == 1) {
+    all_pair_q(nshell, sh, Q, nthreads);
+  } else {
+#pragma omp parallel num_threads(max_threads(nthreads))
+    {
+      scratch s;
+      scratch_init(&s);
+      double *buf = (double *)malloc(sizeof(double) * nmax);
+      double *tmp = (double *)malloc(sizeof(double) * nmax);
+      double *res = (double *)malloc(sizeof(double) * nmax);
+#pragma omp for schedule(dynamic, 1)
+      for (long ij = 0; ij < (long)nshell * nshell; ++ij) {
+        const int i = (int)(ij / nshell), j = (int)(ij % nshell);
+        if (need[i]) Q[ij] = pair_q(&sh[i], &sh[j], res, buf, tmp, &s);
+      }
+      free(buf);
+      free(tmp);
+      free(res);
+      scratch_free(&s);
+    }
+  }
+  /* work items: (block, inner shell) -> a private partial, summed in order */
+  const long nwork = (long)nblk * nshell;
+  double *part = (double *)calloc((size_t)nshell * (bo[nblk] > 0 ? bo[nblk] : 1), sizeof(double));
+#pragma omp parallel num_threads(max_threads(nthreads))
+  {
+    scratch s;
+    scratch_init(&s);
+    double *buf = (double *)malloc(sizeof(double) * nmax);
+    double *tmp = (double *)malloc(sizeof(double) * nmax);
+    double *res = (double *)malloc(sizeof(double) * nmax);
+#pragma omp for schedule(dynamic, 1)
+    for (long w = 0; w < nwork; ++w) {
+      const int n = (int)(w / nshell), x = (int)(w % nshell);
+      const int s0 = blocks[2 * n], s1 = blocks[2 * n + 1];
+      double *o = part + (size_t)x * bo[nblk] + bo[n];
+      const int N0 = nsph(sh[s0].l), N1 = nsph(sh[s1].l);
+      for (int y = 0; y < nshell; ++y) {
+        if (which == 0) {
+          /* quartet (s0 x | s1 y): j = x, m = y */
+          if (Q[(size_t)s0 * nshell + x] * Q[(size_t)s1 * nshell + y] < tau) continue;
+          shell_solid4(&sh[s0], &sh[x], &sh[s1], &sh[y], res, buf, tmp, &s);
+          const int Nb = nsph(sh[x].l), Nd = nsph(sh[y].l);
+          for (int a = 0; a < N0; ++a)
+            for (int c = 0; c < N1; ++c) {
+              double acc = 0.0;
+              for (int b = 0; b < Nb; ++b)
+                for (int d = 0; d < Nd; ++d)
+                  acc += res[((size_t)(a * Nb + b) * N1 + c) * Nd + d] * D[(size_t)(off[x] + b) * nao + off[y] + d];
+              o[a * N1 + c] += acc;
+            }
+        } else {
+          /* quartet (s0 s1 | x y): k = x, m = y */
+          if (Q[(size_t)s0 * nshell + s1] * Q[(size_t)x * nshell + y] < tau) continue;
+          shell_solid4(&sh[s0], &sh[s1], &sh[x], &sh[y], res, buf, tmp, &s);
+          const int Nc = nsph(sh[x].l), Nd = nsph(sh[y].l);
+          for (int a = 0; a < N0; ++a)
+            for (int b = 0; b < N1; ++b) {
+              double acc = 0.0;
+              for (int c = 0; c < Nc; ++c)
+                for (int d = 0; d < Nd; ++d)
+                  acc += res[((size_t)(a * N1 + b) * Nc + c) * Nd + d] * D[(size_t)(off[x] + c) * nao + off[y] + d];
+              o[a * N1 + b] += acc;
+            }
+        }
+      }
+    }
+    free(buf);
+    free(tmp);
+    free(res);
+    scratch_free(&s);
+  }
+  for (int x = 0; x < nshell; ++x)
+    for (size_t e = 0; e < bo[nblk]; ++e) out[e] += part[(size_t)x * bo[nblk] + e];
+  free(part);
+  free(need);
+  free(Q);
+  free(bo);
+  free(off);
+  free(sh);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Nuclear gradient of a general weighted sum of integrals               */
+/*   E = sum_abcd W_abcd (ab|cd),                                        */
+/*   pattern 0 (exchange type): W_abcd = Wl_ac Wr_bd  (E = tr(Wl K[Wr])),*/
+/*   pattern 1 (Coulomb type):  W_abcd = Wl_ab Wr_cd  (E = tr(Wl J[Wr])),*/
+/* brute force over every ordered quartet with Q_ij Q_km >= tau, each    */
+/* differentiated on all four centres (grad is [natom][3], overwritten). */
+/* Wl and Wr need not be symmetric.                                      */
+/* ------------------------------------------------------------------ */
+int oracle_grad_pattern(int nshell, const int *l, const int *nprim, const double *exps, const double *coefs,
+                        const double *centers, int normalize, const int *atom_of_shell, int natom, int pattern,
+                        const double *Wl, const double *Wr, double tau, double *grad, int nthreads) {
+  if (pattern != 0 && pattern != 1) return -2;
+  oshell *sh;
+  if (build_shells(nshell, l, nprim, exps, coefs, centers, normalize, ORACLE_LMAX - 1, &sh)) return -1;
+  for (int i = 0; i < nshell; ++i)
+    if (atom_of_shell[i] < 0 || atom_of_shell[i] >= natom) {
+      free(sh);
+      return -1;
+    }
+  int *off = (int *)malloc(sizeof(int) * (size_t)(nshell > 0 ? nshell : 1));
+  const int nao = basis_offsets(nshell, sh, off);
+  double *Q = (double *)malloc(sizeof(double) * (size_t)nshell * nshell + 8);
+  all_pair_q(nshell, sh, Q, nthreads);
+  const int nthr = max_threads(nthreads);
+  double *gthr = (double *)calloc((size_t)nthr * natom * 3, sizeof(double));
+  const size_t ns4max = (size_t)nsph(ORACLE_LMAX - 1) * nsph(ORACLE_LMAX - 1) * nsph(ORACLE_LMAX - 1) *
+                        nsph(ORACLE_LMAX - 1);
+#pragma omp parallel num_threads(nthr)
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    scratch s;
+    scratch_init(&s);
+    dscratch ds;
+    dscratch_init(&ds);
+    double *res = (double *)malloc(sizeof(double) * 12 * ns4max);
+    double *g = gthr + (size_t)tid * natom * 3;
+#pragma omp for schedule(dynamic, 1)
+    for (int i = 0; i < nshell; ++i)
+      for (int j = 0; j < nshell; ++j)
+        for (int k = 0; k < nshell; ++k)
+          for (int m = 0; m < nshell; ++m) {
+            if (Q[(size_t)i * nshell + j] * Q[(size_t)k * nshell + m] < tau) continue;
+            const oshell *sh4[4] = {&sh[i], &sh[j], &sh[k], &sh[m]};
+            shell_solid4_deriv(sh4, res, &ds, &s);
+            const int Na = nsph(sh[i].l), Nb = nsph(sh[j].l), Nc = nsph(sh[k].l), Nd = nsph(sh[m].l);
+            const size_t ns = (size_t)Na * Nb * Nc * Nd;
+            const int atoms[4] = {atom_of_shell[i], atom_of_shell[j], atom_of_shell[k], atom_of_shell[m]};
+            for (int w = 0; w < 4; ++w)
+              for (int x = 0; x < 3; ++x) {
+                const double *r = res + ((size_t)w * 3 + x) * ns;
+                double acc = 0.0;
+                for (int a = 0; a < Na; ++a)
+                  for (int b = 0; b < Nb; ++b)
+                    for (int c = 0; c < Nc; ++c)
+                      for (int d = 0; d < Nd; ++d) {
+                        const int A = off[i] + a, B = off[j] + b, C = off[k] + c, Dd = off[m] + d;
+                        const double wt = pattern == 0 ? Wl[(size_t)A * nao + C] * Wr[(size_t)B * nao + Dd]
+                                                       : Wl[(size_t)A * nao + B] * Wr[(size_t)C * nao + Dd];
+                        acc += r[((size_t)(a * Nb + b) * Nc + c) * Nd + d] * wt;
+                      }
                 g[atoms[w] * 3 + x] += acc;
               }
           }

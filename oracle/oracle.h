@@ -109,6 +109,33 @@ int oracle_exchange_grad(int nshell, const int *l, const int *nprim, const doubl
                          const int *atom_of_shell, int natom,
                          const double *D, double tau, double *grad, int nthreads);
 
+/* Brute-force Coulomb matrix J_ab = sum_cd (ab|cd) D_cd over every ordered
+ * shell quartet with Q_ij*Q_kl >= tau (the other half of the Fock build).
+ * D, J are row-major nao x nao. */
+int oracle_jbuild(int nshell, const int *l, const int *nprim, const double *exps,
+                  const double *coefs, const double *centers, int normalize,
+                  const double *D, double tau, double *J, int nthreads);
+
+/* Selected shell blocks of K (which = 0) or J (which = 1) by the same brute
+ * force, restricted to the quartets that feed them: block n is the shell
+ * pair (blocks[2n], blocks[2n+1]) and receives, row-major,
+ *   K: out[a][c] = sum (s0 j|s1 m) D_jm over all shells j, m,
+ *   J: out[a][b] = sum (s0 s1|k m) D_km over all shells k, m.
+ * Blocks are stored one after another. */
+int oracle_fock_blocks(int nshell, const int *l, const int *nprim, const double *exps,
+                       const double *coefs, const double *centers, int normalize,
+                       const double *D, double tau, int which, int nblk, const int *blocks,
+                       double *out, int nthreads);
+
+/* Brute-force gradient of E = sum_abcd W_abcd (ab|cd) with respect to atom
+ * positions, W_abcd = Wl_ac Wr_bd (pattern 0, exchange: E = tr(Wl K[Wr]))
+ * or Wl_ab Wr_cd (pattern 1, Coulomb: E = tr(Wl J[Wr])); Wl, Wr need not be
+ * symmetric.  grad is [natom][3] and is overwritten. */
+int oracle_grad_pattern(int nshell, const int *l, const int *nprim, const double *exps,
+                        const double *coefs, const double *centers, int normalize,
+                        const int *atom_of_shell, int natom, int pattern,
+                        const double *Wl, const double *Wr, double tau, double *grad, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

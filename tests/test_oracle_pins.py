@@ -504,3 +504,82 @@ def test_matrix_form_reference_matches_oracle():
         ref = oracle.eri4(ob, [q[:2]], [q[2:]])[0, :, :, 0]
         got = md_matrix.shellset(sh, *q)
         assert np.max(np.abs(got - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))), q
+
+
+def test_jbuild_matches_explicit_contraction():
+    """J_ab = sum_cd (ab|cd) D_cd against an einsum over the full ERI tensor,
+    with an unsymmetric D (catches a transposed operand); tr(DJ) >= 0 for a
+    symmetric D (the Coulomb self-energy of a charge distribution)."""
+    rng = np.random.default_rng(15)
+    ls, K, ex, co, cen, atom, pos = _tiny_molecule(rng)
+    b = oracle.Basis(ls, K, ex, co, cen, 1)
+    nao = b.nao()
+    G = _full_eri(b)
+    Dn = rng.normal(size=(nao, nao))
+    Jref = np.einsum("abcd,cd->ab", G, Dn)
+    np.testing.assert_allclose(oracle.jbuild(b, Dn, tau=0.0), Jref, rtol=1e-12, atol=1e-13 * np.max(np.abs(Jref)))
+    Ds = Dn + Dn.T
+    assert np.sum(Ds * oracle.jbuild(b, Ds, tau=0.0)) > 0
+
+
+def test_fock_blocks_match_full_builds():
+    """Shell blocks of K and J from the restricted brute force equal the same
+    blocks of the full builds, with screening active (tau = 1e-4 drops the
+    quartets of distant pairs here, so both must apply the same rule)."""
+    rng = np.random.default_rng(16)
+    ls, K, ex, co, cen, atom, pos = _tiny_molecule(rng, natom=3, spread=9.0)
+    b = oracle.Basis(ls, K, ex, co, cen, 1)
+    nao = b.nao()
+    D = rng.normal(size=(nao, nao))
+    off = np.concatenate([[0], np.cumsum(2 * np.asarray(ls) + 1)])
+    tau = 1e-4
+    Kf, Jf = oracle.kbuild(b, D, tau=tau), oracle.jbuild(b, D, tau=tau)
+    assert np.max(np.abs(Kf - oracle.kbuild(b, D, tau=0.0))) > 0  # screening is active
+    blocks = [(0, 0), (1, 4), (4, 1), (2, len(ls) - 1), (len(ls) - 1, 3)]
+    for which, full in (("K", Kf), ("J", Jf)):
+        got = oracle.fock_blocks(b, D, blocks, which=which, tau=tau)
+        for (s0, s1), blk in zip(blocks, got):
+            ref = full[off[s0]:off[s0 + 1], off[s1]:off[s1 + 1]]
+            np.testing.assert_allclose(blk, ref, rtol=1e-12, atol=1e-14 * np.max(np.abs(full)))
+
+
+@pytest.mark.parametrize("pattern", ["exchange", "coulomb"])
+def test_pattern_gradient_finite_difference(pattern):
+    """dE/dR for E = tr(Wl K[Wr]) (exchange weights Wl_ac Wr_bd) and
+    E = tr(Wl J[Wr]) (Coulomb weights Wl_ab Wr_cd), Wl != Wr and both
+    unsymmetric, against central differences of the oracle's own K and J
+    (h = 1e-4 bohr); translational invariance of the analytic gradient."""
+    rng = np.random.default_rng(21 if pattern == "exchange" else 22)
+    ls, K, ex, co, cen, atom, pos = _tiny_molecule(rng, shells_per_atom=((0, 1), (1, 1), (2, 1)))
+    b = oracle.Basis(ls, K, ex, co, cen, 1)
+    nao = b.nao()
+    Wl, Wr = rng.normal(size=(nao, nao)), rng.normal(size=(nao, nao))
+    g = oracle.grad_pattern(b, atom, len(pos), pattern, Wl, Wr, tau=0.0)
+    scale = np.max(np.abs(g))
+    assert np.max(np.abs(g.sum(axis=0))) < 1e-11 * scale
+    build = oracle.kbuild if pattern == "exchange" else oracle.jbuild
+
+    def energy(p):
+        bb = oracle.Basis(ls, K, ex, co, p[atom], 1)
+        return float(np.sum(Wl * build(bb, Wr, tau=0.0)))
+
+    h = 1e-4
+    for a in range(len(pos)):
+        for x in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[a, x] += h
+            pm[a, x] -= h
+            fd = (energy(pp) - energy(pm)) / (2 * h)
+            assert abs(fd - g[a, x]) < 1e-6 * scale, (a, x, fd, g[a, x])
+
+
+def test_exchange_pattern_is_the_exchange_gradient():
+    """With Wl = Wr = D the exchange-pattern gradient is dE/dR of tr(D K[D])."""
+    rng = np.random.default_rng(23)
+    ls, K, ex, co, cen, atom, pos = _tiny_molecule(rng, shells_per_atom=((0, 1), (1, 1), (2, 1)))
+    b = oracle.Basis(ls, K, ex, co, cen, 1)
+    C = rng.normal(size=(b.nao(), 2))
+    D = C @ C.T
+    g1 = oracle.grad_pattern(b, atom, len(pos), "exchange", D, D, tau=0.0)
+    g0 = oracle.exchange_grad(b, atom, len(pos), D, tau=0.0)
+    np.testing.assert_allclose(g1, g0, rtol=1e-12, atol=1e-13 * np.max(np.abs(g0)))
