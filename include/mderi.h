@@ -131,6 +131,26 @@ mderi_status mderi_eri4(mderi_ctx_t ctx, mderi_basis_t basis, int nbra, const in
                         void *stream);
 
 /*
+ * Allocation-free variant of mderi_eri4, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Arguments, output layout and
+ * results are those of mderi_eri4 (FP64 only; opts->precision must be
+ * MDERI_FP64 and opts->flags 0).  Every device region the call needs (pair
+ * lists, primitive-pair data and transform matrices of both sides) is a
+ * slice of a fixed 64 MiB device array compiled into the library, and its
+ * metadata goes through the 4 MiB pinned staging buffer that mderi_create
+ * allocates; the call itself calls no allocating routine.  A batch that
+ * needs more scratch or staging than that returns MDERI_ESIZE with nothing
+ * enqueued.  All calls on one GPU share that GPU's array (contexts
+ * included), which keeps the last call's contents: calls that overlap on
+ * one GPU (different streams, or different host threads) race and must be
+ * serialised by the caller.
+ */
+mderi_status mderi_eri4_noalloc(mderi_ctx_t ctx, mderi_basis_t basis, int nbra, const int32_t *bra_host, int nket,
+                                const int32_t *ket_host, double *V_dev, size_t V_elems, const mderi_opts *opts,
+                                void *stream);
+
+/*
  * Class batch of 3-centre integrals (ab|P) (Sec. 2: the 1-centre Hermite
  * expansion of Eqs. (E1rr)-(E1-aa); the paper writes them [P|ab]).
  *

@@ -190,6 +190,19 @@ enum WsSlot {
 struct TaskPlan;
 void free_plan(TaskPlan *p);
 
+// Scratch of the allocation-free entry point mderi_eri4_noalloc: every
+// device region of that call (pair lists, primitive-pair data G and the
+// transform matrices H of both sides) is a slice of this file-scope array.
+// Each GPU holds its own copy from the first use of the library until the
+// process ends.  Host code never passes `scratch` itself to a kernel (its
+// name is a host-side stand-in there): mderi_create looks up this device's
+// address once with hipGetSymbolAddress and keeps it in the context.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+// Pinned host staging allocated when a context is created, so that the
+// allocation-free entry point can upload its metadata without allocating.
+constexpr size_t kStageInitBytes = (size_t)4 << 20;
+
 struct mderi_ctx {
   int device = 0;
   Tables tab;
@@ -211,6 +224,7 @@ struct mderi_ctx {
   hipStream_t cap_stream = nullptr;  // stream used to capture graphs
   std::vector<hipStream_t> side;     // side streams of concurrent task-list groups
   uint64_t next_serial = 1;
+  char *scratch = nullptr;  // device address of `scratch` on this context's device
 };
 
 struct mderi_basis {
@@ -318,6 +332,17 @@ extern "C" mderi_status mderi_create(int device, mderi_ctx_t *out) {
     mderi_destroy(c);
     return fail(MDERI_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
   }
+  // this device's copy of the scratch array (the device is current here)
+  if ((e = hipGetSymbolAddress((void **)&c->scratch, HIP_SYMBOL(scratch))) != hipSuccess || !c->scratch) {
+    mderi_destroy(c);
+    return fail(MDERI_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  }
+  if ((e = hipHostMalloc((void **)&c->stage, kStageInitBytes, hipHostMallocDefault)) != hipSuccess) {
+    c->stage = nullptr;
+    mderi_destroy(c);
+    return fail(MDERI_ENOMEM, "pinned staging of %zu bytes: %s", kStageInitBytes, hipGetErrorString(e));
+  }
+  c->stage_cap = kStageInitBytes;
   *out = c;
   g_err.clear();
   return MDERI_OK;
@@ -675,9 +700,12 @@ mderi_status launch_eri4_timed(mderi_ctx *c, const Eri4Args &ea, hipStream_t s) 
 std::vector<std::array<int, 3>> block_candidates(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad,
                                                  int maxpp);
 
+// noalloc: every device region is a slice of the context's scratch array and
+// the metadata goes through the staging buffer as it is (the allocation-free
+// entry point); otherwise regions come from the pooled workspace.
 mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int diag, double *V,
                              const std::vector<int> *extra_idx, void **d_extra_idx, hipStream_t s, int flags = 0,
-                             int precision = 0, int slices = kSplitDefault) {
+                             int precision = 0, int slices = kSplitDefault, bool noalloc = false) {
   const int nbra = (int)bra.off.size() - 1, nket = (int)ket.off.size() - 1;
   const int la = bra.la, lb = bra.lb, lc = ket.la, ld = ket.one_centre ? 0 : ket.lb;
   const int Lb = la + lb, Lk = lc + ld, L = Lb + Lk;
@@ -720,27 +748,41 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   const std::vector<PrimPair> &ppb = bra.pp, &ppk = ket.pp;
   const std::vector<int> &offb = bra.off, &offk = ket.off;
   mderi_status st;
+  size_t scratch_used = 0;
+  auto region = [&](int slot, size_t bytes, void **out) -> mderi_status {
+    if (!noalloc) return ws_get(c, slot, bytes, out);
+    const size_t off = scratch_used;
+    scratch_used += (bytes + 255) & ~(size_t)255;
+    if (scratch_used > kScratchBytes)
+      return fail(MDERI_ESIZE, "class (%d%d|%d%d) with %d x %d pairs needs more than the %zu-byte scratch of the "
+                  "allocation-free entry point", la, lb, lc, ld, nbra, nket, kScratchBytes);
+    *out = c->scratch + off;
+    return MDERI_OK;
+  };
   void *d_ppb, *d_ppk, *d_offb, *d_offk, *d_Gb, *d_Gk, *d_Hb, *d_Hk, *d_border, *d_korder = nullptr;
-  if ((st = ws_get(c, WS_ORDER, sizeof(uint32_t) * border.size(), &d_border)) ||
-      (st = ws_get(c, WS_PP_BRA, sizeof(PrimPair) * ppb.size(), &d_ppb)) ||
-      (st = ws_get(c, WS_PP_KET, sizeof(PrimPair) * ppk.size(), &d_ppk)) ||
-      (st = ws_get(c, WS_OFF_BRA, sizeof(int) * offb.size(), &d_offb)) ||
-      (st = ws_get(c, WS_OFF_KET, sizeof(int) * offk.size(), &d_offk)) ||
-      (st = ws_get(c, WS_G_BRA, sizeof(double) * 4 * ppb.size(), &d_Gb)) ||
-      (st = ws_get(c, WS_G_KET, sizeof(double) * 4 * ppk.size(), &d_Gk)) ||
-      (st = ws_get(c, WS_H_BRA, sizeof(double) * (size_t)Hb_rows * Nb_pad * ppb.size(), &d_Hb)) ||
-      (st = ws_get(c, WS_H_KET, sizeof(double) * (size_t)Nhk_pad * Nk_pad * ppk.size(), &d_Hk)))
+  if ((st = region(WS_ORDER, sizeof(uint32_t) * border.size(), &d_border)) ||
+      (st = region(WS_PP_BRA, sizeof(PrimPair) * ppb.size(), &d_ppb)) ||
+      (st = region(WS_PP_KET, sizeof(PrimPair) * ppk.size(), &d_ppk)) ||
+      (st = region(WS_OFF_BRA, sizeof(int) * offb.size(), &d_offb)) ||
+      (st = region(WS_OFF_KET, sizeof(int) * offk.size(), &d_offk)) ||
+      (st = region(WS_G_BRA, sizeof(double) * 4 * ppb.size(), &d_Gb)) ||
+      (st = region(WS_G_KET, sizeof(double) * 4 * ppk.size(), &d_Gk)) ||
+      (st = region(WS_H_BRA, sizeof(double) * (size_t)Hb_rows * Nb_pad * ppb.size(), &d_Hb)) ||
+      (st = region(WS_H_KET, sizeof(double) * (size_t)Nhk_pad * Nk_pad * ppk.size(), &d_Hk)))
     return st;
-  if (!korder.empty() && (st = ws_get(c, WS_KORDER, sizeof(uint32_t) * korder.size(), &d_korder))) return st;
+  if (!korder.empty() && (st = region(WS_KORDER, sizeof(uint32_t) * korder.size(), &d_korder))) return st;
   void *d_Hs = nullptr, *d_Hexp = nullptr, *d_Hrow = nullptr;
-  if (split && ((st = ws_get(c, WS_HS, sizeof(uint16_t) * slices * (size_t)Nb_pad * Hs_rows * ppb.size(), &d_Hs)) ||
-                (st = ws_get(c, WS_HEXP, sizeof(int) * (size_t)Nb_pad * ppb.size(), &d_Hexp)) ||
-                (st = ws_get(c, WS_HROW, sizeof(int) * (size_t)Hs_rows * ppb.size(), &d_Hrow))))
+  if (split && ((st = region(WS_HS, sizeof(uint16_t) * slices * (size_t)Nb_pad * Hs_rows * ppb.size(), &d_Hs)) ||
+                (st = region(WS_HEXP, sizeof(int) * (size_t)Nb_pad * ppb.size(), &d_Hexp)) ||
+                (st = region(WS_HROW, sizeof(int) * (size_t)Hs_rows * ppb.size(), &d_Hrow))))
     return st;
-  if (extra_idx && (st = ws_get(c, WS_IDX, sizeof(int) * extra_idx->size(), d_extra_idx))) return st;
+  if (extra_idx && (st = region(WS_IDX, sizeof(int) * extra_idx->size(), d_extra_idx))) return st;
   const size_t stage_need = sizeof(PrimPair) * (ppb.size() + ppk.size()) + sizeof(int) * (offb.size() + offk.size()) +
                             (extra_idx ? sizeof(int) * extra_idx->size() : 0) + sizeof(uint32_t) * border.size() +
                             sizeof(uint32_t) * korder.size() + 12 * 256;
+  if (noalloc && stage_need > c->stage_cap)
+    return fail(MDERI_ESIZE, "class batch metadata of %zu bytes exceeds the %zu-byte staging buffer of the "
+                "allocation-free entry point", stage_need, c->stage_cap);
   if ((st = stage_begin(c, stage_need))) return st;
   size_t used = 0;
   if ((st = stage_copy(c, d_ppb, ppb.data(), sizeof(PrimPair) * ppb.size(), s, &used)) ||
@@ -871,6 +913,10 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
     ea.dbuf = bestc[2];
     ea.Nhb_pad = 16 * bestc[0] * bestc[1];
   }
+  if (noalloc) {  // no timing events (creating them could allocate)
+    HIP_TRY(launch_eri4(ea, s));
+    return MDERI_OK;
+  }
   return launch_eri4_timed(c, ea, s);
 }
 
@@ -916,6 +962,26 @@ extern "C" mderi_status mderi_eri4(mderi_ctx_t c, mderi_basis_t b, int nbra, con
   if (flags & ~MDERI_FLAG_AUTOTUNE) return fail(MDERI_EINVAL, "mderi_eri4: unsupported flags 0x%x", flags);
   HIP_TRY(hipSetDevice(c->device));
   return run_class_batch(c, sb, sk, 0, V, nullptr, nullptr, (hipStream_t)stream, flags, precision, slices);
+}
+
+extern "C" mderi_status mderi_eri4_noalloc(mderi_ctx_t c, mderi_basis_t b, int nbra, const int32_t *bra, int nket,
+                                           const int32_t *ket, double *V, size_t V_elems, const mderi_opts *opts,
+                                           void *stream) {
+  if (!c || !b) return fail(MDERI_EINVAL, "mderi_eri4_noalloc: NULL context or basis");
+  if (b->ctx != c) return fail(MDERI_EINVAL, "mderi_eri4_noalloc: basis belongs to another context");
+  if (opts && opts->precision != MDERI_FP64)
+    return fail(MDERI_EUNSUPPORTED, "mderi_eri4_noalloc: precision %d (FP64 only)", opts->precision);
+  if (opts && opts->flags) return fail(MDERI_EINVAL, "mderi_eri4_noalloc: flags 0x%x (none supported)", opts->flags);
+  Side sb{b, 0, 0, false, {}, {}}, sk{b, 0, 0, false, {}, {}};
+  mderi_status st;
+  if ((st = expand_pairs(b, nbra, bra, "bra", &sb.la, &sb.lb, sb.pp, sb.off)) != MDERI_OK) return st;
+  if ((st = expand_pairs(b, nket, ket, "ket", &sk.la, &sk.lb, sk.pp, sk.off)) != MDERI_OK) return st;
+  const size_t need = (size_t)nbra * nsph(sb.la) * nsph(sb.lb) * nsph(sk.la) * nsph(sk.lb) * nket;
+  if (!V) return fail(MDERI_EINVAL, "mderi_eri4_noalloc: NULL output");
+  if (V_elems < need)
+    return fail(MDERI_ESIZE, "mderi_eri4_noalloc: output holds %zu doubles, needs %zu", V_elems, need);
+  HIP_TRY(hipSetDevice(c->device));
+  return run_class_batch(c, sb, sk, 0, V, nullptr, nullptr, (hipStream_t)stream, 0, MDERI_FP64, kSplitDefault, true);
 }
 
 extern "C" mderi_status mderi_eri3(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t aux, int npair, const int32_t *pairs,

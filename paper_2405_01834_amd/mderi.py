@@ -66,6 +66,9 @@ def load_library():
     L.mderi_eri4.argtypes = [_vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
                              ctypes.POINTER(Opts), _vp]
     L.mderi_eri4.restype = ctypes.c_int
+    L.mderi_eri4_noalloc.argtypes = [_vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
+                                     ctypes.POINTER(Opts), _vp]
+    L.mderi_eri4_noalloc.restype = ctypes.c_int
     L.mderi_eri3.argtypes = [_vp, _vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
                              ctypes.POINTER(Opts), _vp]
     L.mderi_eri3.restype = ctypes.c_int
@@ -150,6 +153,19 @@ class Context:
                                          ctypes.byref(opts), _stream_handle(stream)))
         return out[:n].view(len(ket), ncd, nab, len(bra)).permute(3, 2, 1, 0)
 
+    def eri4_noalloc(self, basis: "Basis", bra, ket, out, stream=None):
+        """mderi_eri4_noalloc into the caller's float64 device tensor `out` (no
+        allocation inside the call) -> the same V[ij, ab, cd, kl] view as eri4."""
+        import torch
+        bra = np.ascontiguousarray(np.asarray(bra, dtype=np.int32).reshape(-1, 2))
+        ket = np.ascontiguousarray(np.asarray(ket, dtype=np.int32).reshape(-1, 2))
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        _check(load_library().mderi_eri4_noalloc(self._h, basis._h, len(bra), bra.ctypes.data_as(_ip), len(ket),
+                                                 ket.ctypes.data_as(_ip), _vp(out.data_ptr()), out.numel(), None,
+                                                 _stream_handle(stream)))
+        nab, ncd = basis.pair_dim(bra), basis.pair_dim(ket)
+        n = len(bra) * nab * ncd * len(ket)
+        return out[:n].view(len(ket), ncd, nab, len(bra)).permute(3, 2, 1, 0)
 
     def eri3(self, basis: "Basis", aux: "Basis", pairs, auxidx, out=None, stream=None):
         """Class batch (ab|P) -> torch float64 tensor V[ij, ab, mP, k] (shape
