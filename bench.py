@@ -77,11 +77,25 @@ def make_batch(ctx, l, K, seed=1, npair=NPAIR):
         ncand *= 2
 
 
-def cpu_baseline(batches, wall_per_class=2.5):
-    """The oracle on a bounded sample of every class batch (all host threads)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(batches, outs, wall_per_class=2.5):
+    """The oracle on a bounded sample of every class batch (all host threads,
+    then one thread on a smaller sample); the sample's integrals are also
+    compared element by element with the GPU output of the timed step."""
     import oracle
     nthr = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
-    total_eris, total_time, parts = 0.0, 0.0, []
+    total_eris, total_time, total_time1, parts = 0.0, 0.0, 0.0, []
+    checked, worst, bad = 0, 0.0, 0
     for (l, K), (sh, _, bra, ket, _) in batches.items():
         ob = oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, 1)
         nq_full = len(bra) * len(ket)
@@ -93,17 +107,35 @@ def cpu_baseline(batches, wall_per_class=2.5):
         nb = max(1, min(len(bra), n // len(ket)))
         nk = len(ket) if nb > 1 else max(1, min(len(ket), n))
         t = time.perf_counter()
-        oracle.eri4(ob, bra[:nb], ket[:nk], nthreads=nthr)
+        ref = oracle.eri4(ob, bra[:nb], ket[:nk], nthreads=nthr)
         dt = time.perf_counter() - t
         rate = nb * nk / dt
-        nb4 = (2 * l + 1) ** 4
+        # one thread on about a tenth of that sample
+        n1 = max(1, min(nk, (nb * nk) // (10 * max(1, nb)) or 1))
+        t = time.perf_counter()
+        oracle.eri4(ob, bra[:1], ket[:n1], nthreads=1)
+        rate1 = n1 / max(time.perf_counter() - t, 1e-9)
+        nab = (2 * l + 1) ** 2
+        got = outs[(l, K)].view(len(ket), nab, nab, len(bra)).permute(3, 2, 1, 0)[:nb, :, :, :nk].cpu().numpy()
+        err = np.abs(got - ref)
+        bad += int(np.sum(err > 1e-14 + 1e-12 * np.abs(ref)))
+        checked += ref.size
+        worst = max(worst, float(np.max(err / (1e-14 + 1e-12 * np.abs(ref)))))
+        nb4 = nab * nab
         total_eris += nq_full * nb4
         total_time += nq_full / rate
+        total_time1 += nq_full / rate1
         parts.append(f"{NAMES[l]}K{K}:{nb * nk}q")
-        log(f"cpu oracle [{NAMES[l]}|{NAMES[l]}] K={K}: {nb * nk} quartets in {dt:.2f}s -> {rate:.1f} quartets/s")
+        log(f"cpu oracle [{NAMES[l]}|{NAMES[l]}] K={K}: {nb * nk} quartets in {dt:.2f}s -> {rate:.1f} quartets/s "
+            f"({rate1:.1f} on one thread); parity vs GPU: {int(np.sum(err > 1e-14 + 1e-12 * np.abs(ref)))} of "
+            f"{ref.size} outside 1e-12/1e-14")
     return {"value": total_eris / total_time, "unit": "ERI/s", "cores": nthr, "kind": "oracle",
+            "single_core_value": total_eris / total_time1, "cpu_model": cpu_model(),
             "sample": "oracle FP64 on the first " + ", ".join(parts) +
-                      " quartets of each class batch; full-step time extrapolated per class"}
+                      " quartets of each class batch (single core: about a tenth of each); full-step time "
+                      "extrapolated per class",
+            "parity": {"elements": checked, "outside_tolerance": bad, "worst_err_over_tol": worst,
+                       "tolerance": "|gpu - oracle| <= 1e-14 + 1e-12 |oracle|, GPU output of the last timed step"}}
 
 
 def mixed_precision(ctx, steps):
@@ -195,36 +227,68 @@ def eri3_task_list(ctx, steps, flags):
                         "(l_P in 0..6, K=1); 20-bohr cube, exponents log-U[0.05,500]; one mderi_eri3_batch call"}
 
 
-def backward_forward(ctx, natom, reps=3):
-    """Exchange gradient time / K-build time on a synthetic cluster."""
+def count_quartets(ctx, basis, sh):
+    """Symmetry-unique quartets of the K build and ordered visits of the
+    gradient that pass the screening (Q_ij Q_max >= tau for pairs, Q_ij Q_kl
+    >= tau for quartets), from the GPU's Schwarz factors of all canonical pairs."""
+    import torch
+    l = sh.l
+    i, j = np.nonzero((l[:, None] > l[None, :]) | ((l[:, None] == l[None, :]) &
+                                                   (np.arange(sh.n)[:, None] >= np.arange(sh.n)[None, :])))
+    pairs = np.stack([i, j], axis=1).astype(np.int32)
+    Q = ctx.schwarz(basis, pairs).cpu().numpy()
+    torch.cuda.synchronize()
+    keep = Q * Q.max() >= TAU
+    q = np.sort(Q[keep])
+    ordered = int(np.sum(len(q) - np.searchsorted(q, TAU / q, side="left")))
+    diag = int(np.sum(q * q >= TAU))
+    return (ordered + diag) // 2, ordered, int(keep.sum())
+
+
+def backward_forward(ctx, natom, warm_atoms=12):
+    """Exchange-gradient time over K-build time on the synthetic cluster
+    (inputs.cluster): both calls first run on a small cluster of the same
+    recipe (same kernels), then once each on the full cluster; wall clock
+    around call + synchronisation (host pair selection included)."""
     import torch
     from paper_2405_01834_amd import inputs
+    sw, aw, _, Dw = inputs.cluster(7, warm_atoms)
+    bw = ctx.basis(sw.l, sw.nprim, sw.exps, sw.coefs, sw.centers, atom=aw)
+    Dwd = torch.tensor(Dw, device="cuda")
+    ctx.kbuild(bw, Dwd, tau=TAU)
+    ctx.jkbuild(bw, Dwd, tau=TAU)
+    ctx.kbuild_grad(bw, Dwd, warm_atoms, tau=TAU)
+    torch.cuda.synchronize()
+    bw.close()
     sh, atom, pos, D = inputs.cluster(7, natom)
     basis = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, atom=atom)
     Dd = torch.tensor(D, device="cuda")
-    K = ctx.kbuild(basis, Dd, tau=TAU)
-    g = ctx.kbuild_grad(basis, Dd, natom, tau=TAU)
-    torch.cuda.synchronize()
+    nq, nvis, npair = count_quartets(ctx, basis, sh)
+    log(f"cluster {natom} atoms, {sh.n} shells, {basis.nao()} AOs: {npair} significant pairs, {nq:.4g} unique "
+        f"quartets (K build), {nvis:.4g} ordered visits (gradient)")
 
     def timed(fn):
-        best = float("inf")
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            best = min(best, time.perf_counter() - t)
-        return best
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
 
-    tf = timed(lambda: ctx.kbuild(basis, Dd, tau=TAU, out=K))
-    tb = timed(lambda: ctx.kbuild_grad(basis, Dd, natom, tau=TAU, out=g))
-    log(f"cluster {natom} atoms, {sh.n} shells, {basis.nao()} AOs: K build {tf * 1e3:.1f} ms, "
-        f"gradient {tb * 1e3:.1f} ms, ratio {tb / tf:.2f}")
-    return {"ratio": tb / tf, "forward_ms": tf * 1e3, "backward_ms": tb * 1e3, "atoms": natom,
-            "shells": int(sh.n), "nao": basis.nao(),
+    tf, K = timed(lambda: ctx.kbuild(basis, Dd, tau=TAU))
+    log(f"  K build {tf:.2f} s ({nq / tf:.3e} quartets/s)")
+    tb, g = timed(lambda: ctx.kbuild_grad(basis, Dd, natom, tau=TAU))
+    log(f"  gradient {tb:.2f} s ({nvis / tb:.3e} visits/s), ratio {tb / tf:.2f}")
+    tjk, _ = timed(lambda: ctx.jkbuild(basis, Dd, tau=TAU))
+    log(f"  J+K build {tjk:.2f} s")
+    gs = g.cpu().numpy()
+    return {"ratio": tb / tf, "forward_ms": tf * 1e3, "backward_ms": tb * 1e3, "jk_build_ms": tjk * 1e3,
+            "atoms": natom, "shells": int(sh.n), "nao": basis.nao(), "significant_pairs": npair,
+            "kbuild_quartets": nq, "gradient_visits": nvis, "kbuild_quartets_per_s": nq / tf,
+            "translational_residual": float(np.max(np.abs(gs.sum(axis=0))) / np.max(np.abs(gs))),
             "workload": "synthetic cluster, per atom s4 p3 d2 f1 g1 (K=1, exponents geometric 0.08-2000), "
-                        "rank-100 PSD density, Schwarz 1e-12; forward = K build, backward = dE/dR of tr(DK); "
-                        "best of %d" % reps}
+                        "atoms >= 2 bohr apart in a 30-bohr box at 150 atoms, rank-100 PSD density, Schwarz "
+                        "1e-12; forward = K build, backward = dE/dR of tr(DK); one call each after a warm-up "
+                        "on %d atoms" % warm_atoms}
 
 
 def main():
@@ -239,7 +303,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the per-class autotuning of the 4-centre batches")
     ap.add_argument("--eri3", default="graph+autotune", choices=["graph+autotune", "graph", "plain", "off"],
                     help="mode of the 3-centre task-list measurement")
-    ap.add_argument("--cluster-atoms", type=int, default=12,
+    ap.add_argument("--cluster-atoms", type=int, default=150,
                     help="atoms of the cluster for the backward/forward ratio (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 2 GiB device-to-device copy (calibrates HBM byte counters)")
@@ -358,7 +422,7 @@ def main():
     if args.cluster_atoms > 0:
         rec["backward_forward"] = backward_forward(ctx, args.cluster_atoms)
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(batches, args.cpu_wall)
+        rec["cpu_baseline"] = cpu_baseline(batches, outs, args.cpu_wall)
     print(json.dumps(rec), flush=True)
 
 

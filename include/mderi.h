@@ -62,13 +62,18 @@ typedef struct mderi_basis *mderi_basis_t;
 typedef struct {
   int precision;      /* MDERI_FP64 (all entry points) or MDERI_SPLIT_BF16 (mderi_eri4) */
   double schwarz_tau; /* screening threshold for the K build (default 1e-12) */
-  int flags;          /* MDERI_FLAG_* (mderi_eri3_batch; mderi_eri4 takes MDERI_FLAG_AUTOTUNE) */
+  int flags;          /* MDERI_FLAG_* (mderi_eri3_batch; mderi_eri4 takes MDERI_FLAG_AUTOTUNE;
+                         mderi_kbuild_grad takes MDERI_FLAG_SYMMETRIC) */
   int split_slices;   /* MDERI_SPLIT_BF16: 7-bit slices per operand, 5..7 (0 = default 6) */
-  int reserved[2];
+  int tile_variant;   /* mderi_eri4, FP64: 0 = the planned (or tuned) work split; v > 0 = the v-th of
+                         the splits mderi_eri4_tile_variants counts for the batch */
+  int reserved;
 } mderi_opts;
 
 #define MDERI_FLAG_GRAPH 1    /* capture the call's launches in a hipGraph, replay it on identical calls */
 #define MDERI_FLAG_AUTOTUNE 2 /* choose each class block's kernel tiles by timing the candidates */
+#define MDERI_FLAG_SYMMETRIC 4 /* mderi_kbuild_grad: Wl_dev == Wr_dev and the matrix is symmetric (the
+                                  caller's guarantee); the weights are then gathered from one block */
 
 /* Creates a context on HIP device `device`: uploads the Boys-function
  * interpolation table and the constant Hermite / solid-harmonic tables.
@@ -129,6 +134,16 @@ int mderi_basis_nao(mderi_basis_t basis);
 mderi_status mderi_eri4(mderi_ctx_t ctx, mderi_basis_t basis, int nbra, const int32_t *bra_host, int nket,
                         const int32_t *ket_host, double *V_dev, size_t V_elems, const mderi_opts *opts,
                         void *stream);
+
+/*
+ * Number of work splits (row tiles per wave, row parts, single or double
+ * [r] buffer) the fused kernel supports for the class batch of mderi_eri4
+ * with these pair lists: the candidates MDERI_FLAG_AUTOTUNE times and
+ * opts->tile_variant selects (0 when the class runs on column slabs, where
+ * the split is fixed).  Validation as for mderi_eri4; nothing is enqueued.
+ */
+mderi_status mderi_eri4_tile_variants(mderi_ctx_t ctx, mderi_basis_t basis, int nbra, const int32_t *bra_host,
+                                      int nket, const int32_t *ket_host, int *count);
 
 /*
  * Allocation-free variant of mderi_eri4, for callers that cannot allocate
@@ -201,19 +216,40 @@ mderi_status mderi_schwarz(mderi_ctx_t ctx, mderi_basis_t basis, int npair, cons
                            void *stream);
 
 /*
- * Exchange matrix K_ac = sum_bd (ab|cd) D_bd (Sec. 6, exchange operator; the
- * paper writes K_bc = sum_ad [ab|cd] D_ad, the same operator for symmetric
- * D) over every shell quartet of `basis` that survives Schwarz screening
- * (Q_ij Q_kl >= tau, opts->schwarz_tau, default 1e-12).  Each
- * symmetry-unique quartet is evaluated once and digested into its four
- * independent permutational images.  D_dev and K_dev are row-major
- * nao x nao device matrices over the AOs in shell order (nao must equal
- * mderi_basis_nao); D must be symmetric; K_dev is overwritten.  The call
- * synchronises the stream once (to select significant pairs on the host);
- * the digestion itself is enqueued asynchronously.
+ * Coulomb and exchange matrices of a symmetric density D (Sec. 6: the
+ * exchange operator K_ac = sum_bd (ab|cd) D_bd, written K_bc = sum_ad
+ * [ab|cd] D_ad there, the same operator for symmetric D; the Coulomb matrix
+ * J_ab = sum_cd (ab|cd) D_cd is the other half of the Fock build):
+ * every shell quartet of `basis` that survives Schwarz screening (Q_ij Q_kl
+ * >= tau, opts->schwarz_tau, default 1e-12; Q over canonical shell pairs,
+ * pairs kept when Q_ij Q_max >= tau) is evaluated once, as a
+ * symmetry-unique quartet, and digested into the permutational images of
+ * both matrices.  D_dev, J_dev and K_dev are row-major nao x nao device
+ * matrices over the AOs in shell order (nao must equal mderi_basis_nao);
+ * J_dev or K_dev may be NULL (that matrix is not built), not both; the
+ * matrices built are overwritten.  energy_dev (device, may be NULL)
+ * receives {tr(D J), tr(D K)} (a NULL matrix gives 0).
+ * The call computes the Schwarz factors of all canonical shell pairs on the
+ * stream and synchronises it once, to sort the significant pairs of each
+ * class by Q on the host (so the admissible partners of every pair are a
+ * prefix of the sorted list); everything after that is enqueued
+ * asynchronously.  Work space grows with the number of significant pairs
+ * (pair data of every class in both roles).  Sums of the images use FP64
+ * atomics, so the last bits of J and K vary from run to run.
  */
+mderi_status mderi_jkbuild(mderi_ctx_t ctx, mderi_basis_t basis, const double *D_dev, double *J_dev, double *K_dev,
+                           int nao, double *energy_dev, const mderi_opts *opts, void *stream);
+
+/* mderi_jkbuild for K alone (J_dev = NULL, no energies). */
 mderi_status mderi_kbuild(mderi_ctx_t ctx, mderi_basis_t basis, const double *D_dev, double *K_dev, int nao,
                           const mderi_opts *opts, void *stream);
+
+/* Replaces the shell centres of a basis by centers_dev[nshell][3] (device,
+ * bohr), copied on `stream` (asynchronous, the caller keeps centers_dev
+ * alive until the stream reaches the copy).  Later calls on that stream
+ * see the new geometry; shells, exponents, coefficients and the atom map
+ * stay. */
+mderi_status mderi_basis_set_centers(mderi_basis_t basis, const double *centers_dev, void *stream);
 
 /*
  * Kernel timing (measurement support, not part of the method).  While
@@ -228,22 +264,32 @@ mderi_status mderi_kbuild(mderi_ctx_t ctx, mderi_basis_t basis, const double *D_
 mderi_status mderi_kernel_timing(mderi_ctx_t ctx, int enable);
 mderi_status mderi_kernel_times(mderi_ctx_t ctx, double *ms_host, int cap, int *count);
 
+/* Weight patterns of mderi_kbuild_grad. */
+#define MDERI_EXCHANGE 0 /* W_abcd = Wl_ac Wr_bd: E = tr(Wl^T K[Wr]) */
+#define MDERI_COULOMB 1  /* W_abcd = Wl_ab Wr_cd: E = tr(Wl^T J[Wr]) */
+
 /*
- * Nuclear gradient of the exchange energy E = tr(D K[D]) =
- * sum_abcd D_ac (ab|cd) D_bd (the adjoint of mderi_kbuild; the paper gives
- * no gradient, the derivative follows from differentiating the Gaussians of
- * Sec. 2: d/dA_x of x_A^{a} e^{-zeta r_A^2} is 2 zeta x_A^{a+1} e^{..} minus
- * a_x x_A^{a-1} e^{..}, so the MD path runs with bra Hermite degree
- * l_a+l_b+1 and R up to L+1).
- * D is held fixed: grad_dev[natom][3] (device, row-major, overwritten)
- * receives dE/dR_atom summed over the shells of each atom (the atom map given
- * to mderi_basis_upload; natom must exceed every atom index).  Screening,
- * D_dev layout and synchronisation are as for mderi_kbuild; D must be
- * symmetric.  Each quartet of canonical shell pairs is evaluated twice, once
- * per side, for the derivatives of its bra centres.
+ * Nuclear gradient of E = scale * sum_abcd W_abcd (ab|cd) over every AO
+ * quadruple of the screened quartets of mderi_jkbuild, W given by
+ * `pattern` from the row-major nao x nao device matrices Wl_dev and Wr_dev
+ * (need not be symmetric).  The paper gives no gradient; the derivative
+ * follows from differentiating the Gaussians of Sec. 2: d/dA_x of
+ * x_A^{a} e^{-zeta r_A^2} is 2 zeta x_A^{a+1} e^{..} minus a_x x_A^{a-1}
+ * e^{..}, so the MD path runs with A-side Hermite degree l_a+l_b+1 and R up
+ * to L+1 and W held fixed.  Each quartet of canonical shell pairs is
+ * visited once per orientation and supplies the derivatives of its first
+ * pair's two centres, weighted by the summed weights of every AO ordering
+ * that maps onto it.  grad_dev[natom][3] (device, row-major) receives
+ * dE/dR_atom summed over the shells of each atom (the atom map given to
+ * mderi_basis_upload; natom must exceed every atom index); accumulate = 0
+ * overwrites it, 1 adds to it.  The exchange energy of mderi_jkbuild,
+ * tr(D K[D]), is pattern MDERI_EXCHANGE with Wl = Wr = D and scale 1; its
+ * Coulomb energy tr(D J[D]) is MDERI_COULOMB with Wl = Wr = D.
+ * Synchronisation and screening as for mderi_jkbuild.
  */
-mderi_status mderi_kbuild_grad(mderi_ctx_t ctx, mderi_basis_t basis, const double *D_dev, int nao, double *grad_dev,
-                               int natom, const mderi_opts *opts, void *stream);
+mderi_status mderi_kbuild_grad(mderi_ctx_t ctx, mderi_basis_t basis, int pattern, const double *Wl_dev,
+                               const double *Wr_dev, int nao, double scale, double *grad_dev, int natom, int accumulate,
+                               const mderi_opts *opts, void *stream);
 
 #ifdef __cplusplus
 }

@@ -51,84 +51,11 @@ __device__ __forceinline__ void with_tiles(int n, F &f) {
   }
 }
 
-// Exchange digestion of one shellset (ab|cd) held in LDS as v[ab][cd]
-// (Sec. 6, K = sum (ab|cd) D): with K_ac = sum_bd (ab|cd) D_bd, the eight
-// index permutations of a unique shell quartet give the images
-//   K_ac += v D_bd, K_bc += v D_ad, K_ad += v D_bc, K_bd += v D_ac
-// and their transposes; the transposes are added once at the end
-// (K = K' + K'^T).  A quartet stands for its whole permutation orbit, so
-// every image carries w = 2^-(#coincidences among i=j, k=l, ij=kl).
-// The four density blocks are first staged in LDS (one round of global
-// loads for the whole workgroup instead of one per image) in dst, the [r]
-// region, which is free once V is complete; dcap is its size in doubles.
-__device__ __forceinline__ void kdigest(const Eri4Args &a, const double *v, int ij, int kl, int tid, double *dst,
-                                        int dcap) {
-  const int si = a.bra_sh[2 * ij], sj = a.bra_sh[2 * ij + 1];
-  const int sk = a.ket_sh[2 * kl], sl = a.ket_sh[2 * kl + 1];
-  const int na = a.nsa, nb = a.nsb, nc = a.nsc, nd = a.nsd;
-  const int oi = a.ao_off[si], oj = a.ao_off[sj], ok = a.ao_off[sk], ol = a.ao_off[sl];
-  int neq = (si == sj) + (sk == sl) + (a.same_list && ij == kl);
-  const double w = neq == 0 ? 1.0 : neq == 1 ? 0.5 : neq == 2 ? 0.25 : 0.125;
-  const int Nk = a.Nk;  // nc * nd
-  const size_t n = (size_t)a.nao;
-  // the staged block holds D_ac, D_ad, D_bc and D_bd: rows r < na are AOs
-  // oi + r, rows na.. are oj + (r - na); columns q < nc are ok + q, columns
-  // nc.. are ol + (q - nc)
-  const int nab = na + nb, ncd = nc + nd;
-  const bool staged = nab * ncd <= dcap;
-  if (staged) {
-    for (int e = tid; e < nab * ncd; e += blockDim.x) {
-      const int r = e / ncd, q = e - r * ncd;
-      const int row = r < na ? oi + r : oj + (r - na), colm = q < nc ? ok + q : ol + (q - nc);
-      dst[e] = a.dm[(size_t)row * n + colm];
-    }
-    __syncthreads();
-  }
-  auto Dab = [&](int r, int q) -> double {
-    if (staged) return dst[r * ncd + q];
-    const int row = r < na ? oi + r : oj + (r - na), colm = q < nc ? ok + q : ol + (q - nc);
-    return a.dm[(size_t)row * n + colm];
-  };
-  // K_ac += sum_bd v[ab][cd] D_bd
-  for (int e = tid; e < na * nc; e += blockDim.x) {
-    const int x = e / nc, c = e - x * nc;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b)
-      for (int d = 0; d < nd; ++d) s += v[(x * nb + b) * Nk + c * nd + d] * Dab(na + b, nc + d);
-    atomicAdd(&a.kx[(oi + x) * n + ok + c], w * s);
-  }
-  // K_bc += sum_ad v[ab][cd] D_ad
-  for (int e = tid; e < nb * nc; e += blockDim.x) {
-    const int b = e / nc, c = e - b * nc;
-    double s = 0.0;
-    for (int x = 0; x < na; ++x)
-      for (int d = 0; d < nd; ++d) s += v[(x * nb + b) * Nk + c * nd + d] * Dab(x, nc + d);
-    atomicAdd(&a.kx[(oj + b) * n + ok + c], w * s);
-  }
-  // K_ad += sum_bc v[ab][cd] D_bc
-  for (int e = tid; e < na * nd; e += blockDim.x) {
-    const int x = e / nd, d = e - x * nd;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b)
-      for (int c = 0; c < nc; ++c) s += v[(x * nb + b) * Nk + c * nd + d] * Dab(na + b, c);
-    atomicAdd(&a.kx[(oi + x) * n + ol + d], w * s);
-  }
-  // K_bd += sum_ac v[ab][cd] D_ac
-  for (int e = tid; e < nb * nd; e += blockDim.x) {
-    const int b = e / nd, d = e - b * nd;
-    double s = 0.0;
-    for (int x = 0; x < na; ++x)
-      for (int c = 0; c < nc; ++c) s += v[(x * nb + b) * Nk + c * nd + d] * Dab(x, c);
-    atomicAdd(&a.kx[(oj + b) * n + ol + d], w * s);
-  }
-}
-
 // One shell quartet (ij, kl) by the whole workgroup.  Waves beyond the
 // block's nct * nps consumers and its producer (a task-list launch sizes the
 // workgroup for its largest block) only take part in the barriers.
 template <int NPT, int LM, int MODE>
 __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, int slab, double *smem, uint32_t tk) {
-  constexpr bool GRAD = MODE == 1;   // gradient mode (see the derivative step)
   constexpr bool SPLIT = MODE >= 2;  // split-precision bra transform with S = MODE + 3 slices
   constexpr int S = MODE + 3;
   const int L = a.L;
@@ -143,8 +70,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
   double *cube1 = a.dbuf ? smem + cube_sz : smem;
   double *work = smem + (a.dbuf ? 2 : 1) * cube_sz;  // R-chain work area of the producer
   double *gsh = work + rr_work_size(L);              // G of this quartet's bra then ket primitive pairs
-  double *gsum = gsh + 4 * a.maxpp;                  // 8 gradient partial sums
-  double *vsh = gsum + 8;                            // V[ab][cd] (or the weights W) of this quartet
+  double *vsh = gsh + 4 * a.maxpp;                   // V[ab][cd] of this quartet
   uint32_t *uvsh = (uint32_t *)(vsh + a.Nb * vstride);  // (u, v, y slot) of the pairs u+v <= L, by u+v
   int *offq = (int *)(uvsh + (L + 1) * (L + 2) / 2);
 
@@ -169,14 +95,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     (void)ylayout(L, v, &vb);
     uvsh[e] = (uint32_t)u | ((uint32_t)v << 8) | ((uint32_t)(vb + u) << 16);
   }
-  if (GRAD) {
-    // the weights W are gathered by the consumer waves after this barrier,
-    // while the producer builds the first [r] (they are read only in the
-    // gradient stage, after the barrier that publishes step 0)
-    if (tid < 8) gsum[tid] = 0.0;
-  } else {
-    for (int e = tid; e < a.Nb * vstride; e += blockDim.x) vsh[e] = 0.0;
-  }
+  for (int e = tid; e < a.Nb * vstride; e += blockDim.x) vsh[e] = 0.0;
   for (int q = tid; q < a.Nhk_pad; q += blockDim.x) {
     int o = 0;
     const uint32_t h = a.korder ? a.korder[q] : (q < a.Nhk ? a.tab.herm[q] : kPadRow);
@@ -233,20 +152,6 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     const int blo = g * a.Nb_pad + c;
     const int nat = a.Nb_pad >> 4;
     d4 xacc[NPT];
-    double gpart[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (GRAD) {
-      // W[ab][cd] = D_ac D_bd + D_ad D_bc (the two distinct pairings of E = tr(D K))
-      const int si = a.bra_sh[2 * ij], sj = a.bra_sh[2 * ij + 1];
-      const int sk = a.ket_sh[2 * kl], sl = a.ket_sh[2 * kl + 1];
-      const int oi = a.ao_off[si], oj = a.ao_off[sj], ok = a.ao_off[sk], ol = a.ao_off[sl];
-      const size_t n = (size_t)a.nao;
-      for (int e = tid; e < a.Nb * a.Nk; e += 64 * ncons) {
-        const int ab = e / a.Nk, cd = e - ab * a.Nk;
-        const int x = ab / a.nsb, b = ab - x * a.nsb, c = cd / a.nsd, d = cd - c * a.nsd;
-        vsh[e] = a.dm[(oi + x) * n + ok + c] * a.dm[(oj + b) * n + ol + d] +
-                 a.dm[(oi + x) * n + ol + d] * a.dm[(oj + b) * n + ok + c];
-      }
-    }
     for (int n = 0; n < nsteps; ++n) {
       if (!a.dbuf && n > 0) __syncthreads();
       const int ib = n / nkp, ik = n - ib * nkp;
@@ -315,14 +220,14 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int pt = 0; pt < NT; ++pt)
-            xacc[pt] = GRAD ? mfma16x16x4(hA, aA[pt], xacc[pt]) : mfma16x16x4(aA[pt], hA, xacc[pt]);
+            xacc[pt] = mfma16x16x4(aA[pt], hA, xacc[pt]);
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int pt = 0; pt < NT; ++pt) aA[pt] = cube[offp[pt] + oq2];
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int pt = 0; pt < NT; ++pt)
-            xacc[pt] = GRAD ? mfma16x16x4(hB, aB[pt], xacc[pt]) : mfma16x16x4(aB[pt], hB, xacc[pt]);
+            xacc[pt] = mfma16x16x4(aB[pt], hB, xacc[pt]);
           __builtin_amdgcn_sched_barrier(0);
           oq1 = on1;
           oq2 = on2;
@@ -334,50 +239,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
       };
       if (ntw == NPT) ket(Tiles<NPT>{});
       else with_tiles<NPT - 1>(ntw, ket);
-      if (GRAD && ik == nkp - 1) {
-        // Gradient mode keeps X transposed (the ket step above swaps the MFMA
-        // operands): register r of lane c + 16 g holds X^T[cd][p] with
-        // cd = 16 ct + 4 r + g and p the c-th row of tile pt.  The weighted
-        // derivative sum_ab,cd W[ab][cd] sum_p H^(X,x)[p][ab] X[p][cd] is
-        // sum_p,ab H^(X,x)[p][ab] Y[p][ab] with Y = X W^T: one MFMA product
-        // (Y^T = W X^T over this wave's 16 cd) and six elementwise dots.
-        const int mstride = a.Hb_rows * a.Nb_pad;  // doubles per derivative matrix
-        // buffer loads: one resource per bra primitive pair, the per-lane part
-        // of the offset in a VGPR and the (tile, matrix, row) part in an SGPR,
-        // so no per-combination addresses stay live across the ab loop
-        const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(a.bra_H + (size_t)(bp0 + ib) * 6 * mstride), (short)0, 6 * mstride * 8, kBufferWord3);
-        const int cd0 = ct * 16 + g;
-#pragma unroll 1
-        for (int at = 0; at < nat; ++at) {
-          const int abw = at * 16 + c;  // W row read by this lane
-          double w[4];
-#pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) {
-            const int cd = cd0 + 4 * s4;
-            w[s4] = (abw < a.Nb && cd < a.Nk) ? vsh[abw * a.Nk + cd] : 0.0;
-          }
-          // this lane's element of the [mat][ab][p] derivative matrices:
-          // ab = 16 at + g (+ 4 r), p = 16 t0 (+ 16 pt) + c
-          const int vo = 8 * (t0 * 16 + c + (at * 16 + g) * a.Hb_rows);
-#pragma unroll
-          for (int pt = 0; pt < NPT; ++pt) {
-            d4 y = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) y = mfma16x16x4(w[s4], xacc[pt][s4], y);
-            // y[r] = Y^T[ab = 16 at + 4 r + g][p = row c of tile pt]
-#pragma unroll
-            for (int mat = 0; mat < 6; ++mat)
-#pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int so = 8 * (mat * mstride + pt * 16 + 4 * r * a.Hb_rows);
-                const double h =
-                    __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(hrs, vo, so, 0));
-                gpart[mat] += y[r] * h;
-              }
-          }
-        }
-      } else if (SPLIT && ik == nkp - 1) {
+      if (SPLIT && ik == nkp - 1) {
         // Split-precision bra transform on the BF16 matrix cores.  After row
         // balancing, with a power-of-two exponent per column of X over this
         // wave's rows (fx)
@@ -481,37 +343,9 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
         }
       }
     }
-    if (GRAD) {
-#pragma unroll
-      for (int m = 0; m < 6; ++m) {
-        double x = gpart[m];
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-        if (lane == 0) atomicAdd(&gsum[m], x);
-      }
-    }
   }
   __syncthreads();  // V complete in LDS
 
-  if (GRAD) {
-    if (tid < 6) {
-      const int si = a.bra_sh[2 * ij], sj = a.bra_sh[2 * ij + 1];
-      const int sk = a.ket_sh[2 * kl], sl = a.ket_sh[2 * kl + 1];
-      // E = sum over ordered combinations (bra pair, ket pair) of canonical
-      // pairs of 2^(1-#(i=j)-#(k=l)) sum W (ab|cd).  The ket-centre terms of
-      // visit (p, q) equal the bra-centre terms of visit (q, p), so each visit
-      // adds twice its bra-centre derivatives.
-      const int neq = (si == sj) + (sk == sl);
-      const double w = neq == 0 ? 4.0 : neq == 1 ? 2.0 : 1.0;
-      const int at = a.atom[tid < 3 ? si : sj];
-      atomicAdd(&a.grad[(size_t)(blockIdx.x % a.gcopies) * a.gstride + 3 * at + (tid % 3)], w * gsum[tid]);
-    }
-    return;
-  }
-
-  if (a.kx) {
-    kdigest(a, vsh, ij, kl, tid, smem, (int)(gsh - smem));
-    return;
-  }
   if (a.diag) {
     // (ab|ab) for the ab that fall in this workgroup's column slab
     for (int cl = tid; cl < vcols; cl += blockDim.x) {
@@ -539,19 +373,12 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
 // One workgroup per quartet of one class batch.
 template <int NPT, int LM, int MODE>
 __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
-  constexpr bool GRAD = MODE == 1;
   extern __shared__ double smem[];
   const long G = (a.diag ? (long)a.nbra : (long)a.nbra * a.nket) * a.nslab;
   const long v0 = xcd_remap(blockIdx.x, G);
   const int slab = (int)(v0 % a.nslab);  // slabs of one quartet are neighbours (shared bra data)
   const long v = v0 / a.nslab;
   const int ij = (int)(v % a.nbra), kl = a.diag ? ij : (int)(v / a.nbra);
-  if (a.kx) {
-    // screened or symmetry-redundant quartet: the whole workgroup leaves
-    // before any barrier
-    if (a.bra_q[ij] * a.ket_q[kl] < a.tau || (a.same_list && ij < kl)) return;
-  }
-  if (GRAD && a.bra_q[ij] * a.ket_q[kl] < a.tau) return;
   eri4_quartet<NPT, LM, MODE>(a, ij, kl, slab, smem, a.wtask[threadIdx.x >> 6]);
 }
 
@@ -611,7 +438,7 @@ __global__ void schwarz_reduce_kernel(int npair, int Nab, const double *__restri
 }
 
 // p tiles per consumer wave that are built.
-const int kTiles[] = {1, 2, 3, 4, 6, 7};
+const int kTiles[] = {1, 2, 3, 4, 6};
 
 __global__ void symmetrize_kernel(int n, const double *__restrict__ in, double *__restrict__ out) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -620,12 +447,52 @@ __global__ void symmetrize_kernel(int n, const double *__restrict__ in, double *
   out[e] = in[e] + in[c * n + r];
 }
 
-__global__ void sum_copies_kernel(int n, int copies, const double *__restrict__ in, double *__restrict__ out) {
+__global__ void sum_copies_kernel(int n, int copies, const double *__restrict__ in, double *__restrict__ out,
+                                  int accumulate) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double acc = 0.0;
   for (int c = 0; c < copies; ++c) acc += in[(size_t)c * n + i];
-  out[i] = acc;
+  out[i] = accumulate ? out[i] + acc : acc;
+}
+
+// part[b] = sum of a[e] b1[e] (and a[e] b2[e]) over this block's stride of e
+// (fixed order per block: the traces are deterministic)
+constexpr int kDotBlocks = 512;
+__global__ void __launch_bounds__(256) dot_partial_kernel(size_t n, const double *__restrict__ a,
+                                                          const double *__restrict__ b1, const double *__restrict__ b2,
+                                                          double *__restrict__ part) {
+  __shared__ double s1[256], s2[256];
+  double x1 = 0.0, x2 = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    if (b1) x1 = fma(a[e], b1[e], x1);
+    if (b2) x2 = fma(a[e], b2[e], x2);
+  }
+  s1[threadIdx.x] = x1;
+  s2[threadIdx.x] = x2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      s1[threadIdx.x] += s1[threadIdx.x + h];
+      s2[threadIdx.x] += s2[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s1[0];
+    part[kDotBlocks + blockIdx.x] = s2[0];
+  }
+}
+
+__global__ void dot_final_kernel(const double *__restrict__ part, double *__restrict__ out) {
+  __shared__ double s[2][kDotBlocks];
+  for (int e = threadIdx.x; e < 2 * kDotBlocks; e += blockDim.x) s[e / kDotBlocks][e % kDotBlocks] = part[e];
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double acc = 0.0;
+    for (int b = 0; b < kDotBlocks; ++b) acc += s[threadIdx.x][b];
+    out[threadIdx.x] = acc;
+  }
 }
 
 __global__ void zero_kernel(size_t n, double *__restrict__ x) {
@@ -642,9 +509,18 @@ hipError_t launch_symmetrize(int n, const double *in, double *out, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_sum_copies(int n, int copies, const double *in, double *out, hipStream_t s) {
+hipError_t launch_sum_copies(int n, int copies, const double *in, double *out, hipStream_t s, int accumulate) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sum_copies_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, copies, in, out);
+  hipLaunchKernelGGL(sum_copies_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, copies, in, out, accumulate);
+  return hipGetLastError();
+}
+
+size_t dot2_work_doubles() { return 2 * kDotBlocks; }
+
+hipError_t launch_dot2(size_t n, const double *a, const double *b1, const double *b2, double *work, double *out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(kDotBlocks), dim3(256), 0, s, n, a, b1, b2, work);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(64), 0, s, (const double *)work, out);
   return hipGetLastError();
 }
 
@@ -664,7 +540,7 @@ hipError_t launch_schwarz_reduce(int npair, int Nab, const double *D, const int 
 static size_t cube_region(int cube_sz, int ncube) { return sizeof(double) * (size_t)cube_sz * ncube; }
 
 static size_t side_bytes(int L, int maxpp, int Nhk_pad, int Nb, int Nk) {
-  return sizeof(double) * ((size_t)rr_work_size(L) + 4 * (size_t)maxpp + 8 + (size_t)Nb * Nk) +
+  return sizeof(double) * ((size_t)rr_work_size(L) + 4 * (size_t)maxpp + (size_t)Nb * Nk) +
          sizeof(uint32_t) * (size_t)((L + 1) * (L + 2) / 2) + sizeof(int) * (size_t)Nhk_pad;
 }
 
@@ -717,27 +593,26 @@ void eri4_fill_wtask(Eri4Args &a) {
   }
 }
 
-bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int maxpp, bool grad, bool slabs,
-               Eri4Plan *p) {
+bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int maxpp, bool slabs, Eri4Plan *p) {
   if (L > 26) return false;
   const int need_p = round16(Nhb) / 16, nct_all = round16(Nk) / 16;
   const size_t lds_budget = 160 * 1024;
   // Preferred: all ket columns in one workgroup, bra rows split over `parts`
-  // waves of at most 6 tiles each (7 in gradient mode, which is built for
-  // the [gg| bra of Hermite degree 9).  When that does not fit the wave or
-  // LDS limits and `slabs` is allowed, the ket columns are split into slabs
-  // of nct tiles handled by separate workgroups.
+  // waves of at most 6 tiles each.  When that does not fit the wave or LDS
+  // limits and `slabs` is allowed, the ket columns are split into slabs of
+  // nct tiles handled by separate workgroups.
   for (int nslab = 1; nslab <= (slabs ? nct_all : 1); ++nslab) {
     const int nct = (nct_all + nslab - 1) / nslab;
     if (nslab > 1 && (nct_all + nct - 1) / nct != nslab) continue;  // same split as a smaller nslab
-    for (int maxt = 6; maxt <= (grad ? 7 : 6); ++maxt) {
+    {
+      const int maxt = 6;
       int parts = 1;
       while ((need_p + parts - 1) / parts > maxt) ++parts;
       const int per = (need_p + parts - 1) / parts;
       if (nct * parts + 1 > kMaxWaves) continue;
       int npt = 0;
       for (int t : kTiles)
-        if (t >= per && (t < 7 || grad)) {
+        if (t >= per) {
           npt = t;
           break;
         }
@@ -774,9 +649,6 @@ hipError_t launch_lm(const Eri4Args &a, hipStream_t s) {
       case 3: return launch_t<3, LM, MODE>(a, s);
       case 4: return launch_t<4, LM, MODE>(a, s);
       case 6: return launch_t<6, LM, MODE>(a, s);
-      case 7:
-        if constexpr (MODE == 1) return launch_t<7, LM, MODE>(a, s);
-        return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
     }
   }
@@ -824,7 +696,6 @@ hipError_t launch_eri4(const Eri4Args &a0, hipStream_t s) {
   if (a0.nct * a0.nps + 1 > kMaxWaves) return hipErrorInvalidValue;
   Eri4Args a = a0;
   eri4_fill_wtask(a);
-  if (a.grad) return launch_g<1>(a, s);
   if (a.bra_Hs) {
     switch (a.split) {  // mode = slices - 3
       case 5: return launch_g<2>(a, s);

@@ -14,6 +14,7 @@
 #include <numeric>
 #include <mutex>
 
+#include "device_common.h"
 #include "internal.h"
 
 using namespace mderi;
@@ -661,20 +662,6 @@ std::vector<uint32_t> top_degree_rows(int l) {
 // Enqueues pair data (bra and ket) and the fused kernel for one class batch.
 // diag != 0 evaluates only (ij|ij) (bra list == ket list) and writes the
 // diagonal [ij][ab] to V.
-// Exchange-digest parameters of a class batch (see kdigest in eri4.hip).
-struct Digest {
-  double *kx;
-  const double *dm;
-  int nao;
-  double tau;
-  // gradient mode: instead of digesting into K, add twice the bra-centre
-  // derivatives of sum W (ab|cd) to grad[atom][xyz] (bra pair data in
-  // derivative form, Hermite rows up to l_a+l_b+1)
-  double *grad = nullptr;
-  int gcopies = 1;  // grad holds gcopies partial copies of 3 natom values
-  int gstride = 0;
-  const int *atom = nullptr;
-};
 
 // Launches the fused kernel, bracketed by timing events when timing is on.
 mderi_status launch_eri4_timed(mderi_ctx *c, const Eri4Args &ea, hipStream_t s) {
@@ -703,9 +690,12 @@ std::vector<std::array<int, 3>> block_candidates(int Nhb, int Nb, int Nk, int L,
 // noalloc: every device region is a slice of the context's scratch array and
 // the metadata goes through the staging buffer as it is (the allocation-free
 // entry point); otherwise regions come from the pooled workspace.
+// tile_variant > 0 forces that work split (see mderi_eri4_tile_variants);
+// count_only stores the number of splits in *count and enqueues nothing.
 mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int diag, double *V,
                              const std::vector<int> *extra_idx, void **d_extra_idx, hipStream_t s, int flags = 0,
-                             int precision = 0, int slices = kSplitDefault, bool noalloc = false) {
+                             int precision = 0, int slices = kSplitDefault, bool noalloc = false, int tile_variant = 0,
+                             int *count = nullptr) {
   const int nbra = (int)bra.off.size() - 1, nket = (int)ket.off.size() - 1;
   const int la = bra.la, lb = bra.lb, lc = ket.la, ld = ket.one_centre ? 0 : ket.lb;
   const int Lb = la + lb, Lk = lc + ld, L = Lb + Lk;
@@ -722,7 +712,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   for (int i = 0; i < nket; ++i) maxk = std::max(maxk, ket.off[i + 1] - ket.off[i]);
   const int maxpp = maxb + maxk;
   Eri4Plan pl{};
-  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, false, true, &pl))
+  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, true, &pl))
     return fail(MDERI_EUNSUPPORTED, "class (%d%d|%d%d) is beyond the fused kernel's tiles", la, lb, lc, ld);
   // tile variants: the tuned choice for this class signature, or all of
   // them timed on this batch when autotuning (single-slab classes only)
@@ -730,11 +720,20 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   if (split && (pl.npt & 1)) ++pl.npt;  // the BF16 operands pair 16-row tiles
   std::vector<std::array<int, 3>> cands = {{pl.npt, pl.nps, pl.dbuf}};
   const std::array<int, 6> sig = {la, lb, lc, ket.one_centre ? -1 : ld, maxb, maxk};
-  if (!diag && pl.nslab == 1 && !split) {
-    std::vector<std::array<int, 3>> all = block_candidates(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp);
+  std::vector<std::array<int, 3>> all;
+  if (!diag && pl.nslab == 1 && !split) all = block_candidates(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp);
+  if (count) {
+    *count = (int)all.size();
+    return MDERI_OK;
+  }
+  if (tile_variant > 0) {
+    if (tile_variant > (int)all.size())
+      return fail(MDERI_EINVAL, "class (%d%d|%d%d): tile variant %d of %zu", la, lb, lc, ld, tile_variant, all.size());
+    cands = {all[tile_variant - 1]};
+  } else if (!all.empty()) {
     auto it = c->tune.find(sig);
     if (it != c->tune.end() && std::find(all.begin(), all.end(), it->second) != all.end()) cands = {it->second};
-    else if ((flags & MDERI_FLAG_AUTOTUNE) && !all.empty()) cands = all;
+    else if (flags & MDERI_FLAG_AUTOTUNE) cands = all;
   }
   int Hb_rows = 0;
   for (auto &cd : cands) Hb_rows = std::max(Hb_rows, 16 * cd[0] * cd[1]);
@@ -960,8 +959,25 @@ extern "C" mderi_status mderi_eri4(mderi_ctx_t c, mderi_basis_t b, int nbra, con
   if (V_elems < need) return fail(MDERI_ESIZE, "mderi_eri4: output holds %zu doubles, needs %zu", V_elems, need);
   const int flags = opts ? opts->flags : 0;
   if (flags & ~MDERI_FLAG_AUTOTUNE) return fail(MDERI_EINVAL, "mderi_eri4: unsupported flags 0x%x", flags);
+  const int variant = opts ? opts->tile_variant : 0;
+  if (variant < 0 || (variant > 0 && precision != MDERI_FP64))
+    return fail(MDERI_EINVAL, "mderi_eri4: tile_variant %d (FP64 batches only, >= 0)", variant);
   HIP_TRY(hipSetDevice(c->device));
-  return run_class_batch(c, sb, sk, 0, V, nullptr, nullptr, (hipStream_t)stream, flags, precision, slices);
+  return run_class_batch(c, sb, sk, 0, V, nullptr, nullptr, (hipStream_t)stream, flags, precision, slices, false,
+                         variant);
+}
+
+extern "C" mderi_status mderi_eri4_tile_variants(mderi_ctx_t c, mderi_basis_t b, int nbra, const int32_t *bra,
+                                                 int nket, const int32_t *ket, int *count) {
+  if (!c || !b) return fail(MDERI_EINVAL, "mderi_eri4_tile_variants: NULL context or basis");
+  if (b->ctx != c) return fail(MDERI_EINVAL, "mderi_eri4_tile_variants: basis belongs to another context");
+  if (!count) return fail(MDERI_EINVAL, "mderi_eri4_tile_variants: NULL count");
+  Side sb{b, 0, 0, false, {}, {}}, sk{b, 0, 0, false, {}, {}};
+  mderi_status st;
+  if ((st = expand_pairs(b, nbra, bra, "bra", &sb.la, &sb.lb, sb.pp, sb.off)) != MDERI_OK) return st;
+  if ((st = expand_pairs(b, nket, ket, "ket", &sk.la, &sk.lb, sk.pp, sk.off)) != MDERI_OK) return st;
+  return run_class_batch(c, sb, sk, 0, nullptr, nullptr, nullptr, nullptr, 0, MDERI_FP64, kSplitDefault, false, 0,
+                         count);
 }
 
 extern "C" mderi_status mderi_eri4_noalloc(mderi_ctx_t c, mderi_basis_t b, int nbra, const int32_t *bra, int nket,
@@ -1070,6 +1086,10 @@ mderi_status select_pairs(mderi_ctx *c, mderi_basis *b, double tau, hipStream_t 
   ps.cls.assign(ncls, {});
   for (int p = 0; p < np; ++p)
     if (ps.q[p] * qmax >= tau) ps.cls[b->l[ps.pairs[2 * p]] * (kLmax + 1) + b->l[ps.pairs[2 * p + 1]]].push_back(p);
+  // decreasing Q inside each class: the partners that pass Q_i Q_k >= tau
+  // are then a prefix of the class's list
+  for (auto &cl : ps.cls)
+    std::stable_sort(cl.begin(), cl.end(), [&](int x, int y) { return ps.q[x] > ps.q[y]; });
   ps.sides.assign(ncls, Side{b, 0, 0, false, {}, {}});
   for (int ci = 0; ci < ncls; ++ci) {
     if (ps.cls[ci].empty()) continue;
@@ -1095,71 +1115,6 @@ mderi_status check_density(const char *fn, mderi_ctx *c, mderi_basis *b, const d
 }
 
 }  // namespace
-
-namespace {
-mderi_status run_pair_blocks(mderi_ctx *c, mderi_basis *b, const PairSets &ps, const Digest &dg, bool grad,
-                             hipStream_t s);
-}  // namespace
-
-extern "C" mderi_status mderi_kbuild(mderi_ctx_t c, mderi_basis_t b, const double *D, double *K, int nao,
-                                     const mderi_opts *opts, void *stream) {
-  mderi_status st;
-  if ((st = check_density("mderi_kbuild", c, b, D, nao, opts))) return st;
-  if (!K) return fail(MDERI_EINVAL, "mderi_kbuild: NULL output");
-  const double tau = (opts && opts->schwarz_tau > 0.0) ? opts->schwarz_tau : 1e-12;
-  HIP_TRY(hipSetDevice(c->device));
-  hipStream_t s = (hipStream_t)stream;
-  PairSets ps;
-  if ((st = select_pairs(c, b, tau, s, ps))) return st;
-  void *d_kt;
-  if ((st = ws_get(c, WS_KTMP, sizeof(double) * (size_t)nao * nao, &d_kt))) return st;
-  HIP_TRY(launch_zero((size_t)nao * nao, (double *)d_kt, s));
-  Digest dg;
-  dg.kx = (double *)d_kt;
-  dg.dm = D;
-  dg.nao = nao;
-  dg.tau = tau;
-  // unordered class blocks; inside a diagonal block the kernel keeps ij >= kl
-  if ((st = run_pair_blocks(c, b, ps, dg, false, s))) return st;
-  HIP_TRY(launch_symmetrize(nao, (const double *)d_kt, K, s));
-  return MDERI_OK;
-}
-
-extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, const double *D, int nao, double *grad,
-                                          int natom, const mderi_opts *opts, void *stream) {
-  mderi_status st;
-  if ((st = check_density("mderi_kbuild_grad", c, b, D, nao, opts))) return st;
-  if (!grad) return fail(MDERI_EINVAL, "mderi_kbuild_grad: NULL output");
-  for (int i = 0; i < b->nshell; ++i)
-    if (b->atom[i] < 0 || b->atom[i] >= natom)
-      return fail(MDERI_EINVAL, "mderi_kbuild_grad: shell %d sits on atom %d, outside [0,%d)", i, b->atom[i], natom);
-  const double tau = (opts && opts->schwarz_tau > 0.0) ? opts->schwarz_tau : 1e-12;
-  HIP_TRY(hipSetDevice(c->device));
-  hipStream_t s = (hipStream_t)stream;
-  PairSets ps;
-  if ((st = select_pairs(c, b, tau, s, ps))) return st;
-  // the workgroups add into kGradCopies partial gradients (spread by
-  // workgroup id, so the atomics of many small quartets do not queue on the
-  // same 3 natom addresses), summed into grad at the end
-  constexpr int kGradCopies = 512;
-  void *d_gpart = nullptr;
-  if ((st = ws_get(c, WS_GPART, sizeof(double) * (size_t)kGradCopies * 3 * natom, &d_gpart))) return st;
-  HIP_TRY(launch_zero((size_t)kGradCopies * 3 * natom, (double *)d_gpart, s));
-  Digest dg;
-  dg.kx = nullptr;
-  dg.dm = D;
-  dg.nao = nao;
-  dg.tau = tau;
-  dg.grad = (double *)d_gpart;
-  dg.gcopies = kGradCopies;
-  dg.gstride = 3 * natom;
-  dg.atom = b->dev.atom;
-  // every ordered (bra class, ket class) block: each visit supplies the
-  // bra-centre derivatives, its swapped visit the ket-centre ones
-  if ((st = run_pair_blocks(c, b, ps, dg, true, s))) return st;
-  HIP_TRY(launch_sum_copies(3 * natom, kGradCopies, (const double *)d_gpart, grad, s));
-  return MDERI_OK;
-}
 
 // ---------------------------------------------------------------------------
 // task lists: mixed-class 3-centre batches in persistent launches
@@ -1234,7 +1189,7 @@ std::vector<std::array<int, 3>> block_candidates(int Nhb, int Nb, int Nk, int L,
                                                  int maxpp) {
   std::vector<std::array<int, 3>> out;
   Eri4Plan pl{};
-  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, false, false, &pl)) return out;
+  if (!eri4_plan(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp, false, &pl)) return out;
   const int dbuf = pl.dbuf;
   out.push_back({pl.npt, pl.nps, pl.dbuf});
   const int need = (Nhb + 15) / 16, nct = (Nk + 15) / 16;
@@ -1695,192 +1650,447 @@ extern "C" mderi_status mderi_eri3_batch(mderi_ctx_t c, mderi_basis_t b, mderi_b
   return launch_groups(c, plan, s);
 }
 
+
 // ---------------------------------------------------------------------------
-// K build and gradient: all class blocks of a call from one upload
+// screened quartet engine: J and K builds and the nuclear gradient (kx.hip)
 // ---------------------------------------------------------------------------
 namespace {
 
-// Pair data is computed once per class (once in the bra role, with the
-// class's bank-spread row order and strides that fit its largest L, and once
-// in the ket role), all metadata goes up in one staged copy, and the blocks
-// are launched back to back without host synchronisation.
-mderi_status run_pair_blocks(mderi_ctx *c, mderi_basis *b, const PairSets &ps, const Digest &dg, bool grad,
-                             hipStream_t s) {
-  struct Cls {
-    int la, lb, Lbb, Lk, Nb, Nb_pad, Nhb, Nhk, Nhk_pad, npp, maxpp, S1 = 0, S2 = 0, Lmax = 0, nh_alloc = 0;
-    size_t o_pp, o_off, o_q, o_sh, o_order, o_Gb, o_Hb, o_Gk, o_Hk;
-  };
-  struct Blk {
-    int c1, c2, L, npt, nps, dbuf, cube_sz, maxpp, S1, S2;
-  };
-  std::map<int, Cls> C;
-  for (size_t ci = 0; ci < ps.cls.size(); ++ci) {
+// What one engine call computes.
+struct KxJob {
+  bool grad = false;
+  // digest mode
+  const double *dm = nullptr;
+  double *kx = nullptr, *jx = nullptr;
+  // gradient mode
+  const double *wl = nullptr, *wr = nullptr;
+  int pattern = 0;
+  int symmetric = 0;
+  double scale = 1.0;
+  double *gpart = nullptr;
+  int gcopies = 1, gstride = 0;
+};
+
+// Per class: its significant pairs (sorted by decreasing Q), sizes, and the
+// metadata / pair data of the roles it plays.
+struct KxClass {
+  int la = 0, lb = 0, Lc = 0, NA = 0, NA_pad = 0, NhB = 0, NhB_pad = 0, maxpp = 0;
+  bool asA = false, asB = false;
+  int LA = 0, NhA = 0, nh_alloc = 0, LmaxA = 0, S1 = 0, S2 = 0;  // A role (LA includes the +1 of gradients)
+  std::vector<double> q;
+  std::vector<int32_t> sh;
+  size_t o_pp = 0, o_off = 0, o_sh = 0, o_order = 0, o_GA = 0, o_HA = 0, o_GB = 0, o_HB = 0;
+};
+
+struct KxPlanBlock {
+  int cA, cB, same, L, npt, nparts, S1, S2;
+  long nq;
+  double cost;  // rough cycles of one quartet on one wave
+  std::vector<long> pre;
+  size_t o_pre = 0;
+  KxBlock blk{};
+};
+
+// One rough cost of a quartet (cycles of one wave): matrix-core steps of the
+// two products plus the R build.
+double kx_cost(int NhA, int NA, int NhB_pad, int NB, int L, int nct) {
+  const int rt = (NhA + 15) / 16, at = (NA + 15) / 16;
+  const double mf = (double)nct * rt * (NhB_pad / 4) + (double)nct * at * rt * 4;
+  return 64.0 * mf + 40.0 * ntil(L) + 1500.0;
+}
+
+mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau, const KxJob &job, hipStream_t s) {
+  const int ncls = (int)ps.cls.size();
+  std::vector<KxClass> C(ncls);
+  const int gextra = job.grad ? 1 : 0;
+  for (int ci = 0; ci < ncls; ++ci) {
     if (ps.cls[ci].empty()) continue;
+    KxClass &k = C[ci];
     const Side &sd = ps.sides[ci];
-    Cls k{};
     k.la = sd.la;
     k.lb = sd.lb;
-    k.Lbb = sd.la + sd.lb + (grad ? 1 : 0);
-    k.Lk = sd.la + sd.lb;
-    k.Nb = nsph(sd.la) * nsph(sd.lb);
-    k.Nb_pad = round16(k.Nb);
-    k.Nhb = ntil(k.Lbb);
-    k.Nhk = ntil(k.Lk);
-    k.Nhk_pad = (k.Nhk + 7) & ~7;
-    k.npp = (int)sd.pp.size();
+    k.Lc = k.la + k.lb;
+    k.NA = nsph(k.la) * nsph(k.lb);
+    k.NA_pad = round16(k.NA);
+    k.NhB = ntil(k.Lc);
+    k.NhB_pad = (k.NhB + 7) & ~7;
+    k.LA = k.Lc + gextra;
+    k.NhA = ntil(k.LA);
     for (size_t i = 0; i + 1 < sd.off.size(); ++i) k.maxpp = std::max(k.maxpp, sd.off[i + 1] - sd.off[i]);
-    C[(int)ci] = k;
-  }
-  std::vector<Blk> blocks;
-  for (auto &x : C)
-    for (auto &y : C) {
-      if (!grad && y.first < x.first) continue;
-      if ((double)ps.cls[x.first].size() * ps.cls[y.first].size() > 2.0e9)
-        return fail(MDERI_EUNSUPPORTED, "class block of %zu x %zu pairs is too large", ps.cls[x.first].size(),
-                    ps.cls[y.first].size());
-      Blk bk{};
-      bk.c1 = x.first;
-      bk.c2 = y.first;
-      bk.L = x.second.Lbb + y.second.Lk;
-      x.second.Lmax = std::max(x.second.Lmax, bk.L);
-      blocks.push_back(bk);
+    for (int p : ps.cls[ci]) {
+      k.q.push_back(ps.q[p]);
+      k.sh.push_back(ps.pairs[2 * p]);
+      k.sh.push_back(ps.pairs[2 * p + 1]);
     }
-  for (auto &x : C) choose_cube(x.second.Lmax, x.second.Lbb, &x.second.S1, &x.second.S2);
-  for (Blk &bk : blocks) {
-    Cls &x = C[bk.c1], &y = C[bk.c2];
-    // strides for the block's own L keep small blocks' cubes small; the
-    // class's row order follows the strides of its largest block
-    choose_cube(bk.L, x.Lbb, &bk.S1, &bk.S2);
-    bk.cube_sz = (bk.L * bk.S1 + 2) & ~1;
-    bk.maxpp = x.maxpp + y.maxpp;
-    Eri4Plan pl{};
-    const bool ok = eri4_plan(x.Nhb, x.Nb, y.Nb, bk.L, bk.cube_sz, y.Nhk_pad, bk.maxpp, grad, false, &pl);
-    bk.npt = pl.npt;
-    bk.nps = pl.nps;
-    bk.dbuf = pl.dbuf;
-    if (!ok)
-      return fail(MDERI_EUNSUPPORTED, "class (%d%d|%d%d)%s is beyond the fused kernel's tiles", x.la, x.lb, y.la, y.lb,
-                  grad ? " (gradient)" : "");
-    x.nh_alloc = std::max(x.nh_alloc, 16 * bk.npt * bk.nps);
   }
+  // blocks: unordered class pairs for the builds (the cheaper orientation),
+  // ordered ones for the gradient (each supplies its A centres)
+  std::vector<KxPlanBlock> blocks;
+  for (int x = 0; x < ncls; ++x)
+    for (int y = 0; y < ncls; ++y) {
+      if (C[x].q.empty() || C[y].q.empty()) continue;
+      if (!job.grad && y < x) continue;
+      int cA = x, cB = y;
+      auto cost_of = [&](int u, int v) {
+        const KxClass &A = C[u], &B = C[v];
+        return kx_cost(A.NhA, A.NA, B.NhB_pad, B.NA, A.LA + B.Lc, B.NA_pad / 16);
+      };
+      if (!job.grad && x != y && cost_of(y, x) < cost_of(x, y)) std::swap(cA, cB);
+      KxPlanBlock pb{};
+      pb.cA = cA;
+      pb.cB = cB;
+      pb.same = (cA == cB) ? 1 : 0;
+      const KxClass &A = C[cA], &B = C[cB];
+      pb.L = A.LA + B.Lc;
+      const int nA = (int)A.q.size();
+      pb.pre.assign(nA + 1, 0);
+      for (int i = 0; i < nA; ++i) {
+        // B pairs k with Q_i Q_k >= tau: a prefix of the sorted list
+        int lo = 0, hi = (int)B.q.size();
+        while (lo < hi) {
+          const int mid = (lo + hi) / 2;
+          if (A.q[i] * B.q[mid] >= tau) lo = mid + 1;
+          else hi = mid;
+        }
+        long cnt = lo;
+        if (pb.same && !job.grad) cnt = std::min<long>(cnt, i + 1);
+        pb.pre[i + 1] = pb.pre[i] + cnt;
+      }
+      pb.nq = pb.pre[nA];
+      if (pb.nq == 0) continue;
+      const int ntiles = (A.NhA + 15) / 16;
+      pb.npt = ntiles <= 1 ? 1 : ntiles <= 2 ? 2 : 4;
+      pb.nparts = (ntiles + pb.npt - 1) / pb.npt;
+      pb.cost = kx_cost(A.NhA, A.NA, B.NhB_pad, B.NA, pb.L, B.NA_pad / 16);
+      if (pb.L > 18) return fail(MDERI_EUNSUPPORTED, "quartet class of total degree %d is beyond the engine", pb.L);
+      blocks.push_back(std::move(pb));
+      C[cA].asA = true;
+      C[cB].asB = true;
+      C[cA].nh_alloc = std::max(C[cA].nh_alloc, blocks.back().nparts * blocks.back().npt * 16);
+      C[cA].LmaxA = std::max(C[cA].LmaxA, blocks.back().L);
+    }
+  if (blocks.empty()) return MDERI_OK;
+  // A-role row order: bank-spread for the strides of the class's largest block
+  for (auto &k : C)
+    if (k.asA) choose_cube(k.LmaxA, k.LA, &k.S1, &k.S2);
+  for (auto &pb : blocks) choose_cube(pb.L, C[pb.cA].LA, &pb.S1, &pb.S2);
+
+  // launch groups by (row tiles, total degree): the wave's LDS regions are
+  // sized for its group; heaviest quartets first inside a group
+  std::map<std::pair<int, int>, std::vector<int>> groups;
+  for (size_t bi = 0; bi < blocks.size(); ++bi) groups[{blocks[bi].npt, blocks[bi].L}].push_back((int)bi);
+  for (auto &gr : groups)
+    std::stable_sort(gr.second.begin(), gr.second.end(),
+                     [&](int x, int y) { return blocks[x].cost > blocks[y].cost; });
+
+  // metadata image: per class pairs, offsets, shells, A order; per block pre;
+  // per group the block descriptors; then the device-only pair data
   Image img;
-  const int mats = grad ? 6 : 1;
-  for (auto &x : C) {
-    Cls &k = x.second;
-    const Side &sd = ps.sides[x.first];
-    std::vector<double> q;
-    std::vector<int32_t> sh;
-    for (int p : ps.cls[x.first]) {
-      q.push_back(ps.q[p]);
-      sh.push_back(ps.pairs[2 * p]);
-      sh.push_back(ps.pairs[2 * p + 1]);
-    }
-    std::vector<uint32_t> order = bra_row_order(k.Lbb, k.S1, k.S2, round16(k.Nhb));
-    while ((int)order.size() < k.nh_alloc) order.push_back(order[0] | kPadRow);
+  for (int ci = 0; ci < ncls; ++ci) {
+    KxClass &k = C[ci];
+    if (!k.asA && !k.asB) continue;
+    const Side &sd = ps.sides[ci];
     k.o_pp = img.add(sd.pp.data(), sizeof(PrimPair) * sd.pp.size());
     k.o_off = img.add(sd.off.data(), sizeof(int) * sd.off.size());
-    k.o_q = img.add(q.data(), sizeof(double) * q.size());
-    k.o_sh = img.add(sh.data(), sizeof(int32_t) * sh.size());
-    k.o_order = img.add(order.data(), sizeof(uint32_t) * order.size());
+    k.o_sh = img.add(k.sh.data(), sizeof(int32_t) * k.sh.size());
+    if (k.asA) {
+      std::vector<uint32_t> order = bra_row_order(k.LA, k.S1, k.S2, round16(k.NhA));
+      while ((int)order.size() < k.nh_alloc) order.push_back(order[0] | kPadRow);
+      order.resize(std::max<size_t>(order.size(), (size_t)k.nh_alloc));
+      k.nh_alloc = (int)order.size();
+      k.o_order = img.add(order.data(), sizeof(uint32_t) * order.size());
+    }
+  }
+  for (auto &pb : blocks) pb.o_pre = img.add(pb.pre.data(), sizeof(long) * pb.pre.size());
+  struct Group {
+    int npt, lm, waves, grid;
+    size_t lds;
+    long nchunk;
+    KxArgs args;
+    size_t o_blocks, o_counter;
+    std::vector<KxBlock> blks;
+  };
+  std::vector<Group> G;
+  for (auto &gr : groups) {
+    Group g{};
+    g.npt = gr.first.first;
+    g.lm = gr.first.second;  // total degree L: the producer bucket follows it
+    g.blks.resize(gr.second.size());
+    g.o_blocks = img.add(g.blks.data(), sizeof(KxBlock) * g.blks.size());  // filled in below
+    G.push_back(std::move(g));
   }
   const size_t meta_bytes = img.bytes.size();
-  for (auto &x : C) {
-    Cls &k = x.second;
-    k.o_Gb = img.add(nullptr, sizeof(double) * 4 * k.npp);
-    k.o_Hb = img.add(nullptr, sizeof(double) * mats * (size_t)k.nh_alloc * k.Nb_pad * k.npp);
-    k.o_Gk = img.add(nullptr, sizeof(double) * 4 * k.npp);
-    k.o_Hk = img.add(nullptr, sizeof(double) * (size_t)k.Nhk_pad * k.Nb_pad * k.npp);
+  const int mats = job.grad ? 6 : 1;
+  for (auto &k : C) {
+    const int npp = (int)ps.sides[&k - &C[0]].pp.size();
+    if (k.asA) {
+      k.o_GA = img.add(nullptr, sizeof(double) * 4 * npp);
+      k.o_HA = img.add(nullptr, sizeof(double) * mats * (size_t)k.nh_alloc * k.NA_pad * npp);
+    }
+    if (k.asB) {
+      k.o_GB = img.add(nullptr, sizeof(double) * 4 * npp);
+      k.o_HB = img.add(nullptr, sizeof(double) * (size_t)k.NhB_pad * k.NA_pad * npp);
+    }
   }
+  for (auto &g : G) g.o_counter = img.add(nullptr, sizeof(unsigned long long));
   mderi_status st;
   void *dmem;
   if ((st = ws_get(c, WS_PAIRS, img.size, &dmem))) return st;
   char *base = (char *)dmem;
   auto dev = [&](size_t off) { return (void *)(base + off); };
+
+  // block descriptors, chunks and per-wave LDS layout of every group
+  size_t gi = 0;
+  for (auto &gr : groups) {
+    Group &g = G[gi++];
+    int cube_max = 2, work_max = 2, v_max = 2, d_max = 2, i_max = 2, g_max = 4, uv_max = 1, oq_max = 8, op_max = 16;
+    bool single = true;  // every quartet is one primitive quartet: v may share the work area
+    long chunk0 = 0;
+    for (size_t j = 0; j < gr.second.size(); ++j) {
+      KxPlanBlock &pb = blocks[gr.second[j]];
+      const KxClass &A = C[pb.cA], &B = C[pb.cB];
+      KxBlock &x = g.blks[j];
+      x.nq = pb.nq;
+      x.chunk = (int)std::max(1.0, std::min(4096.0, 600000.0 / pb.cost));
+      x.chunk0 = chunk0;
+      chunk0 += (pb.nq + x.chunk - 1) / x.chunk;
+      x.pre = (const long *)dev(pb.o_pre);
+      x.nA = (int)A.q.size();
+      x.L = pb.L;
+      x.S1 = pb.S1;
+      x.S2 = pb.S2;
+      x.NhA = A.NhA;
+      x.HA_rows = A.nh_alloc;
+      x.nparts = pb.nparts;
+      x.NhB = B.NhB;
+      x.NhB_pad = B.NhB_pad;
+      x.NA = A.NA;
+      x.NB = B.NA;
+      x.NA_pad = A.NA_pad;
+      x.NB_pad = B.NA_pad;
+      x.nct = B.NA_pad / 16;
+      x.na = nsph(A.la);
+      x.nb = nsph(A.lb);
+      x.nc = nsph(B.la);
+      x.nd = nsph(B.lb);
+      x.same = pb.same;
+      x.inv_nb = 1.0f / (float)x.nb;
+      x.inv_nd = 1.0f / (float)x.nd;
+      x.inv_NB = 1.0f / (float)x.NB;
+      x.inv_ncd = 1.0f / (float)(x.nc + x.nd);
+      x.Aorder = (const uint32_t *)dev(A.o_order);
+      x.A_off = (const int *)dev(A.o_off);
+      x.B_off = (const int *)dev(B.o_off);
+      x.A_G = (const double *)dev(A.o_GA);
+      x.A_H = (const double *)dev(A.o_HA);
+      x.B_G = (const double *)dev(B.o_GB);
+      x.B_H = (const double *)dev(B.o_HB);
+      x.A_sh = (const int *)dev(A.o_sh);
+      x.B_sh = (const int *)dev(B.o_sh);
+      const int nab = x.na + x.nb, ncd = x.nc + x.nd;
+      cube_max = std::max(cube_max, (pb.L * pb.S1 + 2) & ~1);
+      work_max = std::max(work_max, rr_work_size(pb.L));
+      v_max = std::max(v_max, x.NA_pad * 16);  // one B column tile of V or of the weights
+      int d = 0, im = 0;
+      if (job.grad) d = job.pattern == 0 ? (job.symmetric ? 1 : 4) * nab * ncd : 2 * (x.NA + x.NB);
+      else d = im = (job.kx ? nab * ncd : 0) + (job.jx ? x.NA + x.NB : 0);
+      d_max = std::max(d_max, d);
+      i_max = std::max(i_max, im);
+      single = single && A.maxpp == 1 && B.maxpp == 1;
+      g_max = std::max(g_max, 4 * (A.maxpp + B.maxpp));
+      uv_max = std::max(uv_max, (pb.L + 1) * (pb.L + 2) / 2);
+      oq_max = std::max(oq_max, x.NhB_pad);
+      op_max = std::max(op_max, x.HA_rows);
+    }
+    g.nchunk = chunk0;
+    auto even = [](int v) { return (v + 1) & ~1; };
+    KxArgs &ar = g.args;
+    ar.o_work = even(cube_max);
+    ar.o_v = single ? ar.o_work : ar.o_work + even(work_max);
+    ar.o_d = single ? ar.o_work + even(std::max(work_max, v_max)) : ar.o_v + even(v_max);
+    ar.o_img = ar.o_d + even(d_max);
+    ar.o_g = ar.o_img + even(i_max);
+    ar.o_tab = ar.o_g + even(g_max);
+    ar.uv_max = even(uv_max);
+    ar.oq_max = even(oq_max);
+    ar.wave_doubles = ar.o_tab + (ar.uv_max + ar.oq_max + op_max + 1) / 2 + 1;
+    ar.wave_doubles = even(ar.wave_doubles);
+    const size_t wave_bytes = sizeof(double) * (size_t)ar.wave_doubles;
+    g.waves = (int)std::min<size_t>(4, (160 * 1024) / wave_bytes);
+    if (g.waves < 1)
+      return fail(MDERI_EUNSUPPORTED, "quartet engine: a wave needs %zu bytes of LDS (over 160 KiB)", wave_bytes);
+    g.lds = wave_bytes * g.waves;
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / g.lds));
+    g.grid = (int)std::min<long>(256L * per_cu, std::max<long>(1, (g.nchunk + g.waves - 1) / g.waves));
+    ar.blocks = (const KxBlock *)dev(g.o_blocks);
+    ar.nblk = (int)g.blks.size();
+    ar.nchunk = g.nchunk;
+    ar.counter = (unsigned long long *)dev(g.o_counter);
+    ar.tab = c->tab;
+    ar.ao_off = b->dev.ao_off;
+    ar.nao = b->nao;
+    ar.dm = job.dm;
+    ar.kx = job.kx;
+    ar.jx = job.jx;
+    ar.wl = job.wl;
+    ar.wr = job.wr;
+    ar.pattern = job.pattern;
+    ar.symmetric = job.symmetric;
+    ar.scale = job.scale;
+    ar.grad = job.gpart;
+    ar.gcopies = job.gcopies;
+    ar.gstride = job.gstride;
+    ar.atom = b->dev.atom;
+    memcpy(img.bytes.data() + g.o_blocks, g.blks.data(), sizeof(KxBlock) * g.blks.size());
+  }
+
   if ((st = stage_begin(c, meta_bytes))) return st;
   size_t used = 0;
   if ((st = stage_copy(c, base, img.bytes.data(), meta_bytes, s, &used))) return st;
   if ((st = stage_end(c, s))) return st;
-  for (auto &x : C) {
-    const Cls &k = x.second;
+  // pair data once per class and role
+  for (int ci = 0; ci < ncls; ++ci) {
+    const KxClass &k = C[ci];
+    if (!k.asA && !k.asB) continue;
+    const Side &sd = ps.sides[ci];
     PairArgs pa{};
     pa.basis = b->dev;
     pa.tab = c->tab;
-    pa.npp = k.npp;
+    pa.npp = (int)sd.pp.size();
     pa.pp = (const PrimPair *)dev(k.o_pp);
     pa.la = k.la;
     pa.lb = k.lb;
-    pa.Nh = k.Nhb;
-    pa.N = k.Nb;
-    pa.Nh_pad = k.nh_alloc;
-    pa.N_pad = k.Nb_pad;
-    pa.deriv = grad ? 1 : 0;
-    pa.order = (const uint32_t *)dev(k.o_order);
-    pa.G = (double *)dev(k.o_Gb);
-    pa.H = (double *)dev(k.o_Hb);
-    HIP_TRY(launch_pairs(pa, s));
-    pa.Nh = k.Nhk;
-    pa.Nh_pad = k.Nhk_pad;
-    pa.ket_sign = 1;
-    pa.deriv = 0;
-    pa.order = nullptr;
-    pa.G = (double *)dev(k.o_Gk);
-    pa.H = (double *)dev(k.o_Hk);
-    HIP_TRY(launch_pairs(pa, s));
+    pa.N = k.NA;
+    pa.N_pad = k.NA_pad;
+    if (k.asA) {
+      pa.Nh = k.NhA;
+      pa.Nh_pad = k.nh_alloc;
+      pa.deriv = job.grad ? 1 : 0;
+      pa.order = (const uint32_t *)dev(k.o_order);
+      pa.ket_sign = 0;
+      pa.G = (double *)dev(k.o_GA);
+      pa.H = (double *)dev(k.o_HA);
+      HIP_TRY(launch_pairs(pa, s));
+    }
+    if (k.asB) {
+      pa.Nh = k.NhB;
+      pa.Nh_pad = k.NhB_pad;
+      pa.deriv = 0;
+      pa.order = nullptr;
+      pa.ket_sign = 1;
+      pa.G = (double *)dev(k.o_GB);
+      pa.H = (double *)dev(k.o_HB);
+      HIP_TRY(launch_pairs(pa, s));
+    }
   }
-  for (const Blk &bk : blocks) {
-    const Cls &x = C.at(bk.c1), &y = C.at(bk.c2);
-    Eri4Args ea{};
-    ea.nbra = (int)ps.cls[bk.c1].size();
-    ea.nket = (int)ps.cls[bk.c2].size();
-    ea.L = bk.L;
-    ea.Nhb = x.Nhb;
-    ea.Nhk = y.Nhk;
-    ea.Nb = x.Nb;
-    ea.Nk = y.Nb;
-    ea.Nhb_pad = 16 * bk.npt * bk.nps;
-    ea.Hb_rows = x.nh_alloc;
-    ea.Nhk_pad = y.Nhk_pad;
-    ea.Nb_pad = x.Nb_pad;
-    ea.Nk_pad = y.Nb_pad;
-    ea.npt = bk.npt;
-    ea.nps = bk.nps;
-    ea.nct = y.Nb_pad / 16;
-    ea.nslab = 1;
-    ea.dbuf = bk.dbuf;
-    ea.S1 = bk.S1;
-    ea.S2 = bk.S2;
-    ea.cube_sz = bk.cube_sz;
-    ea.maxpp = bk.maxpp;
-    ea.border = (const uint32_t *)dev(x.o_order);
-    ea.korder = nullptr;
-    ea.bra_off = (const int *)dev(x.o_off);
-    ea.ket_off = (const int *)dev(y.o_off);
-    ea.bra_G = (const double *)dev(x.o_Gb);
-    ea.ket_G = (const double *)dev(y.o_Gk);
-    ea.bra_H = (const double *)dev(x.o_Hb);
-    ea.ket_H = (const double *)dev(y.o_Hk);
-    ea.tab = c->tab;
-    ea.kx = grad ? nullptr : dg.kx;
-    ea.grad = grad ? dg.grad : nullptr;
-    ea.gcopies = dg.gcopies;
-    ea.gstride = dg.gstride;
-    ea.atom = grad ? dg.atom : nullptr;
-    ea.dm = dg.dm;
-    ea.nao = dg.nao;
-    ea.tau = dg.tau;
-    ea.same_list = (!grad && bk.c1 == bk.c2) ? 1 : 0;
-    ea.bra_q = (const double *)dev(x.o_q);
-    ea.ket_q = (const double *)dev(y.o_q);
-    ea.bra_sh = (const int *)dev(x.o_sh);
-    ea.ket_sh = (const int *)dev(y.o_sh);
-    ea.ao_off = b->dev.ao_off;
-    ea.nsa = nsph(x.la);
-    ea.nsb = nsph(x.lb);
-    ea.nsc = nsph(y.la);
-    ea.nsd = nsph(y.lb);
-    if ((st = launch_eri4_timed(c, ea, s))) return st;
+  for (auto &g : G) {
+    HIP_TRY(launch_zero(1, (double *)dev(g.o_counter), s));  // chunk counter (zero bits)
+    if (c->timing) {
+      if (c->ev_free.empty()) {
+        std::pair<hipEvent_t, hipEvent_t> e;
+        HIP_TRY(hipEventCreate(&e.first));
+        HIP_TRY(hipEventCreate(&e.second));
+        c->ev_free.push_back(e);
+      }
+      const auto e = c->ev_free.back();
+      c->ev_free.pop_back();
+      c->ev_used.push_back(e);
+      HIP_TRY(hipEventRecord(e.first, s));
+      HIP_TRY(launch_kx(g.args, g.npt, g.lm, job.grad, g.waves, g.lds, g.grid, s));
+      HIP_TRY(hipEventRecord(e.second, s));
+    } else {
+      HIP_TRY(launch_kx(g.args, g.npt, g.lm, job.grad, g.waves, g.lds, g.grid, s));
+    }
   }
   return MDERI_OK;
 }
 
+double opt_tau(const mderi_opts *opts) { return (opts && opts->schwarz_tau > 0.0) ? opts->schwarz_tau : 1e-12; }
+
 }  // namespace
+
+extern "C" mderi_status mderi_jkbuild(mderi_ctx_t c, mderi_basis_t b, const double *D, double *J, double *K, int nao,
+                                      double *energy, const mderi_opts *opts, void *stream) {
+  mderi_status st;
+  if ((st = check_density("mderi_jkbuild", c, b, D, nao, opts))) return st;
+  if (!J && !K) return fail(MDERI_EINVAL, "mderi_jkbuild: J and K are both NULL");
+  const double tau = opt_tau(opts);
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  PairSets ps;
+  if ((st = select_pairs(c, b, tau, s, ps))) return st;
+  const size_t nn = (size_t)nao * nao;
+  void *d_t;
+  if ((st = ws_get(c, WS_KTMP, sizeof(double) * (nn * ((J ? 1 : 0) + (K ? 1 : 0)) + dot2_work_doubles()), &d_t)))
+    return st;
+  double *kt = K ? (double *)d_t : nullptr;
+  double *jt = J ? (double *)d_t + (K ? nn : 0) : nullptr;
+  double *work = (double *)d_t + nn * ((J ? 1 : 0) + (K ? 1 : 0));
+  if (kt) HIP_TRY(launch_zero(nn, kt, s));
+  if (jt) HIP_TRY(launch_zero(nn, jt, s));
+  KxJob job;
+  job.dm = D;
+  job.kx = kt;
+  job.jx = jt;
+  if ((st = run_kx(c, b, ps, tau, job, s))) return st;
+  if (K) HIP_TRY(launch_symmetrize(nao, kt, K, s));
+  if (J) HIP_TRY(launch_symmetrize(nao, jt, J, s));
+  if (energy) HIP_TRY(launch_dot2(nn, D, J, K, work, energy, s));
+  return MDERI_OK;
+}
+
+extern "C" mderi_status mderi_kbuild(mderi_ctx_t c, mderi_basis_t b, const double *D, double *K, int nao,
+                                     const mderi_opts *opts, void *stream) {
+  if (!K) return fail(MDERI_EINVAL, "mderi_kbuild: NULL output");
+  return mderi_jkbuild(c, b, D, nullptr, K, nao, nullptr, opts, stream);
+}
+
+extern "C" mderi_status mderi_basis_set_centers(mderi_basis_t b, const double *centers, void *stream) {
+  if (!b) return fail(MDERI_EINVAL, "mderi_basis_set_centers: NULL basis");
+  if (!centers) return fail(MDERI_EINVAL, "mderi_basis_set_centers: NULL centres");
+  HIP_TRY(hipSetDevice(b->ctx->device));
+  HIP_TRY(hipMemcpyAsync(b->dev.centers, centers, sizeof(double) * 3 * (size_t)b->nshell, hipMemcpyDeviceToDevice,
+                         (hipStream_t)stream));
+  return MDERI_OK;
+}
+
+extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, int pattern, const double *Wl,
+                                          const double *Wr, int nao, double scale, double *grad, int natom,
+                                          int accumulate, const mderi_opts *opts, void *stream) {
+  mderi_status st;
+  if ((st = check_density("mderi_kbuild_grad", c, b, Wl, nao, opts))) return st;
+  if (!Wr) return fail(MDERI_EINVAL, "mderi_kbuild_grad: NULL Wr");
+  if (pattern != MDERI_EXCHANGE && pattern != MDERI_COULOMB)
+    return fail(MDERI_EINVAL, "mderi_kbuild_grad: pattern %d", pattern);
+  if (!grad) return fail(MDERI_EINVAL, "mderi_kbuild_grad: NULL output");
+  if (natom <= 0) return fail(MDERI_EINVAL, "mderi_kbuild_grad: natom %d", natom);
+  if (!std::isfinite(scale)) return fail(MDERI_EINVAL, "mderi_kbuild_grad: scale is not finite");
+  for (int i = 0; i < b->nshell; ++i)
+    if (b->atom[i] < 0 || b->atom[i] >= natom)
+      return fail(MDERI_EINVAL, "mderi_kbuild_grad: shell %d sits on atom %d, outside [0,%d)", i, b->atom[i], natom);
+  const double tau = opt_tau(opts);
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  PairSets ps;
+  if ((st = select_pairs(c, b, tau, s, ps))) return st;
+  // the waves add into kGradCopies partial gradients (by workgroup), summed
+  // into grad at the end, so the atomics of many short flushes do not queue
+  // on the same 3 natom addresses
+  constexpr int kGradCopies = 512;
+  void *d_gpart = nullptr;
+  if ((st = ws_get(c, WS_GPART, sizeof(double) * (size_t)kGradCopies * 3 * natom, &d_gpart))) return st;
+  HIP_TRY(launch_zero((size_t)kGradCopies * 3 * natom, (double *)d_gpart, s));
+  KxJob job;
+  job.grad = true;
+  job.wl = Wl;
+  job.wr = Wr;
+  job.pattern = pattern;
+  job.symmetric = ((opts ? opts->flags : 0) & MDERI_FLAG_SYMMETRIC) && Wl == Wr ? 1 : 0;
+  job.scale = scale;
+  job.gpart = (double *)d_gpart;
+  job.gcopies = kGradCopies;
+  job.gstride = 3 * natom;
+  if ((st = run_kx(c, b, ps, tau, job, s))) return st;
+  HIP_TRY(launch_sum_copies(3 * natom, kGradCopies, (const double *)d_gpart, grad, s, accumulate ? 1 : 0));
+  return MDERI_OK;
+}

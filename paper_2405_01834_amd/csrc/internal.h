@@ -116,24 +116,6 @@ struct Eri4Args {
   const uint32_t *border;  // bra Hermite row order (Nhb_pad entries, see PairArgs::order)
   const uint32_t *korder;  // ket Hermite row order (Nhk_pad entries), or nullptr for the global order
   int diag;      // Schwarz mode: quartets (ij|ij) only, V receives the diagonal [ij][ab]
-  // exchange digest mode (kx != nullptr): instead of storing V, quartets with
-  // Q_ij Q_kl >= tau (and ij >= kl when bra and ket are the same list) add
-  // their four permutational images to K (see kdigest in eri4.hip)
-  double *kx;                     // K' [nao][nao], FP64 atomics
-  const double *dm;               // D [nao][nao]
-  int nao;
-  int same_list;                  // bra list == ket list: keep ij >= kl only
-  double tau;
-  const double *bra_q, *ket_q;    // Schwarz factors per pair
-  const int *bra_sh, *ket_sh;     // shell indices [n][2] (one-centre lists repeat the shell)
-  const int *ao_off;              // first AO of every shell
-  int nsa, nsb, nsc, nsd;         // N(l) of the four shells
-  // gradient mode (grad != nullptr): bra_H holds the six derivative matrices
-  // per bra primitive pair, the bra rows span |p| <= l_a+l_b+1, and the
-  // workgroup adds sum W d(ab|cd)/dA, dB to grad[atom][xyz] (see kgrad)
-  double *grad;
-  int gcopies, gstride;           // grad holds gcopies copies of gstride values; workgroup b adds to copy b % gcopies
-  const int *atom;                // atom of every shell
   // matrix output (orow != nullptr): (ab, cd) of quartet (ij, kl) goes to
   // V[orow[ij] + ab + ld * (ocol[kl] + cd)] instead of the class-batch layout
   const long *orow, *ocol;
@@ -154,6 +136,63 @@ struct Eri4Args {
   uint32_t wtask[kMaxWavesArgs];
 };
 
+// One class block of the screened quartet engine (kx.hip: K and J builds and
+// the nuclear gradient).  Side A holds shell pairs (a, b) of one class, side
+// B pairs (c, d) of one class, each sorted by decreasing Schwarz factor, so
+// the B pairs that pass Q_A Q_B >= tau with A pair i are a prefix of B: the
+// block's quartets are (i, k) with k < cnt(i) = pre[i+1] - pre[i] (same-list
+// blocks of the K and J builds keep k <= i as well).  A's Hermite functions
+// are the matrix-core rows of the ket product; B's are contracted.
+struct KxBlock {
+  long chunk0;            // first global chunk index of the block
+  long nq;                // quartets of the block
+  int chunk;              // quartets per chunk
+  const long *pre;        // [nA + 1] first quartet of every A pair
+  int nA;
+  int L;                  // Hermite degree of R (l_a+l_b+l_c+l_d, +1 in gradient mode)
+  int S1, S2;             // [r] cube strides
+  int NhA, HA_rows;       // A Hermite rows used, rows allocated per A matrix (multiple of 16)
+  int nparts;             // A row parts of NRT tiles
+  int NhB, NhB_pad;       // B Hermite rows, padded to a multiple of 8
+  int NA, NB, NA_pad, NB_pad, nct;  // solid components per side (padded to 16), B column tiles
+  int na, nb, nc, nd;     // N(l) of the four shells
+  int same;               // A and B are the same pair list
+  float inv_nb, inv_nd, inv_NB, inv_ncd;  // 1/nb, 1/nd, 1/NB, 1/(nc + nd) for index decoding
+  const uint32_t *Aorder; // A Hermite row order (HA_rows entries, see PairArgs::order)
+  const int *A_off, *B_off;            // primitive-pair offsets per pair [n + 1]
+  const double *A_G, *B_G, *A_H, *B_H; // pair data (A: derivative matrices in gradient mode)
+  const int *A_sh, *B_sh;              // shells of every pair [n][2]
+};
+
+// Arguments shared by every block of one launch of the quartet engine.
+struct KxArgs {
+  const KxBlock *blocks;  // device array, sorted by chunk0
+  int nblk;
+  long nchunk;            // chunks over all blocks
+  int chunk;              // quartets per chunk
+  unsigned long long *counter;  // next chunk to take (zero before the launch)
+  Tables tab;
+  const int *ao_off;      // first AO of every shell
+  int nao;
+  // digest mode: K' += the four exchange images, J' += the two Coulomb
+  // images (either may be null); K = K' + K'^T, J = J' + J'^T afterwards
+  const double *dm;       // density D [nao][nao] (symmetric)
+  double *kx, *jx;
+  // gradient mode: E = sum W_abcd (ab|cd) with W = Wl_ac Wr_bd (pattern 0) or
+  // Wl_ab Wr_cd (pattern 1), times scale; dE/dR of the A centres added to
+  // grad copy (workgroup % gcopies) at [atom][xyz]
+  const double *wl, *wr;
+  int pattern;
+  int symmetric;          // Wl = Wr and symmetric (caller's guarantee): one staged weight block
+  double scale;
+  double *grad;
+  int gcopies, gstride;
+  const int *atom;
+  // per-wave LDS layout (offsets in doubles from the wave's base)
+  int wave_doubles, o_work, o_v, o_d, o_img, o_g, o_tab;
+  int uv_max, oq_max;     // entries of the (u, v) table and of the B offset table
+};
+
 // Launchers (defined in the .hip files).
 hipError_t launch_pairs(const PairArgs &a, hipStream_t s);
 hipError_t launch_eri4(const Eri4Args &a, hipStream_t s);
@@ -163,8 +202,13 @@ hipError_t launch_schwarz_reduce(int npair, int Nab, const double *D, const int 
 hipError_t launch_symmetrize(int n, const double *in, double *out, hipStream_t s);
 // x[0..n) = 0 with a plain kernel (no memset node, capture-safe).
 hipError_t launch_zero(size_t n, double *x, hipStream_t s);
-// out[i] = sum_c in[c n + i] for i < n, c < copies.
-hipError_t launch_sum_copies(int n, int copies, const double *in, double *out, hipStream_t s);
+// out[i] = sum_c in[c n + i] for i < n, c < copies (added to out[i] when accumulate).
+hipError_t launch_sum_copies(int n, int copies, const double *in, double *out, hipStream_t s, int accumulate = 0);
+// out[0] = sum a[e] b1[e], out[1] = sum a[e] b2[e] over e < n (either b may be
+// null: its sum is 0), in a fixed order; work holds dot2_work_doubles().
+size_t dot2_work_doubles();
+hipError_t launch_dot2(size_t n, const double *a, const double *b1, const double *b2, double *work, double *out,
+                       hipStream_t s);
 // Work split of the fused kernel for one class.
 struct Eri4Plan {
   int npt;    // bra row tiles per consumer wave
@@ -174,10 +218,12 @@ struct Eri4Plan {
   int nslab;  // workgroups per quartet (column slabs)
 };
 // Chooses the split of the 4-centre kernel; false if the class does not
-// fit.  grad admits 7-tile consumer waves (built only for gradient mode);
-// slabs admits splitting the ket columns over workgroups (plain output only).
-bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int maxpp, bool grad, bool slabs,
-               Eri4Plan *p);
+// fit.  slabs admits splitting the ket columns over workgroups (plain output
+// only).
+bool eri4_plan(int Nhb, int Nb, int Nk, int L, int cube_sz, int Nhk_pad, int maxpp, bool slabs, Eri4Plan *p);
+// Launches the quartet engine for blocks sharing the row tile count npt
+// (1, 2 or 4) and the producer bucket of Lmax; grad selects gradient mode.
+hipError_t launch_kx(const KxArgs &a, int npt, int Lmax, bool grad, int waves, size_t lds, int grid, hipStream_t s);
 // Persistent task-list launch over class blocks that share npt and the
 // producer length bucket of Lmax: d_blocks[nblk] device copies of the blocks'
 // arguments, d_tasks[ntask] = (block, ij + nbra kl); the workgroup has

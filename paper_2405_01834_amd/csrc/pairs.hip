@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
     // d/dA_x (x_A^{a} e^{-za r_A^2}) = 2 za x_A^{a+1x} e^{..} - a_x x_A^{a-1x} e^{..},
     // the same for B: H^(X,x)[p][ab] = c_a c_b sum C C [2 z E^{(a+1x) b}_p - a_x E^{(a-1x) b}_p]
     // stored transposed, [mat][ab][p] with p fastest (the gradient stage of
-    // the fused kernel reads 16 consecutive p per lane group)
+    // the quartet engine reads 16 consecutive p per lane group)
     double *H = a.H + (size_t)pp * 6 * a.Nh_pad * a.N_pad;
     const int total = 6 * a.Nh_pad * a.N_pad;
     for (int e = tid; e < total; e += kPairThreads) {

@@ -27,13 +27,16 @@ def lib_path() -> str:
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("schwarz_tau", ctypes.c_double), ("flags", ctypes.c_int),
-                ("split_slices", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
+                ("split_slices", ctypes.c_int), ("tile_variant", ctypes.c_int), ("reserved", ctypes.c_int)]
 
 
 FLAG_GRAPH = 1
 FLAG_AUTOTUNE = 2
+FLAG_SYMMETRIC = 4
 FP64 = 0
 SPLIT_BF16 = 1
+EXCHANGE = 0
+COULOMB = 1
 
 
 _vp = ctypes.c_void_p
@@ -66,6 +69,8 @@ def load_library():
     L.mderi_eri4.argtypes = [_vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
                              ctypes.POINTER(Opts), _vp]
     L.mderi_eri4.restype = ctypes.c_int
+    L.mderi_eri4_tile_variants.argtypes = [_vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, ctypes.POINTER(ctypes.c_int)]
+    L.mderi_eri4_tile_variants.restype = ctypes.c_int
     L.mderi_eri4_noalloc.argtypes = [_vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
                                      ctypes.POINTER(Opts), _vp]
     L.mderi_eri4_noalloc.restype = ctypes.c_int
@@ -81,8 +86,13 @@ def load_library():
     L.mderi_kernel_timing.restype = ctypes.c_int
     L.mderi_kernel_times.argtypes = [_vp, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     L.mderi_kernel_times.restype = ctypes.c_int
-    L.mderi_kbuild_grad.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.POINTER(Opts), _vp]
+    L.mderi_jkbuild.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(Opts), _vp]
+    L.mderi_jkbuild.restype = ctypes.c_int
+    L.mderi_kbuild_grad.argtypes = [_vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_double, _vp, ctypes.c_int,
+                                    ctypes.c_int, ctypes.POINTER(Opts), _vp]
     L.mderi_kbuild_grad.restype = ctypes.c_int
+    L.mderi_basis_set_centers.argtypes = [_vp, _vp, _vp]
+    L.mderi_basis_set_centers.restype = ctypes.c_int
     L.mderi_schwarz.argtypes = [_vp, _vp, ctypes.c_int, _ip, _vp, _vp]
     L.mderi_schwarz.restype = ctypes.c_int
     _lib = L
@@ -133,7 +143,16 @@ class Context:
     def basis(self, l, nprim, exps, coefs, centers, atom=None, normalize=1) -> "Basis":
         return Basis(self, l, nprim, exps, coefs, centers, atom, normalize)
 
-    def eri4(self, basis: "Basis", bra, ket, out=None, stream=None, flags=0, precision=0, slices=0):
+    def eri4_tile_variants(self, basis: "Basis", bra, ket) -> int:
+        """Number of work splits the fused kernel supports for this class batch."""
+        bra = np.ascontiguousarray(np.asarray(bra, dtype=np.int32).reshape(-1, 2))
+        ket = np.ascontiguousarray(np.asarray(ket, dtype=np.int32).reshape(-1, 2))
+        n = ctypes.c_int(0)
+        _check(load_library().mderi_eri4_tile_variants(self._h, basis._h, len(bra), bra.ctypes.data_as(_ip), len(ket),
+                                                       ket.ctypes.data_as(_ip), ctypes.byref(n)))
+        return n.value
+
+    def eri4(self, basis: "Basis", bra, ket, out=None, stream=None, flags=0, precision=0, slices=0, tile_variant=0):
         """Class batch (ab|cd) -> torch float64 tensor V[ij, ab, cd, kl] (shape
         (nbra, Nab, Ncd, nket), a Fortran-order view of the flat output)."""
         import torch
@@ -147,7 +166,7 @@ class Context:
         if out is None:
             out = torch.empty(n, dtype=torch.float64, device=f"cuda:{self.device}")
         assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
-        opts = Opts(int(precision), 1e-12, int(flags), int(slices))
+        opts = Opts(int(precision), 1e-12, int(flags), int(slices), int(tile_variant))
         _check(load_library().mderi_eri4(self._h, basis._h, len(bra), bra.ctypes.data_as(_ip), len(ket),
                                          ket.ctypes.data_as(_ip), _vp(out.data_ptr()), out.numel(),
                                          ctypes.byref(opts), _stream_handle(stream)))
@@ -214,6 +233,23 @@ class Context:
                                                out.numel(), ctypes.byref(opts), _stream_handle(stream)))
         return out[:nrow * ncol].view(ncol, nrow).t()
 
+    def jkbuild(self, basis: "Basis", D, want_j=True, want_k=True, tau=1e-12, energies=False, stream=None):
+        """Coulomb J_ab = sum_cd (ab|cd) D_cd and exchange K_ac = sum_bd (ab|cd) D_bd
+        of a symmetric density D (torch float64 [nao, nao] on the device) ->
+        (J or None, K or None[, energies = float64 tensor [tr(DJ), tr(DK)]])."""
+        import torch
+        nao = basis.nao()
+        assert D.dtype == torch.float64 and D.is_cuda and D.shape == (nao, nao)
+        D = D.contiguous()
+        J = torch.empty((nao, nao), dtype=torch.float64, device=D.device) if want_j else None
+        K = torch.empty((nao, nao), dtype=torch.float64, device=D.device) if want_k else None
+        E = torch.empty(2, dtype=torch.float64, device=D.device) if energies else None
+        opts = Opts(0, float(tau))
+        ptr = lambda t: None if t is None else _vp(t.data_ptr())  # noqa: E731
+        _check(load_library().mderi_jkbuild(self._h, basis._h, _vp(D.data_ptr()), ptr(J), ptr(K), nao, ptr(E),
+                                            ctypes.byref(opts), _stream_handle(stream)))
+        return (J, K, E) if energies else (J, K)
+
     def kbuild(self, basis: "Basis", D, tau=1e-12, out=None, stream=None):
         """Exchange matrix K_ac = sum_bd (ab|cd) D_bd for a symmetric density D
         (torch float64 [nao, nao] on the device) -> K (same shape)."""
@@ -240,18 +276,28 @@ class Context:
         _check(load_library().mderi_kernel_times(self._h, buf.ctypes.data_as(_dp), len(buf), ctypes.byref(n)))
         return buf[:n.value].copy()
 
-    def kbuild_grad(self, basis: "Basis", D, natom, tau=1e-12, out=None, stream=None):
-        """dE/dR for E = tr(D K[D]) with D held fixed -> torch float64 [natom, 3]
-        (atoms as mapped by the basis' atom list)."""
+    def kbuild_grad(self, basis: "Basis", Wl, natom, Wr=None, pattern=EXCHANGE, scale=1.0, tau=1e-12, out=None,
+                    accumulate=False, symmetric=None, stream=None):
+        """dE/dR of E = scale sum W_abcd (ab|cd) with W = Wl_ac Wr_bd (pattern
+        EXCHANGE; Wl = Wr = D gives tr(D K[D])) or Wl_ab Wr_cd (COULOMB), W
+        held fixed -> torch float64 [natom, 3] (atoms as mapped by the basis'
+        atom list).  Wr defaults to Wl; symmetric (default: Wr is None, the
+        density case) declares Wl = Wr symmetric (MDERI_FLAG_SYMMETRIC)."""
         import torch
         nao = basis.nao()
-        assert D.dtype == torch.float64 and D.is_cuda and D.shape == (nao, nao)
-        D = D.contiguous()
+        if symmetric is None:
+            symmetric = Wr is None
+        Wr = Wl if Wr is None else Wr
+        for W in (Wl, Wr):
+            assert W.dtype == torch.float64 and W.is_cuda and W.shape == (nao, nao)
+        Wl, Wr = Wl.contiguous(), Wr.contiguous()
         if out is None:
-            out = torch.empty((natom, 3), dtype=torch.float64, device=D.device)
-        opts = Opts(0, float(tau))
-        _check(load_library().mderi_kbuild_grad(self._h, basis._h, _vp(D.data_ptr()), nao, _vp(out.data_ptr()),
-                                                int(natom), ctypes.byref(opts), _stream_handle(stream)))
+            out = torch.zeros((natom, 3), dtype=torch.float64, device=Wl.device)
+        opts = Opts(0, float(tau), FLAG_SYMMETRIC if (symmetric and Wr is Wl) else 0)
+        _check(load_library().mderi_kbuild_grad(self._h, basis._h, int(pattern), _vp(Wl.data_ptr()),
+                                                _vp(Wr.data_ptr()), nao, float(scale), _vp(out.data_ptr()),
+                                                int(natom), int(bool(accumulate)), ctypes.byref(opts),
+                                                _stream_handle(stream)))
         return out
 
     def schwarz(self, basis: "Basis", pairs, stream=None):
@@ -295,6 +341,15 @@ class Basis:
     def nao(self):
         return int(load_library().mderi_basis_nao(self._h))
 
+    def set_centers(self, centers, stream=None):
+        """Moves the shells to centers (torch float64 [nshell, 3] on the
+        device), copied on the stream; the tensor must stay alive until the
+        stream reaches the copy."""
+        import torch
+        assert centers.dtype == torch.float64 and centers.is_cuda and centers.shape == (self.nshell, 3)
+        assert centers.is_contiguous()
+        _check(load_library().mderi_basis_set_centers(self._h, _vp(centers.data_ptr()), _stream_handle(stream)))
+
     def close(self):
         if getattr(self, "_h", None):
             load_library().mderi_basis_free(self._h)
@@ -307,13 +362,14 @@ class Basis:
             pass
 
 
-def exchange_energy(ctx: Context, coords, D, shells, tau=1e-12):
+def exchange_energy(ctx: Context, coords, D, basis: "Basis", tau=1e-12):
     """E = tr(D K[D]) as a differentiable function of atom coordinates
     coords [natom, 3] (bohr) and the symmetric density D [nao, nao] (both
-    float64 on the device).  shells = (l, nprim, exps, coefs, atom) places
-    shell s at coords[atom[s]].  Backward: dE/dcoords from mderi_kbuild_grad,
-    dE/dD = 2 K."""
-    return _ExchangeEnergy.apply(coords, D, ctx, shells, float(tau))
+    float64 on the device).  `basis` is an uploaded Basis with an atom map;
+    its shells are moved to coords[atom] on the device (mderi_basis_set_centers)
+    before the build.  Forward: E from mderi_jkbuild; backward: dE/dcoords
+    from mderi_kbuild_grad, dE/dD = 2 K."""
+    return _ExchangeEnergy.apply(coords, D, ctx, basis, float(tau))
 
 
 def _make_exchange_function():
@@ -321,21 +377,21 @@ def _make_exchange_function():
 
     class ExchangeEnergy(torch.autograd.Function):
         @staticmethod
-        def forward(fctx, coords, D, ctx, shells, tau):
-            l, nprim, exps, coefs, atom = shells
-            atom = np.ascontiguousarray(atom, dtype=np.int32)
-            centers = coords.detach().cpu().numpy()[atom]
-            basis = Basis(ctx, l, nprim, exps, coefs, centers, atom=atom)
-            K = ctx.kbuild(basis, D.detach(), tau=tau)
+        def forward(fctx, coords, D, ctx, basis, tau):
+            atom = torch.as_tensor(basis.atom, dtype=torch.long, device=coords.device)
+            centers = coords.detach()[atom].contiguous()
+            basis.set_centers(centers)
+            _, K, E = ctx.jkbuild(basis, D.detach(), want_j=False, tau=tau, energies=True)
             fctx.ctx, fctx.basis, fctx.tau, fctx.natom = ctx, basis, tau, coords.shape[0]
-            fctx.save_for_backward(D.detach(), K)
-            return (D.detach() * K).sum()
+            fctx.save_for_backward(D.detach(), K, centers)
+            return E[1]
 
         @staticmethod
         def backward(fctx, gE):
-            D, K = fctx.saved_tensors
+            D, K, centers = fctx.saved_tensors
             gc = gD = None
             if fctx.needs_input_grad[0]:
+                fctx.basis.set_centers(centers)
                 gc = gE * fctx.ctx.kbuild_grad(fctx.basis, D, fctx.natom, tau=fctx.tau)
             if fctx.needs_input_grad[1]:
                 gD = 2.0 * gE * K

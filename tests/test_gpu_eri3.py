@@ -99,3 +99,36 @@ def test_eri3_batch_mixed_classes(ctx, flags):
         err = np.abs(got - ref)
         bad = err > ATOL + RTOL * np.abs(ref)
         assert not bad.any(), f"rep {rep}: {bad.sum()} of {bad.size} outside tolerance; max err {err.max():.3e}"
+
+
+def _class_batch_matrix(sh, aux, pairs, auxidx):
+    """Oracle batch matrix for pairs of one class and aux shells of one l."""
+    ob = oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, 1)
+    oa = oracle.Basis(aux.l, aux.nprim, aux.exps, aux.coefs, aux.centers, 1)
+    V = oracle.eri3(ob, oa, pairs, auxidx)  # [ij, ab, mP, k]
+    npair, nab, nP, naux = V.shape
+    return np.transpose(V, (0, 1, 3, 2)).reshape(npair * nab, naux * nP)
+
+
+@pytest.mark.parametrize("la,lb,lP,npair,naux", [(1, 0, 1, 80, 80), (2, 1, 3, 72, 64)])
+def test_eri3_batch_workgroups_loop(ctx, la, lb, lP, npair, naux):
+    """One class block of more triplets (6,400 and 4,608) than the persistent
+    launch has workgroups, so every workgroup runs several tasks and reuses
+    its LDS; against the oracle, plain and with the graph flag."""
+    import torch
+    from paper_2405_01834_amd.mderi import FLAG_GRAPH
+    rng = np.random.default_rng(90 + la + lP)
+    sh = inputs.random_shells(rng, [la, lb] * npair, [1, 2] * npair, 8.0, 0.05, 200.0)
+    aux = inputs.random_shells(rng, [lP] * naux, 1, 8.0, 0.05, 200.0)
+    pairs = np.arange(2 * npair, dtype=np.int32).reshape(-1, 2)
+    auxidx = np.arange(naux, dtype=np.int32)
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    a = ctx.basis(aux.l, aux.nprim, aux.exps, aux.coefs, aux.centers)
+    ref = _class_batch_matrix(sh, aux, pairs, auxidx)
+    for flags in (0, FLAG_GRAPH, FLAG_GRAPH):
+        Bm = ctx.eri3_batch(b, a, pairs, auxidx, flags=flags)
+        torch.cuda.synchronize()
+        got = Bm.cpu().numpy()
+        err = np.abs(got - ref)
+        bad = err > ATOL + RTOL * np.abs(ref)
+        assert not bad.any(), f"flags {flags}: {bad.sum()} of {bad.size} outside; max err {err.max():.3e}"

@@ -189,3 +189,32 @@ def test_every_total_l(ctx, L):
         for k, (q0, q1) in enumerate(ket):
             ref = md_matrix.shellset(sh, p0, p1, q0, q1)
             _assert_close(got[i, :, :, k], ref, f"L={L} {(la, lb, lc, ld)} quartet ({i},{k})")
+
+
+@pytest.mark.parametrize("cls,K", [((2, 2, 2, 2), 1), ((3, 2, 2, 1), 2), ((4, 4, 4, 4), 1), ((3, 3, 3, 3), 3)])
+def test_every_tile_variant(ctx, cls, K):
+    """Every work split the autotuner may choose (mderi_eri4_tile_variants),
+    forced one at a time, against the oracle; and the autotuned call."""
+    import torch
+    from paper_2405_01834_amd.mderi import FLAG_AUTOTUNE
+    la, lb, lc, ld = cls
+    nbra, nket = (3, 4) if max(cls) < 4 else (2, 2)
+    sh_b, bra = inputs.near_pairs(700 + 7 * sum(cls) + K, la, lb, K, nbra, box=6.0)
+    sh_k, ket = inputs.near_pairs(800 + 7 * sum(cls) + K, lc, ld, K, nket, box=6.0)
+    sh = sh_b.concat(sh_k)
+    ket = ket + sh_b.n
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    nv = ctx.eri4_tile_variants(b, bra, ket)
+    assert nv >= 1
+    ref = oracle.eri4(oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, 1), bra, ket)
+    for v in range(1, nv + 1):
+        print(f"tile variant {v} of {nv} for {cls} K={K}", flush=True)
+        V = ctx.eri4(b, bra, ket, tile_variant=v)
+        torch.cuda.synchronize()
+        _assert_close(V.cpu().numpy(), ref, f"{cls} K={K} variant {v}")
+    V = ctx.eri4(b, bra, ket, flags=FLAG_AUTOTUNE)
+    torch.cuda.synchronize()
+    _assert_close(V.cpu().numpy(), ref, f"{cls} K={K} autotuned")
+    from paper_2405_01834_amd import MderiError
+    with pytest.raises(MderiError):
+        ctx.eri4(b, bra, ket, tile_variant=nv + 1)

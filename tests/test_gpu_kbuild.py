@@ -55,7 +55,8 @@ def test_kbuild_parity(ctx, seed, natom, shells, spread):
 def test_kbuild_workspace_reuse(ctx):
     """K builds and gradients of two molecules interleaved on one context: the
     pair-data workspace is reused with stale contents (larger, then smaller,
-    then larger again) and every K still meets the oracle's tolerance."""
+    then larger again) and every K and gradient still meets the oracle's
+    tolerance."""
     import torch
     specs = {"big": (11, 3, ((0, 2), (1, 1), (2, 1), (3, 1)), 3.0),
              "small": (12, 2, ((0, 1), (1, 1)), 2.0)}
@@ -66,14 +67,17 @@ def test_kbuild_workspace_reuse(ctx):
         b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, atom=atom)
         C = np.random.default_rng(seed + 100).normal(size=(b.nao(), 3)) / np.sqrt(b.nao())
         D = C @ C.T
-        ref = oracle.kbuild(oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, 1), D, tau=1e-12)
-        mols[name] = (b, natom, D, ref)
+        ob = oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, 1)
+        ref = oracle.kbuild(ob, D, tau=1e-12)
+        gref = oracle.exchange_grad(ob, atom, natom, D, tau=1e-12)
+        mols[name] = (b, natom, D, ref, gref)
     for name in ("big", "small", "big", "small"):
-        b, natom, D, ref = mols[name]
+        b, natom, D, ref, gref = mols[name]
         Dd = torch.tensor(D, device="cuda")
         g = ctx.kbuild_grad(b, Dd, natom, tau=1e-12)
         K = ctx.kbuild(b, Dd, tau=1e-12)
         torch.cuda.synchronize()
-        assert torch.isfinite(g).all()
+        gerr = np.max(np.abs(g.cpu().numpy() - gref))
+        assert gerr <= 1e-11 * np.max(np.abs(gref)), (name, gerr, np.max(np.abs(gref)))
         err = np.max(np.abs(K.cpu().numpy() - ref))
         assert err <= 1e-12 * np.max(np.abs(ref)), (name, err, np.max(np.abs(ref)))

@@ -67,8 +67,10 @@ def test_kgrad_autograd_and_fd(ctx):
     from paper_2405_01834_amd.mderi import exchange_energy
     seed, natom, shells, spread = CASES[1]
     sh, pos, atom = _molecule(seed, natom, shells, spread)
-    spec = (sh.l, sh.nprim, sh.exps, sh.coefs, atom)
-    nao = int(sum(2 * l + 1 for l in sh.l))
+    # the autograd function moves the shells of its own basis to the
+    # coordinates on the device (mderi_basis_set_centers)
+    spec = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers + 1.0, atom=atom)
+    nao = spec.nao()
     D0 = _density(seed, nao)
     coords = torch.tensor(pos, device="cuda", requires_grad=True)
     D = torch.tensor(D0, device="cuda", requires_grad=True)

@@ -1,8 +1,9 @@
 """Split-precision bra transform (BF16 matrix cores, rows balanced by powers
 of two, operands split into S 7-bit integer slices, exact FP32 block sums,
-FP64 combination) against the FP64 references, per shellset
-(max |dV| - 1e-14) / max |V|: S = 7 within 1e-10; S = 6 and S = 5 within the bounds
-measured for these classes with a margin (the error grows with the
+FP64 combination) against the FP64 references (the oracle; the matrix-form
+reference at l = 5, 6), per shellset (max |dV| - 1e-14) / max |V|: S = 6 and
+S = 7 within the 1e-10 that the precision target states; S = 5 within the
+bound measured for these classes with a margin (the error grows with the
 cancellation in the bra sum, largest for [gg|gg])."""
 import numpy as np
 import pytest
@@ -12,7 +13,7 @@ from paper_2405_01834_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-BOUNDS = {5: 1e-7, 6: 1e-9, 7: 1e-10}
+BOUNDS = {5: 1e-7, 6: 1e-10, 7: 1e-10}
 
 
 @pytest.fixture(scope="module")
@@ -54,20 +55,24 @@ def test_split_vs_oracle(ctx, cls, K, S):
     assert err <= BOUNDS[S], err
 
 
-@pytest.mark.parametrize("S", [5, 7])
+@pytest.mark.parametrize("S", [5, 6, 7])
 @pytest.mark.parametrize("l", [5, 6])
-def test_split_high_l_vs_fp64(ctx, l, S):
-    """[hh|hh], [ii|ii] (column-slab kernels): split against the FP64 path,
-    which the high-l parity tests pin to the matrix-form reference."""
+def test_split_high_l_vs_matrix_form(ctx, l, S):
+    """[hh|hh], [ii|ii] (column-slab kernels): split precision against the
+    matrix-form reference (tests/ref/md_matrix, pinned to the oracle)."""
     import torch
     from paper_2405_01834_amd.mderi import SPLIT_BF16
+    from tests.ref import md_matrix
     rng = np.random.default_rng(600 + l)
     sh = inputs.random_shells(rng, [l] * 8, 1, 4.0, 0.1, 30.0)
     pairs = np.arange(8, dtype=np.int32).reshape(-1, 2)
     b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
-    ref = ctx.eri4(b, pairs[:2], pairs[2:]).cpu().numpy()
     got = ctx.eri4(b, pairs[:2], pairs[2:], precision=SPLIT_BF16, slices=S).cpu().numpy()
     torch.cuda.synchronize()
+    ref = np.zeros_like(got)
+    for ij, (i, j) in enumerate(pairs[:2]):
+        for kl, (k, m) in enumerate(pairs[2:]):
+            ref[ij, :, :, kl] = md_matrix.shellset(sh, i, j, k, m)
     err = _per_shellset_err(np.moveaxis(got, 3, 1).reshape(-1, got.shape[1], got.shape[2]),
                             np.moveaxis(ref, 3, 1).reshape(-1, ref.shape[1], ref.shape[2]))
     assert err <= BOUNDS[S], err
