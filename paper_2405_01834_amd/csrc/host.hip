@@ -1683,7 +1683,7 @@ struct KxClass {
 };
 
 struct KxPlanBlock {
-  int cA, cB, same, L, npt, nparts, S1, S2;
+  int cA, cB, same, onev, L, npt, nparts, S1, S2;
   long nq;
   double cost;  // rough cycles of one quartet on one wave
   std::vector<long> pre;
@@ -1723,23 +1723,28 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       k.sh.push_back(ps.pairs[2 * p + 1]);
     }
   }
-  // blocks: unordered class pairs for the builds (the cheaper orientation),
-  // ordered ones for the gradient (each supplies its A centres)
+  // blocks: unordered class pairs for the builds, and for the gradient
+  // when every pair of both classes is a single primitive pair (one visit
+  // supplies all four centres); the cheaper orientation.  Otherwise the
+  // gradient takes ordered class pairs (each visit supplies its A centres).
   std::vector<KxPlanBlock> blocks;
   for (int x = 0; x < ncls; ++x)
     for (int y = 0; y < ncls; ++y) {
       if (C[x].q.empty() || C[y].q.empty()) continue;
-      if (!job.grad && y < x) continue;
+      const bool onev = job.grad && C[x].maxpp == 1 && C[y].maxpp == 1;
+      const bool unordered = !job.grad || onev;
+      if (unordered && y < x) continue;
       int cA = x, cB = y;
       auto cost_of = [&](int u, int v) {
         const KxClass &A = C[u], &B = C[v];
         return kx_cost(A.NhA, A.NA, B.NhB_pad, B.NA, A.LA + B.Lc, B.NA_pad / 16);
       };
-      if (!job.grad && x != y && cost_of(y, x) < cost_of(x, y)) std::swap(cA, cB);
+      if (unordered && x != y && cost_of(y, x) < cost_of(x, y)) std::swap(cA, cB);
       KxPlanBlock pb{};
       pb.cA = cA;
       pb.cB = cB;
       pb.same = (cA == cB) ? 1 : 0;
+      pb.onev = onev ? 1 : 0;
       const KxClass &A = C[cA], &B = C[cB];
       pb.L = A.LA + B.Lc;
       const int nA = (int)A.q.size();
@@ -1753,7 +1758,7 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
           else hi = mid;
         }
         long cnt = lo;
-        if (pb.same && !job.grad) cnt = std::min<long>(cnt, i + 1);
+        if (pb.same && unordered) cnt = std::min<long>(cnt, i + 1);
         pb.pre[i + 1] = pb.pre[i] + cnt;
       }
       pb.nq = pb.pre[nA];
@@ -1820,16 +1825,20 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
     G.push_back(std::move(g));
   }
   const size_t meta_bytes = img.bytes.size();
-  const int mats = job.grad ? 6 : 1;
+  // matrices per primitive pair: A role 7 in gradient mode (six derivative
+  // matrices and the plain one), B role 4 for single-primitive classes in
+  // gradient mode (plain and three relative-coordinate derivatives)
+  const int matsA = job.grad ? 7 : 1;
+  auto matsB = [&](const KxClass &k) { return (job.grad && k.maxpp == 1) ? 4 : 1; };
   for (auto &k : C) {
     const int npp = (int)ps.sides[&k - &C[0]].pp.size();
     if (k.asA) {
       k.o_GA = img.add(nullptr, sizeof(double) * 4 * npp);
-      k.o_HA = img.add(nullptr, sizeof(double) * mats * (size_t)k.nh_alloc * k.NA_pad * npp);
+      k.o_HA = img.add(nullptr, sizeof(double) * matsA * (size_t)k.nh_alloc * k.NA_pad * npp);
     }
     if (k.asB) {
       k.o_GB = img.add(nullptr, sizeof(double) * 4 * npp);
-      k.o_HB = img.add(nullptr, sizeof(double) * (size_t)k.NhB_pad * k.NA_pad * npp);
+      k.o_HB = img.add(nullptr, sizeof(double) * matsB(k) * (size_t)k.NhB_pad * k.NA_pad * npp);
     }
   }
   for (auto &g : G) g.o_counter = img.add(nullptr, sizeof(unsigned long long));
@@ -1874,6 +1883,10 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       x.nc = nsph(B.la);
       x.nd = nsph(B.lb);
       x.same = pb.same;
+      x.onev = pb.onev;
+      x.A_mats = matsA;
+      x.B_mats = matsB(B);
+      x.B_pp = (const PrimPair *)dev(B.o_pp);
       x.inv_nb = 1.0f / (float)x.nb;
       x.inv_nd = 1.0f / (float)x.nd;
       x.inv_NB = 1.0f / (float)x.NB;
@@ -1899,7 +1912,7 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       single = single && A.maxpp == 1 && B.maxpp == 1;
       g_max = std::max(g_max, 4 * (A.maxpp + B.maxpp));
       uv_max = std::max(uv_max, (pb.L + 1) * (pb.L + 2) / 2);
-      oq_max = std::max(oq_max, x.NhB_pad);
+      oq_max = std::max(oq_max, round16(x.NhB_pad));
       op_max = std::max(op_max, x.HA_rows);
     }
     g.nchunk = chunk0;
@@ -1941,6 +1954,7 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
     ar.gcopies = job.gcopies;
     ar.gstride = job.gstride;
     ar.atom = b->dev.atom;
+    ar.exps = b->dev.exps;
     memcpy(img.bytes.data() + g.o_blocks, g.blks.data(), sizeof(KxBlock) * g.blks.size());
   }
 
@@ -1976,6 +1990,7 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       pa.Nh = k.NhB;
       pa.Nh_pad = k.NhB_pad;
       pa.deriv = 0;
+      pa.rderiv = matsB(k) == 4 ? 1 : 0;
       pa.order = nullptr;
       pa.ket_sign = 1;
       pa.G = (double *)dev(k.o_GB);

@@ -83,7 +83,10 @@ struct PairArgs {
   int ket_sign;  // fold (-1)^{|q|} of Eq. (pq) into a ket transform matrix
   int one_centre;  // single shells (lb ignored): Eqs. (E1rr)-(E1-aa), zeta_p = zeta_a, P = A
   int deriv;       // write the six centre-derivative matrices d/dA_x, d/dB_x (see pairs.hip)
-                   // transposed, H[6][N_pad][Nh_pad]; rows then span |p| <= la+lb+1
+                   // transposed, H[6][N_pad][Nh_pad] (rows then span |p| <= la+lb+1), then the
+                   // plain matrix [Nh_pad][N_pad]: 7 matrices per primitive pair
+  int rderiv;      // write the plain matrix, then the three derivatives with respect to the
+                   // relative coordinate A - B at fixed P, each [Nh_pad][N_pad]: 4 matrices
   // split precision: also write the matrix as `split` BF16 slices of
   // 7-bit integers relative to a power-of-two exponent per column ab (see
   // pairs.hip), rows in the k order of the BF16 matrix-core operand
@@ -157,6 +160,10 @@ struct KxBlock {
   int NA, NB, NA_pad, NB_pad, nct;  // solid components per side (padded to 16), B column tiles
   int na, nb, nc, nd;     // N(l) of the four shells
   int same;               // A and B are the same pair list
+  int A_mats, B_mats;     // matrices stored per primitive pair (A: 1, or 7 in gradient mode; B: 1 or 4)
+  int onev;               // gradient: one visit per quartet supplies all four centres (single-
+                          // primitive pairs; B side through Z = [p+q]^T (H_A S) and dH_B/d(C-D))
+  const PrimPair *B_pp;   // primitive pairs of B (exponents of the one-visit split)
   float inv_nb, inv_nd, inv_NB, inv_ncd;  // 1/nb, 1/nd, 1/NB, 1/(nc + nd) for index decoding
   const uint32_t *Aorder; // A Hermite row order (HA_rows entries, see PairArgs::order)
   const int *A_off, *B_off;            // primitive-pair offsets per pair [n + 1]
@@ -188,6 +195,7 @@ struct KxArgs {
   double *grad;
   int gcopies, gstride;
   const int *atom;
+  const double *exps;     // basis exponents
   // per-wave LDS layout (offsets in doubles from the wave's base)
   int wave_doubles, o_work, o_v, o_d, o_img, o_g, o_tab;
   int uv_max, oq_max;     // entries of the (u, v) table and of the B offset table

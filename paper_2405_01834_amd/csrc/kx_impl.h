@@ -85,7 +85,7 @@ __device__ __forceinline__ void block_tables(const KxArgs &g, const KxBlock &a, 
     (void)ylayout(L, v, &vb);
     uvsh[e] = (uint32_t)u | ((uint32_t)v << 8) | ((uint32_t)(vb + u) << 16);
   }
-  for (int q = lane; q < a.NhB_pad; q += 64) {
+  for (int q = lane; q < ((a.NhB_pad + 15) & ~15); q += 64) {  // whole 16-row tiles
     const uint32_t h = q < a.NhB ? g.tab.herm[q] : kPadRow;
     offq[q] = (h & kPadRow) ? 0 : (int)(h & 0xff) * a.S1 + (int)((h >> 8) & 0xff) * a.S2 + (int)((h >> 16) & 0xff);
   }
@@ -181,7 +181,7 @@ __device__ __forceinline__ void stage_quartet(const KxArgs &g, const KxBlock &a,
 // S = Wbar(A,B)[ab][cd] + Wbar(B,A)[cd][ab], with Wbar(A,B) collecting the
 // orderings (ab|cd), (ba|cd), (ab|dc), (ba|dc) of distinct shells.
 __device__ __forceinline__ void grad_weights(const KxArgs &g, const KxBlock &a, int si, int sj, int sk, int sl, int ct,
-                                             const double *dsh, double *v, int lane) {
+                                             double wscale, const double *dsh, double *v, int lane) {
   const int na = a.na, nb = a.nb, nc = a.nc, nd = a.nd, nab = na + nb, ncd = nc + nd;
   const int NA = a.NA, NB = a.NB;
   const double ffi = si != sj ? 1.0 : 0.0, ffk = sk != sl ? 1.0 : 0.0;
@@ -212,7 +212,7 @@ __device__ __forceinline__ void grad_weights(const KxArgs &g, const KxBlock &a, 
         s = fma(u1[ab], u2[cd], u3[cd] * u4[ab]);
       }
     }
-    v[e] = g.scale * s;
+    v[e] = wscale * s;
   }
 }
 
@@ -336,9 +336,14 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
   const int ntiles = (a.NhA + 15) >> 4;
   const int nat = a.NA_pad >> 4;
   const int NA = a.NA;
+  double rq[3] = {0.0, 0.0, 0.0};  // one-visit: derivative along C - D of the B pair
+  // S is the weight of (ab|cd) summed over both assignments of the two
+  // pairs; a one-visit quartet whose two pairs are the same pair takes all
+  // four centres' derivatives of an integral that appears once, so half
+  const double wscale = (GRAD && a.onev && a.same && i == k) ? 0.5 * g.scale : g.scale;
   for (int ct = 0; ct < a.nct; ++ct) {
     const int col = ct * 16 + c;  // this lane's B column cd
-    if (GRAD) grad_weights(g, a, si, sj, sk, sl, ct, dsh, vsh, lane);
+    if (GRAD) grad_weights(g, a, si, sj, sk, sl, ct, wscale, dsh, vsh, lane);
     else
       for (int e = lane; e < a.NA_pad * 16; e += 64) vsh[e] = 0.0;
     lds_wave_sync();
@@ -357,7 +362,7 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
             lds_wave_sync();  // the previous step's gathers are done with the cube
             build(ia, ib);
           }
-          const double *Hk = a.B_H + (size_t)(bp0 + ib) * a.NhB_pad * a.NB_pad + col;
+          const double *Hk = a.B_H + (size_t)(bp0 + ib) * a.B_mats * a.NhB_pad * a.NB_pad + col;
           // X[p][cd] += sum_q [p+q] H_B[q][cd] in blocks of four k-steps:
           // the H_B values of the next block are loaded before this block's
           // gathers and products (indices clamped, so every load is
@@ -429,7 +434,7 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
           // with the derivative matrices ([m][ab][p], p fastest).
           const int mstride = a.HA_rows * a.NA_pad;  // doubles per derivative matrix
           const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
-              (void *)(a.A_H + (size_t)(ap0 + ia) * 6 * mstride), (short)0, 6 * mstride * 8, kBufferWord3);
+              (void *)(a.A_H + (size_t)(ap0 + ia) * a.A_mats * mstride), (short)0, 6 * mstride * 8, kBufferWord3);
           auto grd = [&](auto ntc) {
             constexpr int NT = decltype(ntc)::value;
 #pragma unroll 1
@@ -451,6 +456,54 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
             }
           };
           with_tiles<NRT>(ntw, grd);
+          if (a.onev) {
+            // B-pair centres (one-visit blocks, single primitives): with
+            // T[p][cd] = sum_ab H_A[p][ab] S[ab][cd] and Z[q][cd] =
+            // sum_p [p+q] T[p][cd], the derivative of sum S (ab|cd) along
+            // the relative coordinate C - D of the B pair is
+            // sum_q,cd dH_B/d(C-D)[q][cd] Z[q][cd]; T stays in the
+            // accumulator layout, which is Z's B operand
+            const double *Ha = a.A_H + (size_t)(ap0 + ia) * a.A_mats * mstride + (size_t)6 * mstride;
+            const int mB = a.NhB_pad * a.NB_pad;
+            const double *Hr = a.B_H + (size_t)bp0 * a.B_mats * mB + mB;  // the three d/d(C-D) matrices
+            auto zb = [&](auto ntc) {
+              constexpr int NT = decltype(ntc)::value;
+              d4 T[NT];
+#pragma unroll
+              for (int pt = 0; pt < NT; ++pt) T[pt] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+              for (int ks = 0; ks < (a.NA_pad >> 2); ++ks) {
+                const double sb = vsh[(4 * ks + gq) * 16 + c];  // B[k = ab][j = cd] = S[4 ks + k][16 ct + j]
+#pragma unroll
+                for (int pt = 0; pt < NT; ++pt) {
+                  const double ha = Ha[(size_t)((t0 + pt) * 16 + c) * a.NA_pad + 4 * ks + gq];  // A[i = p][k = ab]
+                  T[pt] = mfma16x16x4(ha, sb, T[pt]);
+                }
+              }
+#pragma unroll 1
+              for (int qt = 0; qt < (a.NhB_pad + 15) >> 4; ++qt) {
+                const int oqr = offq[qt * 16 + c];
+                d4 z = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int pt = 0; pt < NT; ++pt)
+#pragma unroll
+                  for (int r = 0; r < 4; ++r)
+                    z = mfma16x16x4(cube[oqr + offp[(t0 + pt) * 16 + 4 * r + gq]], T[pt][r], z);
+                // z[r] = Z[q = 16 qt + 4 r + g][cd = 16 ct + c]
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const int q = qt * 16 + 4 * r + gq;
+                  if (q < a.NhB_pad) {
+                    const size_t o = (size_t)q * a.NB_pad + col;
+                    rq[0] = fma(z[r], Hr[o], rq[0]);
+                    rq[1] = fma(z[r], Hr[mB + o], rq[1]);
+                    rq[2] = fma(z[r], Hr[2 * (size_t)mB + o], rq[2]);
+                  }
+                }
+              }
+            };
+            with_tiles<NRT>(ntw, zb);
+          }
         }
       }
     }
@@ -461,6 +514,47 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
     lds_wave_sync();  // the next tile overwrites v
   }
   if constexpr (!GRAD) digest_flush(g, a, i, k, si, sj, sk, sl, img, lane);
+  if (GRAD && a.onev) {
+    // this quartet's four centres: the A pair's from the derivative dots,
+    // the B pair's by translational invariance, d/dC + d/dD = -(d/dA +
+    // d/dB), split as d/dC = (zeta_c/q) d/dQ + d/d(C-D), d/dD =
+    // (zeta_d/q) d/dQ - d/d(C-D) with d/dQ = -(d/dA + d/dB)
+    double v[9];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      v[m] = gpart[m];
+      gpart[m] = 0.0;
+    }
+#pragma unroll
+    for (int x = 0; x < 3; ++x) v[6 + x] = rq[x];
+#pragma unroll
+    for (int m = 0; m < 9; ++m)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v[m] += __shfl_xor(v[m], off);
+    if (lane < 12) {
+      const int x = lane % 3;
+      double dA = v[0], dB = v[3], r = v[6];
+#pragma unroll
+      for (int y = 1; y < 3; ++y)
+        if (x == y) {
+          dA = v[y];
+          dB = v[3 + y];
+          r = v[6 + y];
+        }
+      double val;
+      int sh;
+      if (lane < 6) {
+        val = lane < 3 ? dA : dB;
+        sh = lane < 3 ? si : sj;
+      } else {
+        const PrimPair pr = a.B_pp[bp0];
+        const double zc = g.exps[pr.pa], zd = g.exps[pr.pb], dq = -(dA + dB);
+        val = lane < 9 ? fma(zc / (zc + zd), dq, r) : fma(zd / (zc + zd), dq, -r);
+        sh = lane < 9 ? sk : sl;
+      }
+      atomicAdd(&g.grad[(size_t)(blockIdx.x % g.gcopies) * g.gstride + 3 * g.atom[sh] + x], val);
+    }
+  }
   lds_wave_sync();  // the next quartet may overwrite the wave's LDS
 }
 

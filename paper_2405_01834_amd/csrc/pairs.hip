@@ -45,7 +45,8 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
     // Eq. (E2-000); a single Gaussian has E^0_0 = 1 and, with zeta_b = 0 and
     // P = A, Eq. (E2rr1) reduces to Eq. (E1rr)
     Ex[0][0][0] = exp(-mu * XAB * XAB);
-    const int lae = la + a.deriv, lbe = lb + a.deriv;  // one more on each centre for derivatives
+    const int up = (a.deriv || a.rderiv) ? 1 : 0;
+    const int lae = la + up, lbe = lb + up;  // one more on each centre for derivatives
     for (int i = 0; i < lae; ++i)  // Eq. (E2rr1), b = 0
       for (int t = 0; t <= i + 1; ++t)
         Ex[i + 1][0][t] = (t > 0 ? o2p * Ex[i][0][t - 1] : 0.0) + XPA * Ex[i][0][t] + (t + 1) * Ex[i][0][t + 1];
@@ -70,7 +71,7 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
     // the same for B: H^(X,x)[p][ab] = c_a c_b sum C C [2 z E^{(a+1x) b}_p - a_x E^{(a-1x) b}_p]
     // stored transposed, [mat][ab][p] with p fastest (the gradient stage of
     // the quartet engine reads 16 consecutive p per lane group)
-    double *H = a.H + (size_t)pp * 6 * a.Nh_pad * a.N_pad;
+    double *H = a.H + (size_t)pp * 7 * a.Nh_pad * a.N_pad;
     const int total = 6 * a.Nh_pad * a.N_pad;
     for (int e = tid; e < total; e += kPairThreads) {
       const int mat = e / (a.Nh_pad * a.N_pad);
@@ -114,9 +115,10 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
       }
       H[e] = h;
     }
-    return;
+    // the plain matrix follows the six derivative matrices ([p][ab], no sign)
   }
-  double *H = a.H + (size_t)pp * a.Nh_pad * a.N_pad;
+  const size_t mats = a.deriv ? 7 : a.rderiv ? 4 : 1;
+  double *H = a.H + (size_t)pp * mats * a.Nh_pad * a.N_pad + (a.deriv ? 6 * (size_t)a.Nh_pad * a.N_pad : 0);
   const int total = a.Nh_pad * a.N_pad;
   for (int e = tid; e < total; e += kPairThreads) {
     const int ph = e / a.N_pad;
@@ -144,6 +146,55 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
       if (a.ket_sign && ((t + u + v) & 1)) h = -h;
     }
     H[e] = h;
+  }
+  if (a.rderiv) {
+    // derivatives with respect to the relative coordinate R = A - B at fixed
+    // P (ket pairs: d/dC = (zeta_c/q) d/dQ + d/dR); with Lambda_t the
+    // derivatives of exp(-p x_P^2) with respect to P_x (so d/dP Lambda_t =
+    // Lambda_{t+1}) and d/dA x_A^i = 2 za x_A^{i+1} - i x_A^{i-1}, the
+    // coefficient of Lambda_t in d/dR_x of x_A^i x_B^j e^{..} is
+    //   2 za E^{i+1,j}_t - i E^{i-1,j}_t - (za / p) E^{ij}_{t-1};
+    // matrices 1..3 after the plain one, [x][p][ab], ket sign included
+    const double za_p = za / p;
+    double *Hr = H + (size_t)a.Nh_pad * a.N_pad;
+    for (int e = tid; e < 3 * total; e += kPairThreads) {
+      const int dir = e / total, rem = e - dir * total;
+      const int ph = rem / a.N_pad, ab = rem - ph * a.N_pad;
+      double h = 0.0;
+      const uint32_t hp = a.order ? a.order[ph] : (ph < a.Nh ? a.tab.herm[ph] : kPadRow);
+      if (!(hp & kPadRow) && ab < a.N) {
+        const int tq[3] = {(int)(hp & 0xff), (int)((hp >> 8) & 0xff), (int)((hp >> 16) & 0xff)};
+        const int ma = ab / Nbb - la, mb = ab % Nbb - lb;
+        const int s0 = a.tab.solid_start[solid_slot(la, ma)], s1 = a.tab.solid_start[solid_slot(la, ma) + 1];
+        const int r0 = a.tab.solid_start[solid_slot(lb, mb)], r1 = a.tab.solid_start[solid_slot(lb, mb) + 1];
+        for (int s_ = s0; s_ < s1; ++s_) {
+          const uint32_t ca = a.tab.solid_cart[s_];
+          const int av[3] = {(int)(ca & 0xff), (int)((ca >> 8) & 0xff), (int)((ca >> 16) & 0xff)};
+          double inner = 0.0;
+          for (int r = r0; r < r1; ++r) {
+            const uint32_t cb = a.tab.solid_cart[r];
+            const int bv[3] = {(int)(cb & 0xff), (int)((cb >> 8) & 0xff), (int)((cb >> 16) & 0xff)};
+            double f = 1.0;
+            for (int x = 0; x < 3 && f != 0.0; ++x) {
+              const int i = av[x], j = bv[x], t = tq[x];
+              if (x != dir) {
+                f *= t <= i + j ? E[x][i][j][t] : 0.0;
+              } else {
+                double d = 2.0 * za * (t <= i + j + 1 ? E[x][i + 1][j][t] : 0.0);
+                if (i > 0 && t <= i + j - 1) d -= i * E[x][i - 1][j][t];
+                if (t > 0 && t - 1 <= i + j) d -= za_p * E[x][i][j][t - 1];
+                f *= d;
+              }
+            }
+            inner += a.tab.solid_coef[r] * f;
+          }
+          h += a.tab.solid_coef[s_] * inner;
+        }
+        h *= cab;
+        if (a.ket_sign && ((tq[0] + tq[1] + tq[2]) & 1)) h = -h;
+      }
+      Hr[e] = h;
+    }
   }
   if (!a.split) return;
   // Split precision.  Rows are balanced first: row p of H is scaled by
