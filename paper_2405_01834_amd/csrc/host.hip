@@ -1679,11 +1679,36 @@ struct KxClass {
   int LA = 0, NhA = 0, nh_alloc = 0, LmaxA = 0, S1 = 0, S2 = 0;  // A role (LA includes the +1 of gradients)
   std::vector<double> q;
   std::vector<int32_t> sh;
-  size_t o_pp = 0, o_off = 0, o_sh = 0, o_order = 0, o_GA = 0, o_HA = 0, o_GB = 0, o_HB = 0;
+  size_t o_pp = 0, o_off = 0, o_sh = 0, o_order = 0, o_shift = 0, o_GA = 0, o_HA = 0, o_GB = 0, o_HB = 0;
 };
 
+// Largest Y accumulator (doubles) a gradient block keeps in LDS; blocks whose
+// A side needs more take the derivative dot products per quartet.
+constexpr int kYaccMax = 2048;
+
+// For every row of an A-role order: the rows of (t+1,u,v), (t,u+1,v) and
+// (t,u,v+1), 10 bits each (row 0 where the order has no such function).
+std::vector<uint32_t> shift_rows(const std::vector<uint32_t> &order) {
+  std::map<uint32_t, int> at;
+  for (size_t r = 0; r < order.size(); ++r)
+    if (!(order[r] & kPadRow) && !at.count(order[r])) at[order[r]] = (int)r;
+  std::vector<uint32_t> out(order.size(), 0u);
+  for (size_t r = 0; r < order.size(); ++r) {
+    if (order[r] & kPadRow) continue;
+    const int t = order[r] & 0xff, u = (order[r] >> 8) & 0xff, v = (order[r] >> 16) & 0xff;
+    const uint32_t nb[3] = {pack3(t + 1, u, v), pack3(t, u + 1, v), pack3(t, u, v + 1)};
+    uint32_t w = 0;
+    for (int x = 0; x < 3; ++x) {
+      auto it = at.find(nb[x]);
+      w |= (uint32_t)(it == at.end() ? 0 : it->second) << (10 * x);
+    }
+    out[r] = w;
+  }
+  return out;
+}
+
 struct KxPlanBlock {
-  int cA, cB, same, onev, L, npt, nparts, S1, S2;
+  int cA, cB, same, onev, yacc, L, npt, nparts, S1, S2;
   long nq;
   double cost;  // rough cycles of one quartet on one wave
   std::vector<long> pre;
@@ -1739,7 +1764,14 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
         const KxClass &A = C[u], &B = C[v];
         return kx_cost(A.NhA, A.NA, B.NhB_pad, B.NA, A.LA + B.Lc, B.NA_pad / 16);
       };
-      if (unordered && x != y && cost_of(y, x) < cost_of(x, y)) std::swap(cA, cB);
+      if (onev) {
+        // the A side carries the derivative matrices and the Y accumulator:
+        // the lighter pair class takes that role
+        const long wx = (long)C[x].NhA * C[x].NA_pad, wy = (long)C[y].NhA * C[y].NA_pad;
+        if (wy < wx || (wy == wx && cost_of(y, x) < cost_of(x, y))) std::swap(cA, cB);
+      } else if (unordered && x != y && cost_of(y, x) < cost_of(x, y)) {
+        std::swap(cA, cB);
+      }
       KxPlanBlock pb{};
       pb.cA = cA;
       pb.cB = cB;
@@ -1764,7 +1796,8 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       pb.nq = pb.pre[nA];
       if (pb.nq == 0) continue;
       const int ntiles = (A.NhA + 15) / 16;
-      pb.npt = ntiles <= 1 ? 1 : ntiles <= 2 ? 2 : 4;
+      // gradient kernels hold more state per wave: at most two row tiles
+      pb.npt = ntiles <= 1 ? 1 : (ntiles <= 2 || job.grad) ? 2 : 4;
       pb.nparts = (ntiles + pb.npt - 1) / pb.npt;
       pb.cost = kx_cost(A.NhA, A.NA, B.NhB_pad, B.NA, pb.L, B.NA_pad / 16);
       if (pb.L > 18) return fail(MDERI_EUNSUPPORTED, "quartet class of total degree %d is beyond the engine", pb.L);
@@ -1780,10 +1813,22 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
     if (k.asA) choose_cube(k.LmaxA, k.LA, &k.S1, &k.S2);
   for (auto &pb : blocks) choose_cube(pb.L, C[pb.cA].LA, &pb.S1, &pb.S2);
 
-  // launch groups by (row tiles, total degree): the wave's LDS regions are
-  // sized for its group; heaviest quartets first inside a group
-  std::map<std::pair<int, int>, std::vector<int>> groups;
-  for (size_t bi = 0; bi < blocks.size(); ++bi) groups[{blocks[bi].npt, blocks[bi].L}].push_back((int)bi);
+  // launch groups by (row tiles, total degree, size of the gradient's
+  // accumulator and staging): the wave's LDS regions are sized for its
+  // group, so blocks with small regions keep their occupancy; heaviest
+  // quartets first inside a group
+  std::map<std::array<int, 3>, std::vector<int>> groups;
+  for (size_t bi = 0; bi < blocks.size(); ++bi) {
+    const KxPlanBlock &pb = blocks[bi];
+    const KxClass &A = C[pb.cA];
+    int extra = 0;
+    if (job.grad) {
+      const int rows = std::max(A.nh_alloc, round16(A.NhA)), y = A.maxpp * rows * A.NA_pad;
+      extra = (y <= kYaccMax ? y : 0) + (pb.onev ? 17 * rows : 0);
+    }
+    const int bucket = extra <= 1024 ? 0 : extra <= 2048 ? 1 : extra <= 3072 ? 2 : 3;
+    groups[{pb.npt, pb.L, bucket}].push_back((int)bi);
+  }
   for (auto &gr : groups)
     std::stable_sort(gr.second.begin(), gr.second.end(),
                      [&](int x, int y) { return blocks[x].cost > blocks[y].cost; });
@@ -1804,6 +1849,9 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       order.resize(std::max<size_t>(order.size(), (size_t)k.nh_alloc));
       k.nh_alloc = (int)order.size();
       k.o_order = img.add(order.data(), sizeof(uint32_t) * order.size());
+      if (k.nh_alloc > 1024) return fail(MDERI_EUNSUPPORTED, "quartet engine: %d A rows", k.nh_alloc);
+      const std::vector<uint32_t> sh = shift_rows(order);
+      k.o_shift = img.add(sh.data(), sizeof(uint32_t) * sh.size());
     }
   }
   for (auto &pb : blocks) pb.o_pre = img.add(pb.pre.data(), sizeof(long) * pb.pre.size());
@@ -1818,8 +1866,8 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
   std::vector<Group> G;
   for (auto &gr : groups) {
     Group g{};
-    g.npt = gr.first.first;
-    g.lm = gr.first.second;  // total degree L: the producer bucket follows it
+    g.npt = gr.first[0];
+    g.lm = gr.first[1];  // total degree L: the producer bucket follows it
     g.blks.resize(gr.second.size());
     g.o_blocks = img.add(g.blks.data(), sizeof(KxBlock) * g.blks.size());  // filled in below
     G.push_back(std::move(g));
@@ -1853,16 +1901,15 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
   for (auto &gr : groups) {
     Group &g = G[gi++];
     int cube_max = 2, work_max = 2, v_max = 2, d_max = 2, i_max = 2, g_max = 4, uv_max = 1, oq_max = 8, op_max = 16;
+    int y_max = 0, x_max = 0;
     bool single = true;  // every quartet is one primitive quartet: v may share the work area
-    long chunk0 = 0;
+    double work = 0.0;  // estimated cycles of the whole group
     for (size_t j = 0; j < gr.second.size(); ++j) {
       KxPlanBlock &pb = blocks[gr.second[j]];
       const KxClass &A = C[pb.cA], &B = C[pb.cB];
       KxBlock &x = g.blks[j];
       x.nq = pb.nq;
-      x.chunk = (int)std::max(1.0, std::min(4096.0, 600000.0 / pb.cost));
-      x.chunk0 = chunk0;
-      chunk0 += (pb.nq + x.chunk - 1) / x.chunk;
+      work += (double)pb.nq * pb.cost;
       x.pre = (const long *)dev(pb.o_pre);
       x.nA = (int)A.q.size();
       x.L = pb.L;
@@ -1884,6 +1931,8 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       x.nd = nsph(B.lb);
       x.same = pb.same;
       x.onev = pb.onev;
+      x.yacc = job.grad && A.maxpp * A.nh_alloc * A.NA_pad <= kYaccMax ? 1 : 0;
+      x.Ashift = (const uint32_t *)dev(A.o_shift);
       x.A_mats = matsA;
       x.B_mats = matsB(B);
       x.B_pp = (const PrimPair *)dev(B.o_pp);
@@ -1912,10 +1961,11 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       single = single && A.maxpp == 1 && B.maxpp == 1;
       g_max = std::max(g_max, 4 * (A.maxpp + B.maxpp));
       uv_max = std::max(uv_max, (pb.L + 1) * (pb.L + 2) / 2);
+      if (x.yacc) y_max = std::max(y_max, A.maxpp * A.nh_alloc * A.NA_pad);
+      if (x.onev) x_max = std::max(x_max, 17 * A.nh_alloc);
       oq_max = std::max(oq_max, round16(x.NhB_pad));
       op_max = std::max(op_max, x.HA_rows);
     }
-    g.nchunk = chunk0;
     auto even = [](int v) { return (v + 1) & ~1; };
     KxArgs &ar = g.args;
     ar.o_work = even(cube_max);
@@ -1923,10 +1973,13 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
     ar.o_d = single ? ar.o_work + even(std::max(work_max, v_max)) : ar.o_v + even(v_max);
     ar.o_img = ar.o_d + even(d_max);
     ar.o_g = ar.o_img + even(i_max);
-    ar.o_tab = ar.o_g + even(g_max);
+    ar.o_y = ar.o_g + even(g_max);
+    ar.o_x = ar.o_y + even(y_max);
+    ar.o_tab = ar.o_x + even(x_max);
     ar.uv_max = even(uv_max);
     ar.oq_max = even(oq_max);
-    ar.wave_doubles = ar.o_tab + (ar.uv_max + ar.oq_max + op_max + 1) / 2 + 1;
+    ar.op_max = even(op_max);
+    ar.wave_doubles = ar.o_tab + (ar.uv_max + ar.oq_max + 2 * ar.op_max + 1) / 2 + 1;
     ar.wave_doubles = even(ar.wave_doubles);
     const size_t wave_bytes = sizeof(double) * (size_t)ar.wave_doubles;
     g.waves = (int)std::min<size_t>(4, (160 * 1024) / wave_bytes);
@@ -1934,6 +1987,20 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       return fail(MDERI_EUNSUPPORTED, "quartet engine: a wave needs %zu bytes of LDS (over 160 KiB)", wave_bytes);
     g.lds = wave_bytes * g.waves;
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / g.lds));
+    // chunks: at least ~6e5 cycles each (the per-chunk search and table
+    // set-up stay small), and larger where the group's work allows about 16
+    // chunks per resident wave (longer runs of one A pair); blocks run
+    // heaviest first, so the tail is made of the cheapest block's chunks
+    const double per_chunk = std::max(6e5, work / (16.0 * 256.0 * per_cu * g.waves));
+    long chunk0 = 0;
+    for (size_t j = 0; j < gr.second.size(); ++j) {
+      const KxPlanBlock &pb = blocks[gr.second[j]];
+      KxBlock &x = g.blks[j];
+      x.chunk = (int)std::max(1.0, std::min(4096.0, per_chunk / pb.cost));
+      x.chunk0 = chunk0;
+      chunk0 += (pb.nq + x.chunk - 1) / x.chunk;
+    }
+    g.nchunk = chunk0;
     g.grid = (int)std::min<long>(256L * per_cu, std::max<long>(1, (g.nchunk + g.waves - 1) / g.waves));
     ar.blocks = (const KxBlock *)dev(g.o_blocks);
     ar.nblk = (int)g.blks.size();

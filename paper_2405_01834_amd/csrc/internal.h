@@ -163,6 +163,10 @@ struct KxBlock {
   int A_mats, B_mats;     // matrices stored per primitive pair (A: 1, or 7 in gradient mode; B: 1 or 4)
   int onev;               // gradient: one visit per quartet supplies all four centres (single-
                           // primitive pairs; B side through Z = [p+q]^T (H_A S) and dH_B/d(C-D))
+  int yacc;               // gradient: Y = sum_k X S^T of one A pair's run of quartets accumulates in
+                          // LDS and meets the derivative matrices once per run
+  const uint32_t *Ashift; // one-visit: rows of (t+1,u,v), (t,u+1,v), (t,u,v+1) for every A row
+                          // (10 bits each; any valid row where the shifted function is absent)
   const PrimPair *B_pp;   // primitive pairs of B (exponents of the one-visit split)
   float inv_nb, inv_nd, inv_NB, inv_ncd;  // 1/nb, 1/nd, 1/NB, 1/(nc + nd) for index decoding
   const uint32_t *Aorder; // A Hermite row order (HA_rows entries, see PairArgs::order)
@@ -176,7 +180,6 @@ struct KxArgs {
   const KxBlock *blocks;  // device array, sorted by chunk0
   int nblk;
   long nchunk;            // chunks over all blocks
-  int chunk;              // quartets per chunk
   unsigned long long *counter;  // next chunk to take (zero before the launch)
   Tables tab;
   const int *ao_off;      // first AO of every shell
@@ -198,7 +201,8 @@ struct KxArgs {
   const double *exps;     // basis exponents
   // per-wave LDS layout (offsets in doubles from the wave's base)
   int wave_doubles, o_work, o_v, o_d, o_img, o_g, o_tab;
-  int uv_max, oq_max;     // entries of the (u, v) table and of the B offset table
+  int o_y, o_x;           // gradient: Y accumulator, one-visit X staging (rows of 17 doubles)
+  int uv_max, oq_max, op_max;  // entries of the (u, v) table, the B and the A offset tables
 };
 
 // Launchers (defined in the .hip files).

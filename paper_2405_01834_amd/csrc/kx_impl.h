@@ -75,7 +75,7 @@ __device__ __forceinline__ long pre_at(const long *p, int i) { return p[i]; }
 // offsets of the B Hermite rows (zero for padding) and of the A rows (in the
 // class's row order; padding rows name valid [r] entries).
 __device__ __forceinline__ void block_tables(const KxArgs &g, const KxBlock &a, uint32_t *uvsh, int *offq, int *offp,
-                                             int lane) {
+                                             uint32_t *shp, int lane) {
   const int L = a.L;
   for (int e = lane; e < (L + 1) * (L + 2) / 2; e += 64) {
     int s = 0;
@@ -92,6 +92,7 @@ __device__ __forceinline__ void block_tables(const KxArgs &g, const KxBlock &a, 
   for (int r = lane; r < a.HA_rows; r += 64) {
     const uint32_t h = a.Aorder[r];
     offp[r] = (int)(h & 0xff) * a.S1 + (int)((h >> 8) & 0xff) * a.S2 + (int)((h >> 16) & 0xff);
+    if (a.onev) shp[r] = a.Ashift[r];
   }
   lds_wave_sync();
 }
@@ -307,8 +308,8 @@ __device__ __forceinline__ void grad_dots(__amdgpu_buffer_rsrc_t hrs, int vo, in
 // One shell quartet (A pair i, B pair k) by one wave.
 template <int NRT, int LM, int MODE>
 __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i, int k, double *base,
-                                        const uint32_t *uvsh, const int *offq, const int *offp, const YLanes<LM> &yl,
-                                        double (&gpart)[6]) {
+                                        const uint32_t *uvsh, const int *offq, const int *offp, const uint32_t *shp,
+                                        const YLanes<LM> &yl, double (&gpart)[6]) {
   constexpr bool GRAD = MODE == 1;
   const int lane = threadIdx.x & 63, gq = lane >> 4, c = lane & 15;
   double *cube = base, *work = base + g.o_work, *vsh = base + g.o_v, *dsh = base + g.o_d, *img = base + g.o_img;
@@ -335,8 +336,8 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
   const int nks = a.NhB_pad >> 2;
   const int ntiles = (a.NhA + 15) >> 4;
   const int nat = a.NA_pad >> 4;
-  const int NA = a.NA;
   double rq[3] = {0.0, 0.0, 0.0};  // one-visit: derivative along C - D of the B pair
+  double dp[3] = {0.0, 0.0, 0.0};  // one-visit: derivative along P (the A pair moved as a whole)
   // S is the weight of (ab|cd) summed over both assignments of the two
   // pairs; a one-visit quartet whose two pairs are the same pair takes all
   // four centres' derivatives of an integral that appears once, so half
@@ -431,80 +432,144 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
           // the weighted derivative sum_ab,cd S[ab][cd] sum_p H^(m)[p][ab]
           // X[p][cd] is sum_p,ab H^(m)[p][ab] Y[p][ab]: Y^T = S X^T over the
           // tile's 16 columns on the matrix cores, then six dot products
-          // with the derivative matrices ([m][ab][p], p fastest).
+          // with the derivative matrices ([m][ab][p], p fastest).  In
+          // accumulating blocks Y^T adds into the wave's LDS accumulator
+          // instead and the dot products wait for the end of the A pair's run.
           const int mstride = a.HA_rows * a.NA_pad;  // doubles per derivative matrix
-          const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
-              (void *)(a.A_H + (size_t)(ap0 + ia) * a.A_mats * mstride), (short)0, 6 * mstride * 8, kBufferWord3);
-          auto grd = [&](auto ntc) {
-            constexpr int NT = decltype(ntc)::value;
-#pragma unroll 1
-            for (int at = 0; at < nat; ++at) {
-              double w[4];
-#pragma unroll
-              for (int s4 = 0; s4 < 4; ++s4) w[s4] = vsh[(at * 16 + c) * 16 + gq + 4 * s4];
-              // this lane's element of the [m][ab][p] matrices: ab = 16 at + g
-              // (+ 4 r), p = 16 (t0 + pt) + c
-              const int vo = 8 * ((at * 16 + gq) * a.HA_rows + t0 * 16 + c);
-#pragma unroll
-              for (int pt = 0; pt < NT; ++pt) {
-                d4 y = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) y = mfma16x16x4(w[s4], xacc[pt][s4], y);
-                // y[r] = Y^T[ab = 16 at + 4 r + g][p = row c of tile pt]
-                grad_dots(hrs, vo + 8 * 16 * pt, mstride, a.HA_rows, y, gpart);
-              }
-            }
-          };
-          with_tiles<NRT>(ntw, grd);
           if (a.onev) {
-            // B-pair centres (one-visit blocks, single primitives): with
-            // T[p][cd] = sum_ab H_A[p][ab] S[ab][cd] and Z[q][cd] =
-            // sum_p [p+q] T[p][cd], the derivative of sum S (ab|cd) along
-            // the relative coordinate C - D of the B pair is
-            // sum_q,cd dH_B/d(C-D)[q][cd] Z[q][cd]; T stays in the
-            // accumulator layout, which is Z's B operand
-            const double *Ha = a.A_H + (size_t)(ap0 + ia) * a.A_mats * mstride + (size_t)6 * mstride;
-            const int mB = a.NhB_pad * a.NB_pad;
-            const double *Hr = a.B_H + (size_t)bp0 * a.B_mats * mB + mB;  // the three d/d(C-D) matrices
-            auto zb = [&](auto ntc) {
-              constexpr int NT = decltype(ntc)::value;
-              d4 T[NT];
+            // X^T of this part for the one-visit d/dP (row p at p * 17)
+            double *xs = base + g.o_x;
 #pragma unroll
-              for (int pt = 0; pt < NT; ++pt) T[pt] = d4{0.0, 0.0, 0.0, 0.0};
+            for (int pt = 0; pt < NRT; ++pt)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) xs[((t0 + pt) * 16 + c) * 17 + 4 * r + gq] = xacc[pt][r];
+          }
+          if (a.yacc) {
+            // tile (p tile t, ab tile at) of primitive pair ia at
+            // ((ia ntA + t) nat + at) 256, register r of every lane at r 64 + lane
+            double *yb = base + g.o_y + (size_t)ia * (a.HA_rows >> 4) * nat * 256 + lane;
+            auto gry = [&](auto ntc) {
+              constexpr int NT = decltype(ntc)::value;
 #pragma unroll 1
-              for (int ks = 0; ks < (a.NA_pad >> 2); ++ks) {
-                const double sb = vsh[(4 * ks + gq) * 16 + c];  // B[k = ab][j = cd] = S[4 ks + k][16 ct + j]
+              for (int at = 0; at < nat; ++at) {
+                double w[4];
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) w[s4] = vsh[(at * 16 + c) * 16 + gq + 4 * s4];
 #pragma unroll
                 for (int pt = 0; pt < NT; ++pt) {
-                  const double ha = Ha[(size_t)((t0 + pt) * 16 + c) * a.NA_pad + 4 * ks + gq];  // A[i = p][k = ab]
-                  T[pt] = mfma16x16x4(ha, sb, T[pt]);
-                }
-              }
-#pragma unroll 1
-              for (int qt = 0; qt < (a.NhB_pad + 15) >> 4; ++qt) {
-                const int oqr = offq[qt * 16 + c];
-                d4 z = d4{0.0, 0.0, 0.0, 0.0};
+                  double *yt = yb + ((t0 + pt) * nat + at) * 256;
+                  d4 y = d4{yt[0], yt[64], yt[128], yt[192]};
 #pragma unroll
-                for (int pt = 0; pt < NT; ++pt)
+                  for (int s4 = 0; s4 < 4; ++s4) y = mfma16x16x4(w[s4], xacc[pt][s4], y);
 #pragma unroll
-                  for (int r = 0; r < 4; ++r)
-                    z = mfma16x16x4(cube[oqr + offp[(t0 + pt) * 16 + 4 * r + gq]], T[pt][r], z);
-                // z[r] = Z[q = 16 qt + 4 r + g][cd = 16 ct + c]
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                  const int q = qt * 16 + 4 * r + gq;
-                  if (q < a.NhB_pad) {
-                    const size_t o = (size_t)q * a.NB_pad + col;
-                    rq[0] = fma(z[r], Hr[o], rq[0]);
-                    rq[1] = fma(z[r], Hr[mB + o], rq[1]);
-                    rq[2] = fma(z[r], Hr[2 * (size_t)mB + o], rq[2]);
-                  }
+                  for (int r = 0; r < 4; ++r) yt[64 * r] = y[r];
                 }
               }
             };
-            with_tiles<NRT>(ntw, zb);
+            with_tiles<NRT>(ntw, gry);
+          } else {
+            const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(a.A_H + (size_t)(ap0 + ia) * a.A_mats * mstride), (short)0, 6 * mstride * 8, kBufferWord3);
+            auto grd = [&](auto ntc) {
+              constexpr int NT = decltype(ntc)::value;
+#pragma unroll 1
+              for (int at = 0; at < nat; ++at) {
+                double w[4];
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) w[s4] = vsh[(at * 16 + c) * 16 + gq + 4 * s4];
+                // this lane's element of the [m][ab][p] matrices: ab = 16 at + g
+                // (+ 4 r), p = 16 (t0 + pt) + c
+                const int vo = 8 * ((at * 16 + gq) * a.HA_rows + t0 * 16 + c);
+#pragma unroll
+                for (int pt = 0; pt < NT; ++pt) {
+                  d4 y = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                  for (int s4 = 0; s4 < 4; ++s4) y = mfma16x16x4(w[s4], xacc[pt][s4], y);
+                  // y[r] = Y^T[ab = 16 at + 4 r + g][p = row c of tile pt]
+                  grad_dots(hrs, vo + 8 * 16 * pt, mstride, a.HA_rows, y, gpart);
+                }
+              }
+            };
+            with_tiles<NRT>(ntw, grd);
           }
         }
+      }
+    }
+    if (GRAD && a.onev) {
+      // B-pair centres (one-visit blocks, single primitives): with
+      // T[p][cd] = sum_ab H_A[p][ab] S[ab][cd] and Z[q][cd] =
+      // sum_p [p+q] T[p][cd], the derivative of sum S (ab|cd) along the
+      // relative coordinate C - D of the B pair is
+      // sum_q,cd dH_B/d(C-D)[q][cd] Z[q][cd], and along P (the A pair moved
+      // as a whole, d/dP [p+q] = [p+e+q]) it is sum_p,cd T[p][cd] X[p+e][cd];
+      // T stays in the accumulator layout, which is Z's B operand
+      lds_wave_sync();  // X^T of every part staged
+      const int mstride = a.HA_rows * a.NA_pad;
+      const double *Ha = a.A_H + (size_t)ap0 * a.A_mats * mstride + (size_t)6 * mstride;
+      const int mB = a.NhB_pad * a.NB_pad;
+      const double *Hr = a.B_H + (size_t)bp0 * a.B_mats * mB + mB;  // the three d/d(C-D) matrices
+      const double *xs = base + g.o_x;
+      for (int part = 0; part < a.nparts; ++part) {
+        const int t0 = part * NRT;
+        const int ntw = min(NRT, ntiles - t0);
+        auto zb = [&](auto ntc) {
+          constexpr int NT = decltype(ntc)::value;
+          d4 T[NT];
+#pragma unroll
+          for (int pt = 0; pt < NT; ++pt) T[pt] = d4{0.0, 0.0, 0.0, 0.0};
+          // four k-steps per pass: the H_A loads of a pass are issued together
+#pragma unroll 1
+          for (int k4 = 0; k4 < (a.NA_pad >> 2); k4 += 4) {
+            double ha[4][NT], sb[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int ks = k4 + j;  // NA_pad is a multiple of 16: ks < NA_pad / 4
+              sb[j] = vsh[(4 * ks + gq) * 16 + c];  // B[k = ab][j = cd] = S[4 ks + k][16 ct + j]
+#pragma unroll
+              for (int pt = 0; pt < NT; ++pt)
+                ha[j][pt] = Ha[(size_t)((t0 + pt) * 16 + c) * a.NA_pad + 4 * ks + gq];  // A[i = p][k = ab]
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+              for (int pt = 0; pt < NT; ++pt) T[pt] = mfma16x16x4(ha[j][pt], sb[j], T[pt]);
+          }
+          // T[pt][r] = T[p = 16 (t0 + pt) + 4 r + g][cd = 16 ct + c]
+#pragma unroll
+          for (int pt = 0; pt < NT; ++pt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const uint32_t sh = shp[(t0 + pt) * 16 + 4 * r + gq];
+              dp[0] = fma(T[pt][r], xs[(int)(sh & 1023u) * 17 + c], dp[0]);
+              dp[1] = fma(T[pt][r], xs[(int)((sh >> 10) & 1023u) * 17 + c], dp[1]);
+              dp[2] = fma(T[pt][r], xs[(int)((sh >> 20) & 1023u) * 17 + c], dp[2]);
+            }
+#pragma unroll 1
+          for (int qt = 0; qt < (a.NhB_pad + 15) >> 4; ++qt) {
+            // the tile's d/d(C-D) elements are loaded before its products
+            // (rows past NhB_pad read row 0 and are dropped)
+            double hr[4][3];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int q = qt * 16 + 4 * r + gq;
+              const size_t o = (size_t)(q < a.NhB_pad ? q : 0) * a.NB_pad + col;
+#pragma unroll
+              for (int x = 0; x < 3; ++x) hr[r][x] = q < a.NhB_pad ? Hr[x * (size_t)mB + o] : 0.0;
+            }
+            const int oqr = offq[qt * 16 + c];
+            d4 z = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int pt = 0; pt < NT; ++pt)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) z = mfma16x16x4(cube[oqr + offp[(t0 + pt) * 16 + 4 * r + gq]], T[pt][r], z);
+            // z[r] = Z[q = 16 qt + 4 r + g][cd = 16 ct + c]
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+              for (int x = 0; x < 3; ++x) rq[x] = fma(z[r], hr[r][x], rq[x]);
+          }
+        };
+        with_tiles<NRT>(ntw, zb);
       }
     }
     if (!GRAD) {
@@ -515,44 +580,27 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
   }
   if constexpr (!GRAD) digest_flush(g, a, i, k, si, sj, sk, sl, img, lane);
   if (GRAD && a.onev) {
-    // this quartet's four centres: the A pair's from the derivative dots,
-    // the B pair's by translational invariance, d/dC + d/dD = -(d/dA +
-    // d/dB), split as d/dC = (zeta_c/q) d/dQ + d/d(C-D), d/dD =
-    // (zeta_d/q) d/dQ - d/d(C-D) with d/dQ = -(d/dA + d/dB)
-    double v[9];
+    // the B pair's centres of this quartet: d/dQ = -d/dP (R depends on
+    // P - Q only), split as d/dC = (zeta_c/q) d/dQ + d/d(C-D) and d/dD =
+    // (zeta_d/q) d/dQ - d/d(C-D); the A pair's centres come with its run
+    double v[6] = {dp[0], dp[1], dp[2], rq[0], rq[1], rq[2]};
 #pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      v[m] = gpart[m];
-      gpart[m] = 0.0;
-    }
-#pragma unroll
-    for (int x = 0; x < 3; ++x) v[6 + x] = rq[x];
-#pragma unroll
-    for (int m = 0; m < 9; ++m)
+    for (int m = 0; m < 6; ++m)
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) v[m] += __shfl_xor(v[m], off);
-    if (lane < 12) {
+    if (lane < 6) {
       const int x = lane % 3;
-      double dA = v[0], dB = v[3], r = v[6];
+      double P = v[0], r = v[3];
 #pragma unroll
       for (int y = 1; y < 3; ++y)
         if (x == y) {
-          dA = v[y];
-          dB = v[3 + y];
-          r = v[6 + y];
+          P = v[y];
+          r = v[3 + y];
         }
-      double val;
-      int sh;
-      if (lane < 6) {
-        val = lane < 3 ? dA : dB;
-        sh = lane < 3 ? si : sj;
-      } else {
-        const PrimPair pr = a.B_pp[bp0];
-        const double zc = g.exps[pr.pa], zd = g.exps[pr.pb], dq = -(dA + dB);
-        val = lane < 9 ? fma(zc / (zc + zd), dq, r) : fma(zd / (zc + zd), dq, -r);
-        sh = lane < 9 ? sk : sl;
-      }
-      atomicAdd(&g.grad[(size_t)(blockIdx.x % g.gcopies) * g.gstride + 3 * g.atom[sh] + x], val);
+      const PrimPair pr = a.B_pp[bp0];
+      const double zc = g.exps[pr.pa], zd = g.exps[pr.pb], dq = -P;
+      const double val = lane < 3 ? fma(zc / (zc + zd), dq, r) : fma(zd / (zc + zd), dq, -r);
+      atomicAdd(&g.grad[(size_t)(blockIdx.x % g.gcopies) * g.gstride + 3 * g.atom[lane < 3 ? sk : sl] + x], val);
     }
   }
   lds_wave_sync();  // the next quartet may overwrite the wave's LDS
@@ -580,6 +628,35 @@ __device__ __forceinline__ void flush_grad(const KxArgs &g, int si, int sj, doub
   }
 }
 
+// End of an A pair's run of quartets (gradient mode): the accumulated Y
+// (accumulating blocks) meets the six derivative matrices of every
+// primitive pair of A pair i, then the partial derivatives of the pair's two
+// centres go to the gradient copy; the accumulator is left at zero.
+__device__ __forceinline__ void flush_run(const KxArgs &g, const KxBlock &a, int i, double *ybase,
+                                          double (&gpart)[6], int lane) {
+  if (a.yacc) {
+    const int gq = lane >> 4, c = lane & 15;
+    const int ap0 = a.A_off[i], nap = a.A_off[i + 1] - ap0;
+    const int ntiles = (a.NhA + 15) >> 4, nat = a.NA_pad >> 4, ntA = a.HA_rows >> 4;
+    const int mstride = a.HA_rows * a.NA_pad;
+    for (int ia = 0; ia < nap; ++ia) {
+      const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(a.A_H + (size_t)(ap0 + ia) * a.A_mats * mstride), (short)0, 6 * mstride * 8, kBufferWord3);
+#pragma unroll 1
+      for (int t = 0; t < ntiles; ++t)
+#pragma unroll 1
+        for (int at = 0; at < nat; ++at) {
+          double *yt = ybase + ((ia * ntA + t) * nat + at) * 256 + lane;
+          const d4 y = d4{yt[0], yt[64], yt[128], yt[192]};
+#pragma unroll
+          for (int r = 0; r < 4; ++r) yt[64 * r] = 0.0;
+          grad_dots(hrs, 8 * ((at * 16 + gq) * a.HA_rows + t * 16 + c), mstride, a.HA_rows, y, gpart);
+        }
+    }
+  }
+  flush_grad(g, a.A_sh[2 * i], a.A_sh[2 * i + 1], gpart, lane);
+}
+
 template <int NRT, int LM, int MODE>
 __global__ void __launch_bounds__(64 * kWavesMax, 2) kx_kernel(KxArgs g) {
   constexpr bool GRAD = MODE == 1;
@@ -589,11 +666,16 @@ __global__ void __launch_bounds__(64 * kWavesMax, 2) kx_kernel(KxArgs g) {
   uint32_t *uvsh = (uint32_t *)(base + g.o_tab);
   int *offq = (int *)(uvsh + g.uv_max);
   int *offp = offq + g.oq_max;
+  uint32_t *shp = (uint32_t *)(offp + g.op_max);
+  double *ybase = base + g.o_y;
   int cur = -1;
   KxBlock a{};
   YLanes<LM> yl;
   double gpart[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int gsi = -1, gsj = -1;  // shells whose derivatives gpart holds
+  int yi = -1;  // A pair (of block cur) whose run the wave's Y and gpart hold
+  if (GRAD) {
+    for (int e = lane; e < g.o_x - g.o_y; e += 64) ybase[e] = 0.0;
+  }
   for (;;) {
     unsigned long long ch = 0;
     if (lane == 0) ch = atomicAdd(g.counter, 1ull);
@@ -608,9 +690,13 @@ __global__ void __launch_bounds__(64 * kWavesMax, 2) kx_kernel(KxArgs g) {
       else hi = mid - 1;
     }
     if (lo != cur) {
+      if (GRAD && yi >= 0) {
+        flush_run(g, a, yi, ybase, gpart, lane);
+        yi = -1;
+      }
       a = block_at(g.blocks, lo);
       cur = lo;
-      block_tables(g, a, uvsh, offq, offp, lane);
+      block_tables(g, a, uvsh, offq, offp, shp, lane);
       if constexpr (LM <= 18) ylanes_init<LM>(a.L, lane, yl);
     }
     long q = (chunk - a.chunk0) * (long)a.chunk;
@@ -625,15 +711,11 @@ __global__ void __launch_bounds__(64 * kWavesMax, 2) kx_kernel(KxArgs g) {
     long pend = pre_at(a.pre, i + 1);
     int k = (int)(q - pre_at(a.pre, i));
     for (; q < qend; ++q) {
-      if (GRAD) {
-        const int si = a.A_sh[2 * i], sj = a.A_sh[2 * i + 1];
-        if (si != gsi || sj != gsj) {
-          if (gsi >= 0) flush_grad(g, gsi, gsj, gpart, lane);
-          gsi = si;
-          gsj = sj;
-        }
+      if (GRAD && i != yi) {
+        if (yi >= 0) flush_run(g, a, yi, ybase, gpart, lane);
+        yi = i;
       }
-      quartet<NRT, LM, MODE>(g, a, i, k, base, uvsh, offq, offp, yl, gpart);
+      quartet<NRT, LM, MODE>(g, a, i, k, base, uvsh, offq, offp, shp, yl, gpart);
       ++k;
       if (q + 1 == pend && q + 1 < qend) {  // next A pair that has quartets
         do {
@@ -644,7 +726,7 @@ __global__ void __launch_bounds__(64 * kWavesMax, 2) kx_kernel(KxArgs g) {
       }
     }
   }
-  if (GRAD && gsi >= 0) flush_grad(g, gsi, gsj, gpart, lane);
+  if (GRAD && yi >= 0) flush_run(g, a, yi, ybase, gpart, lane);
 }
 
 template <int NRT, int LM, int MODE>
@@ -665,10 +747,13 @@ hipError_t launch_mode(const KxArgs &a, int npt, int Lmax, int waves, size_t lds
   const int lm = rr_lm_bucket(Lmax);
 #define KX_CASE(NRT, LM) \
   if (npt == NRT && lm == LM) return launch_t<NRT, LM, MODE>(a, waves, lds, grid, s);
-  KX_CASE(1, 8) KX_CASE(2, 8) KX_CASE(4, 8)
-  KX_CASE(1, 10) KX_CASE(2, 10) KX_CASE(4, 10)
-  KX_CASE(1, 16) KX_CASE(2, 16) KX_CASE(4, 16)
-  KX_CASE(1, 18) KX_CASE(2, 18) KX_CASE(4, 18)
+  KX_CASE(1, 8) KX_CASE(2, 8)
+  KX_CASE(1, 10) KX_CASE(2, 10)
+  KX_CASE(1, 16) KX_CASE(2, 16)
+  KX_CASE(1, 18) KX_CASE(2, 18)
+  if constexpr (MODE == 0) {  // the gradient plans at most two row tiles per part
+    KX_CASE(4, 8) KX_CASE(4, 10) KX_CASE(4, 16) KX_CASE(4, 18)
+  }
 #undef KX_CASE
   return hipErrorInvalidValue;
 }
