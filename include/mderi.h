@@ -264,6 +264,16 @@ mderi_status mderi_basis_set_centers(mderi_basis_t basis, const double *centers_
 mderi_status mderi_kernel_timing(mderi_ctx_t ctx, int enable);
 mderi_status mderi_kernel_times(mderi_ctx_t ctx, double *ms_host, int cap, int *count);
 
+/*
+ * Progress report (measurement support, not part of the method).  While
+ * enabled, the J/K builds and the gradient enqueue a host function after each
+ * launch group of the screened quartet engine; it prints one line to stderr
+ * when the group's kernel has finished (group index, total degree, quartets,
+ * seconds since the call).  Meant for long calls on large systems.  EINVAL
+ * for a NULL context.
+ */
+mderi_status mderi_progress(mderi_ctx_t ctx, int enable);
+
 /* Weight patterns of mderi_kbuild_grad. */
 #define MDERI_EXCHANGE 0 /* W_abcd = Wl_ac Wr_bd: E = tr(Wl^T K[Wr]) */
 #define MDERI_COULOMB 1  /* W_abcd = Wl_ab Wr_cd: E = tr(Wl^T J[Wr]) */

@@ -2,6 +2,7 @@
 // class-batch planning and kernel dispatch.  Constant tables (Boys grid,
 // Hermite order, Cartesian->solid coefficients) are generated here on the
 // host from their mathematical definitions and uploaded once per context.
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -218,6 +219,7 @@ struct mderi_ctx {
   // of events on its stream (pairs are recycled after they are read)
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+  bool progress = false;  // report finished launch groups of the quartet engine
   // task-list plans of mderi_eri3_batch, most recent last, and the tile
   // choices of the autotuner per class signature
   std::vector<TaskPlan *> plans;
@@ -375,6 +377,12 @@ extern "C" void mderi_destroy(mderi_ctx_t c) {
 extern "C" mderi_status mderi_kernel_timing(mderi_ctx_t c, int enable) {
   if (!c) return fail(MDERI_EINVAL, "mderi_kernel_timing: NULL context");
   c->timing = enable != 0;
+  return MDERI_OK;
+}
+
+extern "C" mderi_status mderi_progress(mderi_ctx_t c, int enable) {
+  if (!c) return fail(MDERI_EINVAL, "mderi_progress: NULL context");
+  c->progress = enable != 0;
   return MDERI_OK;
 }
 
@@ -1656,6 +1664,23 @@ extern "C" mderi_status mderi_eri3_batch(mderi_ctx_t c, mderi_basis_t b, mderi_b
 // ---------------------------------------------------------------------------
 namespace {
 
+// One finished launch group of the quartet engine (printed from the stream's
+// host-function thread once the group's kernel is done).
+struct ProgressMsg {
+  int group, ngroup, L, grad;
+  long nq;
+  std::chrono::steady_clock::time_point t0;
+};
+
+void progress_line(void *p) {
+  const ProgressMsg *m = (const ProgressMsg *)p;
+  const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - m->t0).count();
+  fprintf(stderr, "mderi: %s group %d/%d done (total degree %d, %ld quartets) at %.1f s\n",
+          m->grad ? "gradient" : "J/K build", m->group + 1, m->ngroup, m->L, m->nq, s);
+  fflush(stderr);
+  delete m;
+}
+
 // What one engine call computes.
 struct KxJob {
   bool grad = false;
@@ -1676,6 +1701,7 @@ struct KxJob {
 struct KxClass {
   int la = 0, lb = 0, Lc = 0, NA = 0, NA_pad = 0, NhB = 0, NhB_pad = 0, maxpp = 0;
   bool asA = false, asB = false;
+  bool a6 = false, arel = false;  // gradient A role: in two-visit / one-visit blocks
   int LA = 0, NhA = 0, nh_alloc = 0, LmaxA = 0, S1 = 0, S2 = 0;  // A role (LA includes the +1 of gradients)
   std::vector<double> q;
   std::vector<int32_t> sh;
@@ -1684,7 +1710,7 @@ struct KxClass {
 
 // Largest Y accumulator (doubles) a gradient block keeps in LDS; blocks whose
 // A side needs more take the derivative dot products per quartet.
-constexpr int kYaccMax = 2048;
+constexpr int kYaccMax = 4608;
 
 // For every row of an A-role order: the rows of (t+1,u,v), (t,u+1,v) and
 // (t,u,v+1), 10 bits each (row 0 where the order has no such function).
@@ -1803,6 +1829,7 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       if (pb.L > 18) return fail(MDERI_EUNSUPPORTED, "quartet class of total degree %d is beyond the engine", pb.L);
       blocks.push_back(std::move(pb));
       C[cA].asA = true;
+      if (job.grad) (onev ? C[cA].arel : C[cA].a6) = true;
       C[cB].asB = true;
       C[cA].nh_alloc = std::max(C[cA].nh_alloc, blocks.back().nparts * blocks.back().npt * 16);
       C[cA].LmaxA = std::max(C[cA].LmaxA, blocks.back().L);
@@ -1876,13 +1903,15 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
   // matrices per primitive pair: A role 7 in gradient mode (six derivative
   // matrices and the plain one), B role 4 for single-primitive classes in
   // gradient mode (plain and three relative-coordinate derivatives)
-  const int matsA = job.grad ? 7 : 1;
+  // A role in gradient mode: six derivative matrices (two-visit blocks), the
+  // plain matrix, three d/d(A-B) matrices (one-visit blocks)
+  auto matsA = [&](const KxClass &k) { return (k.a6 ? 6 : 0) + 1 + (k.arel ? 3 : 0); };
   auto matsB = [&](const KxClass &k) { return (job.grad && k.maxpp == 1) ? 4 : 1; };
   for (auto &k : C) {
     const int npp = (int)ps.sides[&k - &C[0]].pp.size();
     if (k.asA) {
       k.o_GA = img.add(nullptr, sizeof(double) * 4 * npp);
-      k.o_HA = img.add(nullptr, sizeof(double) * matsA * (size_t)k.nh_alloc * k.NA_pad * npp);
+      k.o_HA = img.add(nullptr, sizeof(double) * matsA(k) * (size_t)k.nh_alloc * k.NA_pad * npp);
     }
     if (k.asB) {
       k.o_GB = img.add(nullptr, sizeof(double) * 4 * npp);
@@ -1933,7 +1962,10 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       x.onev = pb.onev;
       x.yacc = job.grad && A.maxpp * A.nh_alloc * A.NA_pad <= kYaccMax ? 1 : 0;
       x.Ashift = (const uint32_t *)dev(A.o_shift);
-      x.A_mats = matsA;
+      x.A_mats = matsA(A);
+      x.A_plain = A.a6 ? 6 : 0;
+      x.A_rel = x.A_plain + 1;
+      x.A_pp = (const PrimPair *)dev(A.o_pp);
       x.B_mats = matsB(B);
       x.B_pp = (const PrimPair *)dev(B.o_pp);
       x.inv_nb = 1.0f / (float)x.nb;
@@ -2046,7 +2078,9 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
     if (k.asA) {
       pa.Nh = k.NhA;
       pa.Nh_pad = k.nh_alloc;
-      pa.deriv = job.grad ? 1 : 0;
+      pa.deriv = k.a6 ? 1 : 0;
+      pa.rderiv = k.arel ? 1 : 0;
+      pa.rtrans = 1;
       pa.order = (const uint32_t *)dev(k.o_order);
       pa.ket_sign = 0;
       pa.G = (double *)dev(k.o_GA);
@@ -2058,6 +2092,7 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       pa.Nh_pad = k.NhB_pad;
       pa.deriv = 0;
       pa.rderiv = matsB(k) == 4 ? 1 : 0;
+      pa.rtrans = 0;
       pa.order = nullptr;
       pa.ket_sign = 1;
       pa.G = (double *)dev(k.o_GB);
@@ -2065,6 +2100,7 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       HIP_TRY(launch_pairs(pa, s));
     }
   }
+  const auto t_start = std::chrono::steady_clock::now();
   for (auto &g : G) {
     HIP_TRY(launch_zero(1, (double *)dev(g.o_counter), s));  // chunk counter (zero bits)
     if (c->timing) {
@@ -2082,6 +2118,16 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
       HIP_TRY(hipEventRecord(e.second, s));
     } else {
       HIP_TRY(launch_kx(g.args, g.npt, g.lm, job.grad, g.waves, g.lds, g.grid, s));
+    }
+    if (c->progress) {
+      long nq = 0;
+      for (const KxBlock &x : g.blks) nq += x.nq;
+      ProgressMsg *m = new ProgressMsg{(int)(&g - &G[0]), (int)G.size(), g.lm, job.grad ? 1 : 0, nq, t_start};
+      const hipError_t e = hipLaunchHostFunc(s, progress_line, m);
+      if (e != hipSuccess) {
+        delete m;
+        HIP_TRY(e);
+      }
     }
   }
   return MDERI_OK;

@@ -83,10 +83,12 @@ struct PairArgs {
   int ket_sign;  // fold (-1)^{|q|} of Eq. (pq) into a ket transform matrix
   int one_centre;  // single shells (lb ignored): Eqs. (E1rr)-(E1-aa), zeta_p = zeta_a, P = A
   int deriv;       // write the six centre-derivative matrices d/dA_x, d/dB_x (see pairs.hip)
-                   // transposed, H[6][N_pad][Nh_pad] (rows then span |p| <= la+lb+1), then the
-                   // plain matrix [Nh_pad][N_pad]: 7 matrices per primitive pair
-  int rderiv;      // write the plain matrix, then the three derivatives with respect to the
-                   // relative coordinate A - B at fixed P, each [Nh_pad][N_pad]: 4 matrices
+                   // transposed, H[6][N_pad][Nh_pad] (rows then span |p| <= la+lb+1), before
+                   // the plain matrix [Nh_pad][N_pad]
+  int rderiv;      // after the plain matrix, the three derivatives with respect to the
+                   // relative coordinate A - B at fixed P, each [Nh_pad][N_pad] ([N_pad][Nh_pad]
+                   // with rtrans); per primitive pair 6 deriv + 1 + 3 rderiv matrices
+  int rtrans;
   // split precision: also write the matrix as `split` BF16 slices of
   // 7-bit integers relative to a power-of-two exponent per column ab (see
   // pairs.hip), rows in the k order of the BF16 matrix-core operand
@@ -167,7 +169,8 @@ struct KxBlock {
                           // LDS and meets the derivative matrices once per run
   const uint32_t *Ashift; // one-visit: rows of (t+1,u,v), (t,u+1,v), (t,u,v+1) for every A row
                           // (10 bits each; any valid row where the shifted function is absent)
-  const PrimPair *B_pp;   // primitive pairs of B (exponents of the one-visit split)
+  const PrimPair *A_pp, *B_pp;  // primitive pairs (exponents of the one-visit splits)
+  int A_plain, A_rel;     // A role: index of the plain matrix and of the first d/d(A-B) matrix
   float inv_nb, inv_nd, inv_NB, inv_ncd;  // 1/nb, 1/nd, 1/NB, 1/(nc + nd) for index decoding
   const uint32_t *Aorder; // A Hermite row order (HA_rows entries, see PairArgs::order)
   const int *A_off, *B_off;            // primitive-pair offsets per pair [n + 1]

@@ -288,18 +288,20 @@ __device__ __forceinline__ void digest_flush(const KxArgs &g, const KxBlock &a, 
 
 constexpr int kBufferWord3 = 0x00020000;  // buffer resource word 3 for gfx9-family raw loads
 
-// Derivative contraction of the gradient: gpart[m] += sum_p,ab H^(m)[p][ab]
-// Y[p][ab] over one 16 x 16 tile of Y^T (register r of lane c + 16 g holds
-// Y^T[ab = 16 at + 4 r + g][p = row c of the tile]).  The matrices are read
-// by buffer loads: the lane's part of the offset (vo, bytes) in a VGPR, the
-// (matrix, row) part in an SGPR, so no per-element addresses stay live.
-__device__ __forceinline__ void grad_dots(__amdgpu_buffer_rsrc_t hrs, int vo, int mstride, int HA_rows, const d4 &y,
-                                          double (&gpart)[6]) {
+// Derivative contraction of the gradient: gpart[m] += sum_p,ab H^(m0+m)[p][ab]
+// Y[p][ab], m < NM, over one 16 x 16 tile of Y^T (register r of lane c + 16 g
+// holds Y^T[ab = 16 at + 4 r + g][p = row c of the tile]); the matrices are
+// stored transposed, [ab][p].  They are read by buffer loads: the lane's
+// part of the offset (vo, bytes) in a VGPR, the (matrix, row) part in an
+// SGPR, so no per-element addresses stay live.
+template <int NM>
+__device__ __forceinline__ void grad_dots(__amdgpu_buffer_rsrc_t hrs, int vo, int mstride, int HA_rows, int m0,
+                                          const d4 &y, double (&gpart)[6]) {
 #pragma unroll
-  for (int m = 0; m < 6; ++m)
+  for (int m = 0; m < NM; ++m)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int so = 8 * (m * mstride + 4 * r * HA_rows);
+      const int so = 8 * ((m0 + m) * mstride + 4 * r * HA_rows);
       const double h = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(hrs, vo, so, 0));
       gpart[m] = fma(y[r], h, gpart[m]);
     }
@@ -309,7 +311,7 @@ __device__ __forceinline__ void grad_dots(__amdgpu_buffer_rsrc_t hrs, int vo, in
 template <int NRT, int LM, int MODE>
 __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i, int k, double *base,
                                         const uint32_t *uvsh, const int *offq, const int *offp, const uint32_t *shp,
-                                        const YLanes<LM> &yl, double (&gpart)[6]) {
+                                        const YLanes<LM> &yl, double (&gpart)[6], double (&dpa)[3]) {
   constexpr bool GRAD = MODE == 1;
   const int lane = threadIdx.x & 63, gq = lane >> 4, c = lane & 15;
   double *cube = base, *work = base + g.o_work, *vsh = base + g.o_v, *dsh = base + g.o_d, *img = base + g.o_img;
@@ -469,7 +471,8 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
             with_tiles<NRT>(ntw, gry);
           } else {
             const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
-                (void *)(a.A_H + (size_t)(ap0 + ia) * a.A_mats * mstride), (short)0, 6 * mstride * 8, kBufferWord3);
+                (void *)(a.A_H + (size_t)(ap0 + ia) * a.A_mats * mstride), (short)0, a.A_mats * mstride * 8,
+                kBufferWord3);
             auto grd = [&](auto ntc) {
               constexpr int NT = decltype(ntc)::value;
 #pragma unroll 1
@@ -485,8 +488,10 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
                   d4 y = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                   for (int s4 = 0; s4 < 4; ++s4) y = mfma16x16x4(w[s4], xacc[pt][s4], y);
-                  // y[r] = Y^T[ab = 16 at + 4 r + g][p = row c of tile pt]
-                  grad_dots(hrs, vo + 8 * 16 * pt, mstride, a.HA_rows, y, gpart);
+                  // y[r] = Y^T[ab = 16 at + 4 r + g][p = row c of tile pt]; one-visit
+                  // blocks take the relative coordinate A - B (d/dP comes with d/dQ)
+                  if (a.onev) grad_dots<3>(hrs, vo + 8 * 16 * pt, mstride, a.HA_rows, a.A_rel, y, gpart);
+                  else grad_dots<6>(hrs, vo + 8 * 16 * pt, mstride, a.HA_rows, 0, y, gpart);
                 }
               }
             };
@@ -505,7 +510,7 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
       // T stays in the accumulator layout, which is Z's B operand
       lds_wave_sync();  // X^T of every part staged
       const int mstride = a.HA_rows * a.NA_pad;
-      const double *Ha = a.A_H + (size_t)ap0 * a.A_mats * mstride + (size_t)6 * mstride;
+      const double *Ha = a.A_H + ((size_t)ap0 * a.A_mats + a.A_plain) * mstride;
       const int mB = a.NhB_pad * a.NB_pad;
       const double *Hr = a.B_H + (size_t)bp0 * a.B_mats * mB + mB;  // the three d/d(C-D) matrices
       const double *xs = base + g.o_x;
@@ -582,12 +587,15 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
   if (GRAD && a.onev) {
     // the B pair's centres of this quartet: d/dQ = -d/dP (R depends on
     // P - Q only), split as d/dC = (zeta_c/q) d/dQ + d/d(C-D) and d/dD =
-    // (zeta_d/q) d/dQ - d/d(C-D); the A pair's centres come with its run
+    // (zeta_d/q) d/dQ - d/d(C-D); d/dP adds to the A pair's run (its split
+    // needs only the A pair's exponents)
     double v[6] = {dp[0], dp[1], dp[2], rq[0], rq[1], rq[2]};
 #pragma unroll
     for (int m = 0; m < 6; ++m)
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) v[m] += __shfl_xor(v[m], off);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) dpa[x] += v[x];
     if (lane < 6) {
       const int x = lane % 3;
       double P = v[0], r = v[3];
@@ -629,11 +637,12 @@ __device__ __forceinline__ void flush_grad(const KxArgs &g, int si, int sj, doub
 }
 
 // End of an A pair's run of quartets (gradient mode): the accumulated Y
-// (accumulating blocks) meets the six derivative matrices of every
-// primitive pair of A pair i, then the partial derivatives of the pair's two
-// centres go to the gradient copy; the accumulator is left at zero.
+// (accumulating blocks) meets the derivative matrices of every primitive
+// pair of A pair i (the six centre derivatives, or the three along A - B in
+// one-visit blocks), then the derivatives of the pair's two centres go to
+// the gradient copy; the accumulators are left at zero.
 __device__ __forceinline__ void flush_run(const KxArgs &g, const KxBlock &a, int i, double *ybase,
-                                          double (&gpart)[6], int lane) {
+                                          double (&gpart)[6], double (&dpa)[3], int lane) {
   if (a.yacc) {
     const int gq = lane >> 4, c = lane & 15;
     const int ap0 = a.A_off[i], nap = a.A_off[i + 1] - ap0;
@@ -641,7 +650,7 @@ __device__ __forceinline__ void flush_run(const KxArgs &g, const KxBlock &a, int
     const int mstride = a.HA_rows * a.NA_pad;
     for (int ia = 0; ia < nap; ++ia) {
       const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
-          (void *)(a.A_H + (size_t)(ap0 + ia) * a.A_mats * mstride), (short)0, 6 * mstride * 8, kBufferWord3);
+          (void *)(a.A_H + (size_t)(ap0 + ia) * a.A_mats * mstride), (short)0, a.A_mats * mstride * 8, kBufferWord3);
 #pragma unroll 1
       for (int t = 0; t < ntiles; ++t)
 #pragma unroll 1
@@ -650,11 +659,46 @@ __device__ __forceinline__ void flush_run(const KxArgs &g, const KxBlock &a, int
           const d4 y = d4{yt[0], yt[64], yt[128], yt[192]};
 #pragma unroll
           for (int r = 0; r < 4; ++r) yt[64 * r] = 0.0;
-          grad_dots(hrs, 8 * ((at * 16 + gq) * a.HA_rows + t * 16 + c), mstride, a.HA_rows, y, gpart);
+          const int vo = 8 * ((at * 16 + gq) * a.HA_rows + t * 16 + c);
+          if (a.onev) grad_dots<3>(hrs, vo, mstride, a.HA_rows, a.A_rel, y, gpart);
+          else grad_dots<6>(hrs, vo, mstride, a.HA_rows, 0, y, gpart);
         }
     }
   }
-  flush_grad(g, a.A_sh[2 * i], a.A_sh[2 * i + 1], gpart, lane);
+  const int si = a.A_sh[2 * i], sj = a.A_sh[2 * i + 1];
+  if (!a.onev) {
+    flush_grad(g, si, sj, gpart, lane);
+    return;
+  }
+  // one-visit (single primitive pair): d/dA = (zeta_a/p) d/dP + d/d(A-B),
+  // d/dB = (zeta_b/p) d/dP - d/d(A-B); dpa holds the run's d/dP (the same in
+  // every lane), gpart[0..2] the lanes' parts of d/d(A-B)
+  double r3[3];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    double v = gpart[x];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    r3[x] = v;
+  }
+  if (lane < 6) {
+    const int x = lane % 3;
+    double P = dpa[0], r = r3[0];
+#pragma unroll
+    for (int y = 1; y < 3; ++y)
+      if (x == y) {
+        P = dpa[y];
+        r = r3[y];
+      }
+    const PrimPair pr = a.A_pp[a.A_off[i]];
+    const double za = g.exps[pr.pa], zb = g.exps[pr.pb];
+    const double val = lane < 3 ? fma(za / (za + zb), P, r) : fma(zb / (za + zb), P, -r);
+    atomicAdd(&g.grad[(size_t)(blockIdx.x % g.gcopies) * g.gstride + 3 * g.atom[lane < 3 ? si : sj] + x], val);
+  }
+#pragma unroll
+  for (int m = 0; m < 6; ++m) gpart[m] = 0.0;
+#pragma unroll
+  for (int x = 0; x < 3; ++x) dpa[x] = 0.0;
 }
 
 template <int NRT, int LM, int MODE>
@@ -672,6 +716,7 @@ __global__ void __launch_bounds__(64 * kWavesMax, 2) kx_kernel(KxArgs g) {
   KxBlock a{};
   YLanes<LM> yl;
   double gpart[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double dpa[3] = {0.0, 0.0, 0.0};
   int yi = -1;  // A pair (of block cur) whose run the wave's Y and gpart hold
   if (GRAD) {
     for (int e = lane; e < g.o_x - g.o_y; e += 64) ybase[e] = 0.0;
@@ -691,7 +736,7 @@ __global__ void __launch_bounds__(64 * kWavesMax, 2) kx_kernel(KxArgs g) {
     }
     if (lo != cur) {
       if (GRAD && yi >= 0) {
-        flush_run(g, a, yi, ybase, gpart, lane);
+        flush_run(g, a, yi, ybase, gpart, dpa, lane);
         yi = -1;
       }
       a = block_at(g.blocks, lo);
@@ -712,10 +757,10 @@ __global__ void __launch_bounds__(64 * kWavesMax, 2) kx_kernel(KxArgs g) {
     int k = (int)(q - pre_at(a.pre, i));
     for (; q < qend; ++q) {
       if (GRAD && i != yi) {
-        if (yi >= 0) flush_run(g, a, yi, ybase, gpart, lane);
+        if (yi >= 0) flush_run(g, a, yi, ybase, gpart, dpa, lane);
         yi = i;
       }
-      quartet<NRT, LM, MODE>(g, a, i, k, base, uvsh, offq, offp, shp, yl, gpart);
+      quartet<NRT, LM, MODE>(g, a, i, k, base, uvsh, offq, offp, shp, yl, gpart, dpa);
       ++k;
       if (q + 1 == pend && q + 1 < qend) {  // next A pair that has quartets
         do {
@@ -726,7 +771,7 @@ __global__ void __launch_bounds__(64 * kWavesMax, 2) kx_kernel(KxArgs g) {
       }
     }
   }
-  if (GRAD && yi >= 0) flush_run(g, a, yi, ybase, gpart, lane);
+  if (GRAD && yi >= 0) flush_run(g, a, yi, ybase, gpart, dpa, lane);
 }
 
 template <int NRT, int LM, int MODE>

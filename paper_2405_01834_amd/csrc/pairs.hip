@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
     // the same for B: H^(X,x)[p][ab] = c_a c_b sum C C [2 z E^{(a+1x) b}_p - a_x E^{(a-1x) b}_p]
     // stored transposed, [mat][ab][p] with p fastest (the gradient stage of
     // the quartet engine reads 16 consecutive p per lane group)
-    double *H = a.H + (size_t)pp * 7 * a.Nh_pad * a.N_pad;
+    double *H = a.H + (size_t)pp * (7 + (a.rderiv ? 3 : 0)) * a.Nh_pad * a.N_pad;
     const int total = 6 * a.Nh_pad * a.N_pad;
     for (int e = tid; e < total; e += kPairThreads) {
       const int mat = e / (a.Nh_pad * a.N_pad);
@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
     }
     // the plain matrix follows the six derivative matrices ([p][ab], no sign)
   }
-  const size_t mats = a.deriv ? 7 : a.rderiv ? 4 : 1;
+  const size_t mats = (a.deriv ? 6 : 0) + 1 + (a.rderiv ? 3 : 0);
   double *H = a.H + (size_t)pp * mats * a.Nh_pad * a.N_pad + (a.deriv ? 6 * (size_t)a.Nh_pad * a.N_pad : 0);
   const int total = a.Nh_pad * a.N_pad;
   for (int e = tid; e < total; e += kPairThreads) {
@@ -154,7 +154,8 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
     // Lambda_{t+1}) and d/dA x_A^i = 2 za x_A^{i+1} - i x_A^{i-1}, the
     // coefficient of Lambda_t in d/dR_x of x_A^i x_B^j e^{..} is
     //   2 za E^{i+1,j}_t - i E^{i-1,j}_t - (za / p) E^{ij}_{t-1};
-    // matrices 1..3 after the plain one, [x][p][ab], ket sign included
+    // matrices 1..3 after the plain one, [x][p][ab] ([x][ab][p] with
+    // rtrans), ket sign included
     const double za_p = za / p;
     double *Hr = H + (size_t)a.Nh_pad * a.N_pad;
     for (int e = tid; e < 3 * total; e += kPairThreads) {
@@ -193,7 +194,7 @@ __global__ void __launch_bounds__(kPairThreads) pair_kernel(PairArgs a) {
         h *= cab;
         if (a.ket_sign && ((tq[0] + tq[1] + tq[2]) & 1)) h = -h;
       }
-      Hr[e] = h;
+      Hr[a.rtrans ? (size_t)dir * total + (size_t)ab * a.Nh_pad + ph : (size_t)e] = h;
     }
   }
   if (!a.split) return;

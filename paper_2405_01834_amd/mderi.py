@@ -84,6 +84,8 @@ def load_library():
     L.mderi_eri3_batch.restype = ctypes.c_int
     L.mderi_kernel_timing.argtypes = [_vp, ctypes.c_int]
     L.mderi_kernel_timing.restype = ctypes.c_int
+    L.mderi_progress.argtypes = [_vp, ctypes.c_int]
+    L.mderi_progress.restype = ctypes.c_int
     L.mderi_kernel_times.argtypes = [_vp, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     L.mderi_kernel_times.restype = ctypes.c_int
     L.mderi_jkbuild.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(Opts), _vp]
@@ -267,6 +269,10 @@ class Context:
     def kernel_timing(self, enable: bool):
         """Brackets every fused-kernel launch with HIP events on its stream."""
         _check(load_library().mderi_kernel_timing(self._h, int(bool(enable))))
+
+    def progress(self, enable: bool):
+        """Prints a line to stderr as each launch group of the J/K builds and the gradient finishes."""
+        _check(load_library().mderi_progress(self._h, int(bool(enable))))
 
     def kernel_times(self):
         """Durations (ms) of the fused-kernel launches recorded since the last read."""
