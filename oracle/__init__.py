@@ -69,6 +69,7 @@ def _setup(L):
     L.oracle_eri3.argtypes = [ctypes.c_int, _ip, _ip, _dp, _dp, _dp, ctypes.c_int, _ip, _ip, _dp, _dp, _dp,
                               ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int, _ip, _dp, ctypes.c_int]
     L.oracle_schwarz.argtypes = basis + [ctypes.c_int, _ip, _dp, ctypes.c_int]
+    L.oracle_eri2.argtypes = basis + [ctypes.c_int, _ip, ctypes.c_int, _ip, _dp, ctypes.c_int]
     L.oracle_kbuild.argtypes = basis + [_dp, ctypes.c_double, _dp, ctypes.c_int]
     L.oracle_exchange_grad.argtypes = basis + [_ip, ctypes.c_int, _dp, ctypes.c_double, _dp, ctypes.c_int]
     L.oracle_jbuild.argtypes = basis + [_dp, ctypes.c_double, _dp, ctypes.c_int]
@@ -76,7 +77,7 @@ def _setup(L):
                                              ctypes.c_int]
     L.oracle_grad_pattern.argtypes = basis + [_ip, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_double, _dp,
                                               ctypes.c_int]
-    for name in ("oracle_jbuild", "oracle_fock_blocks", "oracle_grad_pattern"):
+    for name in ("oracle_jbuild", "oracle_fock_blocks", "oracle_grad_pattern", "oracle_eri2"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("oracle_eri4_cart", "oracle_eri4_deriv", "oracle_eri4", "oracle_eri3", "oracle_schwarz",
                  "oracle_kbuild", "oracle_exchange_grad"):
@@ -223,6 +224,17 @@ def eri3(basis: Basis, aux: Basis, pairs, auxidx, nthreads=0) -> np.ndarray:
     _check(lib().oracle_eri3(*basis.args()[:6], a[0], a[1], a[2], a[3], a[4], a[5], basis.normalize, len(pairs), pp,
                              len(auxidx), ap, V.ctypes.data_as(_dp), nthreads), "oracle_eri3")
     return V.reshape((len(pairs), nab, nc, len(auxidx)), order="F")
+
+
+def eri2(basis: Basis, shells_a, shells_c, nthreads=0) -> np.ndarray:
+    """2-centre Coulomb integrals (a|c) of single shells of one basis (one l per
+    list) as V[i, ma, mc, k] (shape (na, Na, Nc, nc), Fortran order)."""
+    sa, ap = _i(np.asarray(shells_a).reshape(-1))
+    sc, cp = _i(np.asarray(shells_c).reshape(-1))
+    na_, nc_ = nsph(int(basis.l[sa[0]])), nsph(int(basis.l[sc[0]]))
+    V = np.zeros(len(sa) * na_ * nc_ * len(sc))
+    _check(lib().oracle_eri2(*basis.args(), len(sa), ap, len(sc), cp, V.ctypes.data_as(_dp), nthreads), "oracle_eri2")
+    return V.reshape((len(sa), na_, nc_, len(sc)), order="F")
 
 
 def schwarz(basis: Basis, pairs, nthreads=0) -> np.ndarray:

@@ -17,6 +17,7 @@
  *   Sec. 6 exchange operator, brute force                  -> oracle_kbuild
  *   Coulomb operator (the J half of the Fock build)        -> oracle_jbuild
  *   selected shell blocks of K or J                        -> oracle_fock_blocks
+ *   2-centre Coulomb metric (P|Q)                          -> oracle_eri2
  *   gradient of sum W (ab|cd), exchange or Coulomb weights -> oracle_grad_pattern
  * Nuclear derivatives use d/dA_x [x_A^a e^{-z r_A^2}] =
  * 2 z x_A^{a+1} e^{..} - a x_A^{a-1} e^{..} on Cartesian primitives.
@@ -616,6 +617,99 @@ int oracle_eri3(int nshell, const int *l, const int *nprim, const double *exps, 
   }
   free(sh);
   free(ax);
+  return 0;
+}
+
+/* 2-centre Coulomb integral of two primitive Cartesian shells (a|c), both
+ * expanded in Hermite Gaussians about their own centres with the 1-centre
+ * coefficients of Eqs. (E1rr)-(E1-aa):
+ *   (a|c) = 2 pi^{5/2} / (za zc sqrt(za+zc)) sum_t sum_tau E^a_t E^c_tau
+ *           (-1)^{|tau|} R_{t+tau}(rho, A - C),   rho = za zc / (za + zc),
+ * the one-centre bra and ket of Eqs. (0m), (r) and (pq).  Adds w * (a|c) to
+ * out[ia][ic] (Cartesian components). */
+static void prim_cart2(int la, int lc, double za, const double *A, double zc, const double *C, double w,
+                       double *out, scratch *s) {
+  const double rho = za * zc / (za + zc);
+  const double pref = 2.0 * pow(PI_D, 2.5) / (za * zc * sqrt(za + zc));
+  const double AC[3] = {A[0] - C[0], A[1] - C[1], A[2] - C[2]};
+  const int L = la + lc;
+  const size_t n1 = (size_t)L + 1;
+  double *Ea = s->E[0], *Ec = s->E[3];
+  oracle_E1(la, za, Ea);
+  oracle_E1(lc, zc, Ec);
+  R_work(L, rho, AC, pref, s->R, s->RW, s->F);
+  int ca[64][3], cc[64][3];
+  cart_list(la, ca);
+  cart_list(lc, cc);
+  for (int ia = 0; ia < ncart(la); ++ia)
+    for (int ic = 0; ic < ncart(lc); ++ic) {
+      double sum = 0.0;
+      for (int t = 0; t <= ca[ia][0]; ++t)
+        for (int u = 0; u <= ca[ia][1]; ++u)
+          for (int v = 0; v <= ca[ia][2]; ++v) {
+            const double ea = Ea[ca[ia][0] * (la + 1) + t] * Ea[ca[ia][1] * (la + 1) + u] * Ea[ca[ia][2] * (la + 1) + v];
+            if (ea == 0.0) continue;
+            for (int tau = 0; tau <= cc[ic][0]; ++tau)
+              for (int nu = 0; nu <= cc[ic][1]; ++nu)
+                for (int phi = 0; phi <= cc[ic][2]; ++phi) {
+                  const double ec = Ec[cc[ic][0] * (lc + 1) + tau] * Ec[cc[ic][1] * (lc + 1) + nu] *
+                                    Ec[cc[ic][2] * (lc + 1) + phi];
+                  const double sgn = ((tau + nu + phi) & 1) ? -1.0 : 1.0;
+                  sum += ea * sgn * ec * s->R[((t + tau) * n1 + (u + nu)) * n1 + (v + phi)];
+                }
+          }
+      out[(size_t)ia * ncart(lc) + ic] += w * sum;
+    }
+}
+
+int oracle_eri2(int nshell, const int *l, const int *nprim, const double *exps, const double *coefs,
+                const double *centers, int normalize, int na, const int *as, int nc, const int *cs, double *V,
+                int nthreads) {
+  oshell *sh;
+  if (build_shells(nshell, l, nprim, exps, coefs, centers, normalize, ORACLE_LMAX - 1, &sh)) return -1;
+  if (na <= 0 || nc <= 0) {
+    free(sh);
+    return 0;
+  }
+  for (int n = 0; n < na; ++n)
+    if (as[n] < 0 || as[n] >= nshell || sh[as[n]].l != sh[as[0]].l) {
+      free(sh);
+      return -2;
+    }
+  for (int n = 0; n < nc; ++n)
+    if (cs[n] < 0 || cs[n] >= nshell || sh[cs[n]].l != sh[cs[0]].l) {
+      free(sh);
+      return -2;
+    }
+  const int la = sh[as[0]].l, lc = sh[cs[0]].l;
+  const int Na = nsph(la), Nc = nsph(lc);
+  const size_t ncart2 = (size_t)ncart(la) * ncart(lc);
+  const long nq = (long)na * nc;
+#pragma omp parallel num_threads(max_threads(nthreads))
+  {
+    scratch s;
+    scratch_init(&s);
+    double *buf = (double *)malloc(sizeof(double) * ncart2);
+    double *tmp = (double *)malloc(sizeof(double) * ncart2);
+    double *res = (double *)malloc(sizeof(double) * ncart2);
+#pragma omp for schedule(dynamic, 1)
+    for (long q = 0; q < nq; ++q) {
+      const int i = (int)(q % na), k = (int)(q / na);
+      const oshell *a = &sh[as[i]], *c = &sh[cs[k]];
+      memset(buf, 0, sizeof(double) * ncart2);
+      for (int ka = 0; ka < a->K; ++ka)
+        for (int kc = 0; kc < c->K; ++kc) prim_cart2(la, lc, a->z[ka], a->A, c->z[kc], c->A, a->c[ka] * c->c[kc], buf, &s);
+      const int ls[2] = {la, lc};
+      solid_all(buf, tmp, 2, ls, res);
+      for (int ma = 0; ma < Na; ++ma)
+        for (int mc = 0; mc < Nc; ++mc) V[i + (size_t)na * (ma + (size_t)Na * (mc + (size_t)Nc * k))] = res[(size_t)ma * Nc + mc];
+    }
+    free(buf);
+    free(tmp);
+    free(res);
+    scratch_free(&s);
+  }
+  free(sh);
   return 0;
 }
 

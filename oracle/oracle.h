@@ -83,6 +83,13 @@ int oracle_eri3(int nshell, const int *l, const int *nprim, const double *exps,
                 const double *acoefs, const double *acenters, int normalize,
                 int npair, const int *pairs, int naux, const int *aux, double *V, int nthreads);
 
+/* 2-centre Coulomb integrals (a|c) (the density-fitting metric): single
+ * shells as[na] (one l) against single shells cs[nc] (one l) of one basis;
+ * layout V[i, ma, mc, k] (i fastest). */
+int oracle_eri2(int nshell, const int *l, const int *nprim, const double *exps,
+                const double *coefs, const double *centers, int normalize,
+                int na, const int *as, int nc, const int *cs, double *V, int nthreads);
+
 /* Schwarz factors Q_ij = sqrt(max_{ab} |(ab|ab)|) for each pair. */
 int oracle_schwarz(int nshell, const int *l, const int *nprim, const double *exps,
                    const double *coefs, const double *centers, int normalize,
