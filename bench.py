@@ -227,6 +227,41 @@ def eri3_task_list(ctx, steps, flags):
                         "(l_P in 0..6, K=1); 20-bohr cube, exponents log-U[0.05,500]; one mderi_eri3_batch call"}
 
 
+def eri2_metric(ctx, steps):
+    """The 2-centre Coulomb metric (P|Q) of the 512 auxiliary shells of the
+    3-centre workload (l_P 0..6, K=1): every class batch (l_a | l_c), both
+    triangles, timed as one step."""
+    import torch
+    from paper_2405_01834_amd import inputs, model
+    _, aux, _, _ = inputs.eri3_batch(3)
+    a = ctx.basis(aux.l, aux.nprim, aux.exps, aux.coefs, aux.centers)
+    by_l = {l: np.flatnonzero(aux.l == l).astype(np.int32) for l in sorted(set(int(x) for x in aux.l))}
+    outs = {}
+    flops = 0.0
+    for la, A in by_l.items():
+        for lc, C in by_l.items():
+            outs[(la, lc)] = ctx.eri2(a, A, C)
+            # the 3-centre model with a one-centre bra (l_b = 0)
+            flops += len(A) * len(C) * model.eri3_flops(la, 0, lc, 1, 1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        for (la, lc), V in outs.items():
+            ctx.eri2(a, by_l[la], by_l[lc], out=V.permute(3, 2, 1, 0).reshape(-1))
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nao = int(np.sum(2 * aux.l + 1))
+    log(f"eri2 metric: {len(aux.l)} shells, {nao}x{nao} elements, {ms:.3f} ms ({nao * nao / (ms * 1e-3):.3e} "
+        f"elements/s, {flops / (ms * 1e-3) / 1e12:.2f} TFLOP/s)")
+    return {"ms": ms, "shells": int(len(aux.l)), "elements": nao * nao, "elements_per_s": nao * nao / (ms * 1e-3),
+            "model_tflops": flops / (ms * 1e-3) / 1e12,
+            "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / model.FP64_PEAK_TFLOPS, "class_batches": len(outs),
+            "workload": "2-centre metric of the 512 auxiliary shells of the 3-centre workload (l 0..6, K=1, "
+                        "20-bohr cube, exponents log-U[0.05,500]); all 49 class batches, both triangles"}
+
+
 def count_quartets(ctx, basis, sh):
     """Symmetry-unique quartets of the K build and ordered visits of the
     gradient that pass the screening (Q_ij Q_max >= tau for pairs, Q_ij Q_kl
@@ -435,6 +470,7 @@ def main():
         rec["mixed_precision"] = mixed_precision(ctx, max(args.steps, 2))
     if args.eri3 != "off":
         rec["eri3_batch"] = eri3_task_list(ctx, max(args.steps, 3), args.eri3)
+        rec["eri2_metric"] = eri2_metric(ctx, max(args.steps, 3))
     if args.cluster_atoms > 0:
         rec["backward_forward"] = backward_forward(ctx, args.cluster_atoms)
     if not args.no_cpu:

@@ -166,6 +166,24 @@ mderi_status mderi_eri4_noalloc(mderi_ctx_t ctx, mderi_basis_t basis, int nbra, 
                                 void *stream);
 
 /*
+ * Class batch of 2-centre Coulomb integrals (P|Q), the metric of density
+ * fitting (Sec. 1 motivates 3-centre integrals by it; Sec. 2: both shells
+ * expanded with the 1-centre Hermite coefficients of Eqs. (E1rr)-(E1-aa),
+ * then Eqs. (0m), (r), (pq) and the two transforms, as for (ab|P) with a
+ * 1-centre bra).
+ *
+ * shells_a_host[na] and shells_c_host[nc] are int32 shell indices of `basis`,
+ * each list of one l (l_a, l_c).  Writes
+ *     V_dev[i + na*(ma + N(l_a)*(mc + N(l_c)*k))]
+ * (i fastest).  V_elems must be at least na*N(l_a)*N(l_c)*nc.  FP64;
+ * opts may be NULL or carry MDERI_FLAG_AUTOTUNE.  EINVAL for bad shells or
+ * mixed l within a list, ESIZE for a short output.
+ */
+mderi_status mderi_eri2(mderi_ctx_t ctx, mderi_basis_t basis, int na, const int32_t *shells_a_host, int nc,
+                        const int32_t *shells_c_host, double *V_dev, size_t V_elems, const mderi_opts *opts,
+                        void *stream);
+
+/*
  * Class batch of 3-centre integrals (ab|P) (Sec. 2: the 1-centre Hermite
  * expansion of Eqs. (E1rr)-(E1-aa); the paper writes them [P|ab]).
  *

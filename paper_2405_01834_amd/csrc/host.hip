@@ -705,7 +705,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
                              int precision = 0, int slices = kSplitDefault, bool noalloc = false, int tile_variant = 0,
                              int *count = nullptr) {
   const int nbra = (int)bra.off.size() - 1, nket = (int)ket.off.size() - 1;
-  const int la = bra.la, lb = bra.lb, lc = ket.la, ld = ket.one_centre ? 0 : ket.lb;
+  const int la = bra.la, lb = bra.one_centre ? 0 : bra.lb, lc = ket.la, ld = ket.one_centre ? 0 : ket.lb;
   const int Lb = la + lb, Lk = lc + ld, L = Lb + Lk;
   const int Nb = nsph(la) * nsph(lb), Nk = ket.one_centre ? nsph(lc) : nsph(lc) * nsph(ld);
   const int Nhb = ntil(Lb);
@@ -727,7 +727,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   const bool split = precision == MDERI_SPLIT_BF16;
   if (split && (pl.npt & 1)) ++pl.npt;  // the BF16 operands pair 16-row tiles
   std::vector<std::array<int, 3>> cands = {{pl.npt, pl.nps, pl.dbuf}};
-  const std::array<int, 6> sig = {la, lb, lc, ket.one_centre ? -1 : ld, maxb, maxk};
+  const std::array<int, 6> sig = {la, bra.one_centre ? -1 : lb, lc, ket.one_centre ? -1 : ld, maxb, maxk};
   std::vector<std::array<int, 3>> all;
   if (!diag && pl.nslab == 1 && !split) all = block_candidates(Nhb, Nb, Nk, L, cube_sz, Nhk_pad, maxpp);
   if (count) {
@@ -817,7 +817,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
   pa.Nh_pad = Hb_rows;
   pa.N_pad = Nb_pad;
   pa.ket_sign = 0;
-  pa.one_centre = 0;
+  pa.one_centre = bra.one_centre ? 1 : 0;
   pa.deriv = 0;
   pa.split = split ? slices : 0;
   pa.Hs = (uint16_t *)d_Hs;
@@ -1023,6 +1023,26 @@ extern "C" mderi_status mderi_eri3(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t
   if (V_elems < need) return fail(MDERI_ESIZE, "mderi_eri3: output holds %zu doubles, needs %zu", V_elems, need);
   HIP_TRY(hipSetDevice(c->device));
   return run_class_batch(c, sb, sk, 0, V, nullptr, nullptr, (hipStream_t)stream);
+}
+
+extern "C" mderi_status mderi_eri2(mderi_ctx_t c, mderi_basis_t b, int na, const int32_t *shells_a, int nc,
+                                   const int32_t *shells_c, double *V, size_t V_elems, const mderi_opts *opts,
+                                   void *stream) {
+  if (!c || !b) return fail(MDERI_EINVAL, "mderi_eri2: NULL context or basis");
+  if (b->ctx != c) return fail(MDERI_EINVAL, "mderi_eri2: basis belongs to another context");
+  if (opts && opts->precision != 0) return fail(MDERI_EUNSUPPORTED, "mderi_eri2: precision %d", opts->precision);
+  // both sides single shells: the 1-centre Hermite expansion on the bra as on
+  // the ket of the 3-centre integrals
+  Side sa{b, 0, 0, true, {}, {}}, sc{b, 0, 0, true, {}, {}};
+  mderi_status st;
+  if ((st = expand_shells(b, na, shells_a, "shells_a", &sa.la, sa)) != MDERI_OK) return st;
+  if ((st = expand_shells(b, nc, shells_c, "shells_c", &sc.la, sc)) != MDERI_OK) return st;
+  const size_t need = (size_t)na * nsph(sa.la) * nsph(sc.la) * nc;
+  if (!V) return fail(MDERI_EINVAL, "mderi_eri2: NULL output");
+  if (V_elems < need) return fail(MDERI_ESIZE, "mderi_eri2: output holds %zu doubles, needs %zu", V_elems, need);
+  HIP_TRY(hipSetDevice(c->device));
+  return run_class_batch(c, sa, sc, 0, V, nullptr, nullptr, (hipStream_t)stream,
+                         (opts && (opts->flags & MDERI_FLAG_AUTOTUNE)) ? MDERI_FLAG_AUTOTUNE : 0);
 }
 
 extern "C" mderi_status mderi_schwarz(mderi_ctx_t c, mderi_basis_t b, int npair, const int32_t *pairs, double *Q,

@@ -77,6 +77,9 @@ def load_library():
     L.mderi_eri3.argtypes = [_vp, _vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
                              ctypes.POINTER(Opts), _vp]
     L.mderi_eri3.restype = ctypes.c_int
+    L.mderi_eri2.argtypes = [_vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
+                             ctypes.POINTER(Opts), _vp]
+    L.mderi_eri2.restype = ctypes.c_int
     L.mderi_kbuild.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _vp]
     L.mderi_kbuild.restype = ctypes.c_int
     L.mderi_eri3_batch.argtypes = [_vp, _vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
@@ -209,6 +212,30 @@ class Context:
                                          len(auxidx), auxidx.ctypes.data_as(_ip), _vp(out.data_ptr()), out.numel(),
                                          None, _stream_handle(stream)))
         return out[:n].view(len(auxidx), npp, nab, len(pairs)).permute(3, 2, 1, 0)
+
+    def eri2(self, basis: "Basis", shells_a, shells_c, flags=0, out=None, stream=None):
+        """Class batch of the 2-centre metric (a|c) -> torch float64 tensor
+        V[i, ma, mc, k] (shape (na, N(l_a), N(l_c), nc), a Fortran-order view of
+        the flat output).  flags: FLAG_AUTOTUNE."""
+        import torch
+        sa = np.ascontiguousarray(np.asarray(shells_a, dtype=np.int32).reshape(-1))
+        sc = np.ascontiguousarray(np.asarray(shells_c, dtype=np.int32).reshape(-1))
+        ok = (len(sa) > 0 and len(sc) > 0 and min(sa.min(), sc.min()) >= 0 and
+              max(sa.max(), sc.max()) < basis.nshell)
+        opts = Opts(0, 0.0, int(flags))
+        if not ok:
+            _check(load_library().mderi_eri2(self._h, basis._h, len(sa), sa.ctypes.data_as(_ip), len(sc),
+                                             sc.ctypes.data_as(_ip), None, 0, ctypes.byref(opts),
+                                             _stream_handle(stream)))
+        na_, nc_ = nsph(int(basis.l[sa[0]])), nsph(int(basis.l[sc[0]]))
+        n = len(sa) * na_ * nc_ * len(sc)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=f"cuda:{self.device}")
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        _check(load_library().mderi_eri2(self._h, basis._h, len(sa), sa.ctypes.data_as(_ip), len(sc),
+                                         sc.ctypes.data_as(_ip), _vp(out.data_ptr()), out.numel(), ctypes.byref(opts),
+                                         _stream_handle(stream)))
+        return out[:n].view(len(sc), nc_, na_, len(sa)).permute(3, 2, 1, 0)
 
     def eri3_batch(self, basis: "Basis", aux: "Basis", pairs, auxidx, flags=0, out=None, stream=None):
         """(ab|P) over pairs and auxiliary shells of any classes in one task-list

@@ -1,0 +1,141 @@
+"""GPU parity of the 2-centre Coulomb metric (a|c) (both shells expanded with
+the 1-centre Hermite coefficients of Eqs. (E1rr)-(E1-aa)).
+
+Reference: every primitive pair by Obara-Saika/Head-Gordon-Pople in 40
+digits on (a s0|c s0) (s functions of exponent 0, the oracle's 2-centre pin),
+the solid-harmonic transform in 40 digits, contracted with the raw
+coefficients (normalize = 0 on both sides).  Bar: every (a|c) shell block
+within 1e-12 of its largest element plus 1e-14 q_a q_c, q_a^2 the largest
+element of (a|a) (Cauchy-Schwarz: |(a|c)| <= q_a q_c, the block's natural
+scale when symmetry makes it vanish).  The FP64 oracle is not the
+reference here: its Cartesian route cancels up to four digits in the
+solid-harmonic sums of blocks that mix tight and diffuse shells (it sits up
+to 6e-11 of a (6|6) block's largest element from the 40-digit value), and
+on coincident centres the integrals of l_a != l_c vanish by symmetry, so an
+element-wise relative bar has no meaning there.  The metric of a mixed-l set
+assembled from class batches is also checked to be symmetric and positive
+definite."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_01834_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(need_gpu):
+    from paper_2405_01834_amd import Context
+    return Context(0)
+
+
+def _os_solid2(la, za, A, lc, zc, C):
+    """(a|c) of raw primitives, 40 digits, solid components [ma][mc]."""
+    import mpmath as mp
+    from tests.ref.os_hgp import cart_list, prim_eri_cart
+    with mp.workdps(40):
+        prim = prim_eri_cart(la, 0, lc, 0, za, A, 0.0, A, zc, C, 0.0, C, 40)
+        s0 = cart_list(0)[0]
+        M = mp.matrix([[prim[(a, s0, c, s0)] for c in cart_list(lc)] for a in cart_list(la)])
+        R = mp.matrix(oracle.solid(la).tolist()) * M * mp.matrix(oracle.solid(lc).tolist()).T
+        return np.array([[float(R[x, y]) for y in range(2 * lc + 1)] for x in range(2 * la + 1)])
+
+
+def _block_ref(sh, i, k):
+    po = np.concatenate([[0], np.cumsum(sh.nprim)])
+    out = 0.0
+    for p in range(po[i], po[i + 1]):
+        for q in range(po[k], po[k + 1]):
+            out = out + sh.coefs[p] * sh.coefs[q] * _os_solid2(int(sh.l[i]), sh.exps[p], sh.centers[i], int(sh.l[k]),
+                                                               sh.exps[q], sh.centers[k])
+    return out
+
+
+def _run_and_check(ctx, sh, A, C):
+    import torch
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, normalize=0)
+    V = ctx.eri2(b, A, C)
+    torch.cuda.synchronize()
+    got = V.cpu().numpy()
+    q = {s: float(np.sqrt(np.max(np.abs(_block_ref(sh, s, s))))) for s in list(A) + list(C)}
+    for i, si in enumerate(A):
+        for k, sk in enumerate(C):
+            ref = _block_ref(sh, si, sk)
+            err = np.max(np.abs(got[i, :, :, k] - ref))
+            assert err <= 1e-12 * np.max(np.abs(ref)) + 1e-14 * q[si] * q[sk], (i, k, err, np.max(np.abs(ref)))
+
+
+CASES = [(0, 0, 1, 4, 5), (1, 0, 2, 3, 3), (2, 1, 3, 3, 2), (3, 3, 1, 5, 4), (4, 2, 2, 2, 5), (4, 4, 3, 3, 2),
+         (5, 3, 1, 4, 3), (6, 6, 1, 4, 3), (6, 1, 2, 2, 3), (2, 5, 1, 9, 2)]
+
+
+@pytest.mark.parametrize("la,lc,K,na,nc", CASES)
+def test_eri2_class_parity(ctx, la, lc, K, na, nc):
+    """One class batch (l_a | l_c) with K primitives per shell, ragged counts,
+    exponents log-uniform over [0.05, 500], coefficients U[0.1, 1], centres in
+    a 6-bohr cube."""
+    rng = np.random.default_rng(700 + 13 * la + lc + 3 * K)
+    sh = inputs.random_shells(rng, [la] * na + [lc] * nc, K, 6.0, 0.05, 500.0)
+    _run_and_check(ctx, sh, np.arange(na, dtype=np.int32), np.arange(na, na + nc, dtype=np.int32))
+
+
+@pytest.mark.parametrize("la,lc", [(0, 0), (1, 1), (2, 0), (3, 3), (4, 2), (5, 5), (6, 6)])
+def test_eri2_coincident_centres(ctx, la, lc):
+    """Shells on one centre (the same-atom blocks of a fitting metric; two
+    primitives, exponents 0.1-20)."""
+    rng = np.random.default_rng(900 + 7 * la + lc)
+    sh = inputs.random_shells(rng, [la] * 3 + [lc] * 3, 2, 3.0, 0.1, 20.0)
+    sh.centers[:] = sh.centers[0]
+    _run_and_check(ctx, sh, np.arange(3, dtype=np.int32), np.arange(3, 6, dtype=np.int32))
+
+
+def test_eri2_matches_oracle_normalised(ctx):
+    """Normalised contracted shells of a moderate class against the FP64
+    oracle element by element (1e-14 + 1e-12 |ref|): both sides normalise the
+    same way."""
+    import torch
+    rng = np.random.default_rng(21)
+    sh = inputs.random_shells(rng, [2] * 4 + [1] * 3, 2, 5.0, 0.2, 20.0)
+    A, C = np.arange(4, dtype=np.int32), np.arange(4, 7, dtype=np.int32)
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    V = ctx.eri2(b, A, C)
+    torch.cuda.synchronize()
+    got = V.cpu().numpy()
+    ref = oracle.eri2(oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, 1), A, C)
+    err = np.abs(got - ref)
+    assert not (err > 1e-14 + 1e-12 * np.abs(ref)).any(), err.max()
+
+
+def test_eri2_metric_symmetric_positive_definite(ctx):
+    """The metric of 16 shells (l 0..6, K 1..2) assembled from class batches
+    is symmetric and positive definite."""
+    import torch
+    rng = np.random.default_rng(17)
+    ls = [0, 1, 2, 3, 4, 5, 6, 0, 1, 2, 3, 4, 2, 1, 0, 3]
+    Ks = [int(x) for x in rng.integers(1, 3, len(ls))]
+    sh = inputs.random_shells(rng, ls, Ks, 4.0, 0.1, 20.0)
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    off = np.concatenate([[0], np.cumsum(2 * np.asarray(ls) + 1)])
+    n = off[-1]
+    M = np.zeros((n, n))
+    by_l = {l: np.array([i for i, x in enumerate(ls) if x == l], np.int32) for l in set(ls)}
+    for la, A in by_l.items():
+        for lc, C in by_l.items():
+            V = ctx.eri2(b, A, C)
+            torch.cuda.synchronize()
+            got = V.cpu().numpy()
+            for i, si in enumerate(A):
+                for k, sk in enumerate(C):
+                    M[off[si]:off[si + 1], off[sk]:off[sk + 1]] = got[i, :, :, k]
+    assert np.max(np.abs(M - M.T)) <= 1e-13 * np.max(np.abs(M))
+    assert np.min(np.linalg.eigvalsh(0.5 * (M + M.T))) > 0.0
+
+
+def test_eri2_rejects_mixed_l(ctx):
+    from paper_2405_01834_amd.mderi import MderiError
+    rng = np.random.default_rng(3)
+    sh = inputs.random_shells(rng, [1, 2, 1], 1, 4.0, 0.1, 10.0)
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    with pytest.raises(MderiError):
+        ctx.eri2(b, [0, 1], [2])
