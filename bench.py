@@ -40,8 +40,8 @@ TAU = 1e-12
 # WRITE_SIZE (x1) counters (profiles/eri4_ggK3_hbm_counters.md), valid only for
 # the kernel sources they were taken with.
 TRAFFIC = {"kernel": "eri4_kernel [gg|gg] K=3", "bytes": 1.1305e11,
-           "sources": {"eri4.hip": "3ab90cc2c6237d63", "device_common.h": "1d6737b5b2d84adb",
-                       "internal.h": "54ee5b1c74a9bbdf"}}
+           "sources": {"eri4.hip": "ff26cc5271d31933", "device_common.h": "1d6737b5b2d84adb",
+                       "internal.h": "2c30d7b888ea459f"}}
 
 
 def measured_traffic(kernel):
