@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
-ORACLE_LMAX = 6  # public shells; derivatives use l+1 internally
+ORACLE_LMAX = 8  # public shells; derivatives use l+1 internally
 
 
 def build(force: bool = True) -> str:

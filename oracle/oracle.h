@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define ORACLE_LMAX 7  /* shells up to l=7 (l=6 plus one for derivatives) */
+#define ORACLE_LMAX 9  /* shells up to l=9 (l=8 plus one for derivatives) */
 #define ORACLE_KMAX 16 /* primitives per shell */
 
 /* Boys function F_m(T), m = 0..mmax, Eq. (boys). */
