@@ -262,6 +262,40 @@ def eri2_metric(ctx, steps):
                         "20-bohr cube, exponents log-U[0.05,500]); all 49 class batches, both triangles"}
 
 
+def high_l_aux(ctx, steps):
+    """3-centre class batches with auxiliary shells beyond l = 6: 256 (dd)
+    pairs (K=3 per shell) x 256 auxiliary shells of l = 7 and of l = 8 (K=1)."""
+    import torch
+    from paper_2405_01834_amd import inputs, model
+    rng = np.random.default_rng(8)
+    prim = inputs.random_shells(rng, [2] * 512, 3, 20.0, 0.05, 500.0)
+    b = ctx.basis(prim.l, prim.nprim, prim.exps, prim.coefs, prim.centers)
+    pairs = np.arange(512, dtype=np.int32).reshape(-1, 2)
+    res = {}
+    for lP in (7, 8):
+        aux = inputs.random_shells(rng, [lP] * 256, 1, 20.0, 0.05, 500.0)
+        a = ctx.basis(aux.l, aux.nprim, aux.exps, aux.coefs, aux.centers)
+        idx = np.arange(256, dtype=np.int32)
+        V = ctx.eri3(b, a, pairs, idx)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        flat = V.permute(3, 2, 1, 0).reshape(-1)
+        e0.record()
+        for _ in range(steps):
+            ctx.eri3(b, a, pairs, idx, out=flat)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        flops = len(pairs) * len(idx) * model.eri3_flops(2, 2, lP, 9, 1)
+        res[f"(dd|{lP})"] = {"ms": ms, "triplets_per_s": len(pairs) * len(idx) / (ms * 1e-3),
+                             "model_tflops": flops / (ms * 1e-3) / 1e12,
+                             "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / model.FP64_PEAK_TFLOPS}
+        log(f"(dd|{lP}) K=3: {ms:.3f} ms ({flops / (ms * 1e-3) / 1e12:.2f} TFLOP/s)")
+    res["workload"] = ("256 (dd) pairs, K=3 per shell, x 256 auxiliary shells of l = 7 and of l = 8 (K=1); 20-bohr "
+                       "cube, exponents log-U[0.05,500]")
+    return res
+
+
 def count_quartets(ctx, basis, sh):
     """Symmetry-unique quartets of the K build and ordered visits of the
     gradient that pass the screening (Q_ij Q_max >= tau for pairs, Q_ij Q_kl
@@ -471,6 +505,7 @@ def main():
     if args.eri3 != "off":
         rec["eri3_batch"] = eri3_task_list(ctx, max(args.steps, 3), args.eri3)
         rec["eri2_metric"] = eri2_metric(ctx, max(args.steps, 3))
+        rec["high_l_aux"] = high_l_aux(ctx, max(args.steps, 3))
     if args.cluster_atoms > 0:
         rec["backward_forward"] = backward_forward(ctx, args.cluster_atoms)
     if not args.no_cpu:

@@ -47,7 +47,7 @@ typedef enum {
   MDERI_ESIZE = -5         /* output buffer too small */
 } mderi_status;
 
-#define MDERI_LMAX 6  /* largest shell angular momentum */
+#define MDERI_LMAX 8  /* largest shell angular momentum */
 #define MDERI_KMAX 16 /* largest number of primitives per shell */
 
 typedef struct mderi_ctx *mderi_ctx_t;

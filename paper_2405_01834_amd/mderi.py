@@ -11,7 +11,7 @@ _LIB_PATH = os.path.join(_HERE, "libmderi.so")
 
 _lib = None
 
-MDERI_LMAX = 6
+MDERI_LMAX = 8
 MDERI_KMAX = 16
 
 

@@ -67,7 +67,8 @@ def _run_and_check(ctx, sh, A, C):
 
 
 CASES = [(0, 0, 1, 4, 5), (1, 0, 2, 3, 3), (2, 1, 3, 3, 2), (3, 3, 1, 5, 4), (4, 2, 2, 2, 5), (4, 4, 3, 3, 2),
-         (5, 3, 1, 4, 3), (6, 6, 1, 4, 3), (6, 1, 2, 2, 3), (2, 5, 1, 9, 2)]
+         (5, 3, 1, 4, 3), (6, 6, 1, 4, 3), (6, 1, 2, 2, 3), (2, 5, 1, 9, 2), (8, 8, 1, 2, 2), (7, 2, 2, 3, 2),
+         (0, 8, 1, 3, 3)]
 
 
 @pytest.mark.parametrize("la,lc,K,na,nc", CASES)
@@ -80,7 +81,7 @@ def test_eri2_class_parity(ctx, la, lc, K, na, nc):
     _run_and_check(ctx, sh, np.arange(na, dtype=np.int32), np.arange(na, na + nc, dtype=np.int32))
 
 
-@pytest.mark.parametrize("la,lc", [(0, 0), (1, 1), (2, 0), (3, 3), (4, 2), (5, 5), (6, 6)])
+@pytest.mark.parametrize("la,lc", [(0, 0), (1, 1), (2, 0), (3, 3), (4, 2), (5, 5), (6, 6), (8, 7)])
 def test_eri2_coincident_centres(ctx, la, lc):
     """Shells on one centre (the same-atom blocks of a fitting metric; two
     primitives, exponents 0.1-20)."""

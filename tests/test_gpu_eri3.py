@@ -33,7 +33,9 @@ def _run(ctx, sh, aux, pairs, auxidx):
 
 
 CASES = [((0, 0), 0, 1, 1), ((1, 0), 2, 2, 1), ((1, 1), 1, 3, 1), ((2, 1), 3, 1, 1), ((3, 3), 6, 1, 1),
-         ((2, 2), 4, 5, 1), ((3, 2), 5, 2, 1), ((0, 0), 6, 3, 1), ((3, 3), 0, 2, 1), ((1, 3), 4, 4, 1)]
+         ((2, 2), 4, 5, 1), ((3, 2), 5, 2, 1), ((0, 0), 6, 3, 1), ((3, 3), 0, 2, 1), ((1, 3), 4, 4, 1),
+         # auxiliary shells beyond l = 6
+         ((1, 1), 8, 2, 1), ((3, 2), 7, 1, 1), ((0, 0), 8, 3, 1), ((3, 3), 8, 1, 1)]
 
 
 @pytest.mark.parametrize("cls,lP,K,KP", CASES)

@@ -112,7 +112,9 @@ def test_schwarz_factors_mixed_classes(ctx):
 
 
 HIGH_L = [((5, 5, 5, 5), 1, 3, 2), ((6, 6, 6, 6), 1, 2, 2), ((6, 5, 4, 4), 1, 2, 2), ((5, 5, 5, 5), 2, 1, 2),
-          ((6, 6, 3, 2), 1, 2, 3)]
+          ((6, 6, 3, 2), 1, 2, 3),
+          # shells beyond l = 6 (total degree within the [r] builder's 26)
+          ((7, 0, 7, 0), 1, 3, 2), ((8, 1, 2, 0), 2, 2, 2), ((8, 8, 4, 2), 1, 1, 2), ((7, 7, 6, 0), 1, 1, 2)]
 
 
 @pytest.mark.parametrize("cls,K,nbra,nket", HIGH_L)
@@ -137,6 +139,17 @@ def test_high_l_parity(ctx, cls, K, nbra, nket):
         for k, (q0, q1) in enumerate(ket):
             ref = md_matrix.shellset(sh, p0, p1, q0, q1)
             _assert_close(got[i, :, :, k], ref, f"{cls} K={K} quartet ({i},{k})")
+
+
+def test_beyond_fused_tiles_is_refused(ctx):
+    """(77|75): V of one quartet (225 x 165) and its 455 ket Hermite rows do
+    not fit the fused kernel's tiles; the call is refused, nothing runs."""
+    from paper_2405_01834_amd.mderi import MderiError
+    rng = np.random.default_rng(5)
+    sh = inputs.random_shells(rng, [7, 7, 7, 5], 1, 4.0, 0.1, 30.0)
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    with pytest.raises(MderiError, match="beyond the fused kernel"):
+        ctx.eri4(b, [[0, 1]], [[2, 3]])
 
 
 def test_schwarz_high_l(ctx):
