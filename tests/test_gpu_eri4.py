@@ -94,7 +94,7 @@ def test_validation_errors(ctx):
     with pytest.raises(MderiError):  # non-positive exponent
         ctx.basis([0], [1], [-1.0], [1.0], [[0, 0, 0]])
     with pytest.raises(MderiError):  # l beyond the built maximum
-        ctx.basis([7], [1], [1.0], [1.0], [[0, 0, 0]])
+        ctx.basis([9], [1], [1.0], [1.0], [[0, 0, 0]])
 
 
 def test_schwarz_factors_mixed_classes(ctx):
