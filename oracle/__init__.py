@@ -274,6 +274,43 @@ def jbuild(basis: Basis, D, tau=1e-12, nthreads=0) -> np.ndarray:
     return J
 
 
+def three_index(basis: Basis, aux: Basis, nthreads=0) -> np.ndarray:
+    """Dense (ab|P) over all AO pairs of `basis` and all AOs of `aux`:
+    T[a, b, P] (shape (nao, nao, naux_ao)), assembled from eri3 shell by shell."""
+    ao = np.concatenate([[0], np.cumsum(2 * basis.l + 1)])
+    xo = np.concatenate([[0], np.cumsum(2 * aux.l + 1)])
+    T = np.zeros((ao[-1], ao[-1], xo[-1]))
+    for i in range(basis.nshell):
+        for j in range(basis.nshell):
+            for k in range(aux.nshell):
+                V = eri3(basis, aux, [[i, j]], [k], nthreads)[0]  # [ab, mP]
+                T[ao[i]:ao[i + 1], ao[j]:ao[j + 1], xo[k]:xo[k + 1]] = V.reshape(ao[i + 1] - ao[i], ao[j + 1] - ao[j], -1)
+    return T
+
+
+def metric(aux: Basis, nthreads=0) -> np.ndarray:
+    """Dense Coulomb metric M_PQ = (P|Q) over all AOs of `aux`."""
+    xo = np.concatenate([[0], np.cumsum(2 * aux.l + 1)])
+    M = np.zeros((xo[-1], xo[-1]))
+    for i in range(aux.nshell):
+        for k in range(aux.nshell):
+            M[xo[i]:xo[i + 1], xo[k]:xo[k + 1]] = eri2(aux, [i], [k], nthreads)[0, :, :, 0]
+    return M
+
+
+def dfj(basis: Basis, aux: Basis, D, nthreads=0) -> np.ndarray:
+    """Density-fitted Coulomb matrix (the use of 3-centre integrals that Sec. 1
+    motivates): the pair density sum_cd D_cd (cd| is fitted in the Coulomb
+    metric, c = M^{-1} gamma with gamma_Q = sum_cd (Q|cd) D_cd and
+    M_PQ = (P|Q), and J_ab = sum_P (ab|P) c_P.  Dense assembly; numpy solves."""
+    assert basis.normalize == aux.normalize
+    T = three_index(basis, aux, nthreads)
+    M = metric(aux, nthreads)
+    gamma = np.einsum("abP,ab->P", T, np.asarray(D, dtype=np.float64))
+    c = np.linalg.solve(M, gamma)
+    return T @ c
+
+
 def fock_blocks(basis: Basis, D, blocks, which="K", tau=1e-12, nthreads=0):
     """Shell blocks of K (which="K", block (s0, s1) = K[AOs of s0, AOs of s1])
     or J (which="J") by the brute force restricted to the quartets feeding

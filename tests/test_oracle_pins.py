@@ -662,3 +662,45 @@ def test_three_centre_high_aux_l_against_obara_saika(la, lb, lP):
                                  (lP, ex[2], [1.0], cen[2]), (0, [0.0], [1.0], cen[2])], dps=30)[..., 0]
     ref = np.einsum("ai,bj,ck,ijk->abc", oracle.solid(la), oracle.solid(lb), oracle.solid(lP), ref_c).reshape(V.shape)
     assert np.max(np.abs(V - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_dfj_exact_when_products_are_in_the_fitting_set():
+    """s shells of single primitives: phi_i phi_j is one s Gaussian of exponent
+    a_i + a_j at P_ij, so with those products as the fitting set the pair
+    density lies in its span and density-fitted J equals the exact J (the
+    oracle's brute force)."""
+    rng = np.random.default_rng(31)
+    n = 3
+    ex = np.exp(rng.uniform(np.log(0.3), np.log(3.0), n))
+    cen = rng.uniform(-1.0, 1.0, (n, 3))
+    b = oracle.Basis([0] * n, [1] * n, ex, np.ones(n), cen, 1)
+    pe, pc = [], []
+    for i in range(n):
+        for j in range(i, n):
+            pe.append(ex[i] + ex[j])
+            pc.append((ex[i] * cen[i] + ex[j] * cen[j]) / (ex[i] + ex[j]))
+    aux = oracle.Basis([0] * len(pe), [1] * len(pe), np.array(pe), np.ones(len(pe)), np.array(pc), 1)
+    C = rng.normal(size=(n, n))
+    D = C @ C.T
+    J = oracle.jbuild(b, D)
+    Jdf = oracle.dfj(b, aux, D)
+    assert np.max(np.abs(Jdf - J)) <= 1e-10 * np.max(np.abs(J))
+
+
+def test_dfj_energy_is_variational():
+    """The fitted Coulomb energy never exceeds the exact one:
+    tr(D J_df) = gamma^T M^{-1} gamma <= tr(D J), the fitting error being
+    non-negative in the Coulomb norm (mixed l, incomplete fitting set)."""
+    rng = np.random.default_rng(32)
+    ls = [0, 1, 0, 2]
+    b = oracle.Basis(ls, [1] * 4, np.exp(rng.uniform(np.log(0.3), np.log(3), 4)), np.ones(4),
+                     rng.uniform(-1, 1, (4, 3)), 1)
+    aux = oracle.Basis([0, 1, 2, 0, 1], [1] * 5, np.exp(rng.uniform(np.log(0.2), np.log(4), 5)), np.ones(5),
+                       rng.uniform(-1, 1, (5, 3)), 1)
+    nao = b.nao()
+    C = rng.normal(size=(nao, 3))
+    D = C @ C.T
+    J = oracle.jbuild(b, D)
+    Jdf = oracle.dfj(b, aux, D)
+    E, Edf = float(np.sum(D * J)), float(np.sum(D * Jdf))
+    assert 0.0 < Edf <= E * (1 + 1e-12)
