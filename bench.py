@@ -296,6 +296,42 @@ def high_l_aux(ctx, steps):
     return res
 
 
+def dfj_leg(ctx, natom=12):
+    """Density-fitted J on the cluster recipe with an even-tempered fitting
+    set per atom (s4 p3 d3 f2 g2 h1, exponents geometric 0.1-60), against the
+    4-centre J of the quartet engine: time of one call (after a warm-up) and
+    the relative error of tr(D J)."""
+    import torch
+    from paper_2405_01834_amd import inputs
+    sh, atom, pos, D = inputs.cluster(7, natom)
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, atom=atom)
+    ls, ex, cen = [], [], []
+    for p in pos:
+        for l, n in ((0, 4), (1, 3), (2, 3), (3, 2), (4, 2), (5, 1)):
+            for z in (np.geomspace(0.1, 60.0, n) if n > 1 else [np.sqrt(6.0)]):
+                ls.append(l)
+                ex.append(z)
+                cen.append(p)
+    a = ctx.basis(np.array(ls, np.int32), np.ones(len(ls), np.int32), np.array(ex), np.ones(len(ls)), np.array(cen))
+    Dd = torch.tensor(D, device="cuda")
+    ctx.dfj(b, a, Dd)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Jdf = ctx.dfj(b, a, Dd)
+    torch.cuda.synchronize()
+    tdf = time.perf_counter() - t
+    J, _ = ctx.jkbuild(b, Dd, want_k=False, tau=TAU)
+    torch.cuda.synchronize()
+    e, edf = float(torch.sum(Dd * J)), float(torch.sum(Dd * Jdf))
+    nrow = int(sum((2 * sh.l[i] + 1) * (2 * sh.l[j] + 1) for i in range(sh.n) for j in range(i + 1)))
+    log(f"DF-J {natom} atoms: {a.nao()} fitting AOs, {nrow} pair rows, {tdf * 1e3:.1f} ms; "
+        f"tr(DJ) relative error {abs(edf - e) / abs(e):.2e}")
+    return {"ms": tdf * 1e3, "atoms": natom, "nao": b.nao(), "fitting_aos": a.nao(), "pair_rows": nrow,
+            "triplets": int(sh.n * (sh.n + 1) // 2 * len(ls)), "energy_rel_err": abs(edf - e) / abs(e),
+            "workload": "cluster recipe, %d atoms; fitting set per atom s4 p3 d3 f2 g2 h1 (K=1, even-tempered "
+                        "0.1-60); one mderi_dfj call (all canonical pairs, no screening) after a warm-up" % natom}
+
+
 def count_quartets(ctx, basis, sh):
     """Symmetry-unique quartets of the K build and ordered visits of the
     gradient that pass the screening (Q_ij Q_max >= tau for pairs, Q_ij Q_kl
@@ -506,6 +542,7 @@ def main():
         rec["eri3_batch"] = eri3_task_list(ctx, max(args.steps, 3), args.eri3)
         rec["eri2_metric"] = eri2_metric(ctx, max(args.steps, 3))
         rec["high_l_aux"] = high_l_aux(ctx, max(args.steps, 3))
+        rec["dfj"] = dfj_leg(ctx)
     if args.cluster_atoms > 0:
         rec["backward_forward"] = backward_forward(ctx, args.cluster_atoms)
     if not args.no_cpu:

@@ -184,6 +184,24 @@ mderi_status mderi_eri2(mderi_ctx_t ctx, mderi_basis_t basis, int na, const int3
                         void *stream);
 
 /*
+ * Density-fitted Coulomb matrix (the use of 3-centre integrals Sec. 1
+ * motivates): the pair density sum_cd D_cd (cd| is fitted in the Coulomb
+ * metric of the auxiliary basis,
+ *     gamma_Q = sum_cd (Q|cd) D_cd,  M_PQ = (P|Q),  c = M^{-1} gamma,
+ *     J_ab = sum_P (ab|P) c_P,
+ * with (ab|P) over every canonical shell pair of `basis` and every shell of
+ * `aux` (mderi_eri3_batch), M from mderi_eri2's class batches, and the
+ * Cholesky solve by rocSOLVER on the stream.  D_dev, J_dev: [nao][nao]
+ * row-major FP64 on the device, D symmetric; J is written in full.  The
+ * metric must be positive definite (a linearly dependent fitting set is the
+ * caller's to prune; the solve does not report it and J is then undefined).
+ * Device workspace grows to hold the npairrow x naux (ab|P) matrix and the
+ * naux x naux metric.  The (ab|P) plan's first call synchronises the stream.
+ */
+mderi_status mderi_dfj(mderi_ctx_t ctx, mderi_basis_t basis, mderi_basis_t aux, const double *D_dev, double *J_dev,
+                       int nao, const mderi_opts *opts, void *stream);
+
+/*
  * Class batch of 3-centre integrals (ab|P) (Sec. 2: the 1-centre Hermite
  * expansion of Eqs. (E1rr)-(E1-aa); the paper writes them [P|ab]).
  *

@@ -1,0 +1,116 @@
+// df.hip -- the contractions of density-fitted Coulomb (the use of 3-centre
+// integrals that Sec. 1 motivates): with B the (ab|P) matrix (rows = AO pairs
+// of the canonical shell pairs, columns = auxiliary AOs, column-major) and M
+// the metric (P|Q),
+//   gamma_Q = sum_rows B[row][Q] w_row D[a_row][b_row]      (the fitted charge)
+//   c = M^{-1} gamma                                        (library Cholesky)
+//   J[a][b] = J[b][a] = sum_Q B[row][Q] c_Q                 (every pair row)
+// w_row = 2 for rows of a pair of two different shells (the pair stands for
+// both orders), 1 on a diagonal shell pair.
+#include <algorithm>
+
+#include "device_common.h"
+
+namespace mderi {
+
+namespace {
+
+constexpr int kDfThreads = 256;
+
+// dvec[row] = w_row D[a][b]
+__global__ void __launch_bounds__(kDfThreads) df_dvec_kernel(int nrow, const int2 *ab, const double *w,
+                                                            const double *D, int nao, double *dvec) {
+  const int r = blockIdx.x * kDfThreads + threadIdx.x;
+  if (r >= nrow) return;
+  const int2 x = ab[r];
+  dvec[r] = w[r] * D[(size_t)x.x * nao + x.y];
+}
+
+// gamma[col] = sum_row B[row + nrow col] dvec[row]: one workgroup per column,
+// consecutive rows across the workgroup's threads, tree reduction in LDS.
+__global__ void __launch_bounds__(kDfThreads) df_gamma_kernel(int nrow, const double *B, const double *dvec,
+                                                             double *gamma) {
+  __shared__ double part[kDfThreads];
+  const int col = blockIdx.x;
+  const double *Bc = B + (size_t)nrow * col;
+  double s = 0.0;
+  for (int r = threadIdx.x; r < nrow; r += kDfThreads) s = fma(Bc[r], dvec[r], s);
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = kDfThreads / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gamma[col] = part[0];
+}
+
+// J rows: jr = sum_col B[row + nrow col] c[col], then J[a][b] = J[b][a] = jr
+// from the rows with a >= b (a diagonal shell pair holds both (a, b) and
+// (b, a), equal up to rounding; the other pairs have a > b throughout), so
+// every element has one writer and J is exactly symmetric
+__global__ void __launch_bounds__(kDfThreads) df_j_kernel(int nrow, int ncol, const double *B, const double *c,
+                                                         const int2 *ab, double *J, int nao) {
+  const int r = blockIdx.x * kDfThreads + threadIdx.x;
+  if (r >= nrow) return;
+  const int2 x = ab[r];
+  if (x.x < x.y) return;
+  double s = 0.0;
+  for (int k = 0; k < ncol; ++k) s = fma(B[r + (size_t)nrow * k], c[k], s);
+  J[(size_t)x.x * nao + x.y] = s;
+  J[(size_t)x.y * nao + x.x] = s;
+}
+
+// One class batch of the metric, V[i + na (ma + Na (mc + Nc k))], into the
+// column-major metric M[row + n col] (row = first AO of shell A_i + ma, col =
+// first AO of shell C_k + mc).
+__global__ void __launch_bounds__(kDfThreads) df_scatter_kernel(int na, int Na, int nc, int Nc, const double *V,
+                                                               const int *shells_a, const int *shells_c,
+                                                               const int *ao_off, double *M, int n) {
+  const long total = (long)na * Na * Nc * nc;
+  for (long e = (long)blockIdx.x * kDfThreads + threadIdx.x; e < total; e += (long)gridDim.x * kDfThreads) {
+    long q = e;
+    const int i = (int)(q % na);
+    q /= na;
+    const int ma = (int)(q % Na);
+    q /= Na;
+    const int mc = (int)(q % Nc);
+    const int k = (int)(q / Nc);
+    M[(size_t)(ao_off[shells_a[i]] + ma) + (size_t)n * (ao_off[shells_c[k]] + mc)] = V[e];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_df_dvec(int nrow, const int2 *ab, const double *w, const double *D, int nao, double *dvec,
+                          hipStream_t s) {
+  if (nrow <= 0) return hipSuccess;
+  hipLaunchKernelGGL(df_dvec_kernel, dim3((nrow + kDfThreads - 1) / kDfThreads), dim3(kDfThreads), 0, s, nrow, ab, w,
+                     D, nao, dvec);
+  return hipGetLastError();
+}
+
+hipError_t launch_df_gamma(int nrow, int ncol, const double *B, const double *dvec, double *gamma, hipStream_t s) {
+  if (ncol <= 0) return hipSuccess;
+  hipLaunchKernelGGL(df_gamma_kernel, dim3(ncol), dim3(kDfThreads), 0, s, nrow, B, dvec, gamma);
+  return hipGetLastError();
+}
+
+hipError_t launch_df_j(int nrow, int ncol, const double *B, const double *c, const int2 *ab, double *J, int nao,
+                       hipStream_t s) {
+  if (nrow <= 0) return hipSuccess;
+  hipLaunchKernelGGL(df_j_kernel, dim3((nrow + kDfThreads - 1) / kDfThreads), dim3(kDfThreads), 0, s, nrow, ncol, B,
+                     c, ab, J, nao);
+  return hipGetLastError();
+}
+
+hipError_t launch_df_scatter(int na, int Na, int nc, int Nc, const double *V, const int *shells_a, const int *shells_c,
+                             const int *ao_off, double *M, int n, hipStream_t s) {
+  const long total = (long)na * Na * Nc * nc;
+  if (total <= 0) return hipSuccess;
+  const int grid = (int)std::min<long>(4096, (total + kDfThreads - 1) / kDfThreads);
+  hipLaunchKernelGGL(df_scatter_kernel, dim3(grid), dim3(kDfThreads), 0, s, na, Na, nc, Nc, V, shells_a, shells_c,
+                     ao_off, M, n);
+  return hipGetLastError();
+}
+
+}  // namespace mderi

@@ -15,6 +15,9 @@
 #include <numeric>
 #include <mutex>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -186,7 +189,8 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 // ---------------------------------------------------------------------------
 enum WsSlot {
   WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_ORDER,
-  WS_KORDER, WS_KTMP, WS_QALL, WS_PAIRS, WS_HS, WS_HEXP, WS_HROW, WS_GPART, WS_COUNT
+  WS_KORDER, WS_KTMP, WS_QALL, WS_PAIRS, WS_HS, WS_HEXP, WS_HROW, WS_GPART, WS_DFB, WS_DFM, WS_DFT, WS_DFV, WS_DFI,
+  WS_COUNT
 };
 
 struct TaskPlan;
@@ -228,6 +232,7 @@ struct mderi_ctx {
   std::vector<hipStream_t> side;     // side streams of concurrent task-list groups
   uint64_t next_serial = 1;
   char *scratch = nullptr;  // device address of `scratch` on this context's device
+  rocblas_handle blas = nullptr;  // library handle of the density-fitting solve (created on first use)
 };
 
 struct mderi_basis {
@@ -364,6 +369,7 @@ extern "C" void mderi_destroy(mderi_ctx_t c) {
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
   for (TaskPlan *p : c->plans) free_plan(p);
+  if (c->blas) (void)rocblas_destroy_handle(c->blas);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipStream_t x : c->side) (void)hipStreamDestroy(x);
   for (auto *v : {&c->ev_used, &c->ev_free})
@@ -2240,5 +2246,101 @@ extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, int pa
   job.gstride = 3 * natom;
   if ((st = run_kx(c, b, ps, tau, job, s))) return st;
   HIP_TRY(launch_sum_copies(3 * natom, kGradCopies, (const double *)d_gpart, grad, s, accumulate ? 1 : 0));
+  return MDERI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// density-fitted Coulomb matrix
+// ---------------------------------------------------------------------------
+extern "C" mderi_status mderi_dfj(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t aux, const double *D, double *J,
+                                  int nao, const mderi_opts *opts, void *stream) {
+  if (!c || !b || !aux) return fail(MDERI_EINVAL, "mderi_dfj: NULL context or basis");
+  if (b->ctx != c || aux->ctx != c) return fail(MDERI_EINVAL, "mderi_dfj: basis belongs to another context");
+  if (!D || !J) return fail(MDERI_EINVAL, "mderi_dfj: NULL density or output");
+  if (nao != b->nao) return fail(MDERI_EINVAL, "mderi_dfj: nao %d but the basis has %d AOs", nao, b->nao);
+  if (opts && opts->precision != 0) return fail(MDERI_EUNSUPPORTED, "mderi_dfj: precision %d", opts->precision);
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  // canonical shell pairs (i >= j) and their AO rows in the (ab|P) matrix
+  std::vector<int32_t> pairs;
+  std::vector<int2> ab;
+  std::vector<double> w;
+  for (int i = 0; i < b->nshell; ++i)
+    for (int j = 0; j <= i; ++j) {
+      pairs.push_back(i);
+      pairs.push_back(j);
+      const int Na = nsph(b->l[i]), Nb = nsph(b->l[j]);
+      for (int ma = 0; ma < Na; ++ma)
+        for (int mb = 0; mb < Nb; ++mb) {
+          ab.push_back(make_int2(b->ao_off[i] + ma, b->ao_off[j] + mb));
+          w.push_back(i == j ? 1.0 : 2.0);
+        }
+    }
+  const int nrow = (int)ab.size(), ncol = aux->nao, npair = (int)pairs.size() / 2;
+  std::vector<int32_t> auxidx(aux->nshell);
+  std::iota(auxidx.begin(), auxidx.end(), 0);
+  // auxiliary shells ordered by l: the class batches of the metric
+  std::vector<int32_t> byl;
+  std::vector<int> lstart(kLmax + 2, 0);
+  for (int l = 0; l <= kLmax; ++l) {
+    for (int k = 0; k < aux->nshell; ++k)
+      if (aux->l[k] == l) byl.push_back(k);
+    lstart[l + 1] = (int)byl.size();
+  }
+  size_t maxT = 1;
+  for (int la = 0; la <= kLmax; ++la)
+    for (int lc = 0; lc <= kLmax; ++lc)
+      maxT = std::max(maxT, (size_t)(lstart[la + 1] - lstart[la]) * nsph(la) * nsph(lc) * (lstart[lc + 1] - lstart[lc]));
+  mderi_status st;
+  void *dB, *dM, *dT, *dV, *dI;
+  const size_t o_w = sizeof(int2) * (size_t)nrow, o_byl = o_w + sizeof(double) * (size_t)nrow;
+  const size_t ibytes = o_byl + sizeof(int32_t) * byl.size();
+  if ((st = ws_get(c, WS_DFB, sizeof(double) * (size_t)nrow * ncol, &dB)) ||
+      (st = ws_get(c, WS_DFM, sizeof(double) * (size_t)ncol * ncol, &dM)) ||
+      (st = ws_get(c, WS_DFT, sizeof(double) * maxT, &dT)) ||
+      (st = ws_get(c, WS_DFV, sizeof(double) * ((size_t)nrow + ncol) + 64, &dV)) ||
+      (st = ws_get(c, WS_DFI, ibytes, &dI)))
+    return st;
+  double *dvec = (double *)dV, *gamma = dvec + nrow;
+  rocblas_int *info = (rocblas_int *)(gamma + ncol);
+  const int2 *d_ab = (const int2 *)dI;
+  const double *d_w = (const double *)((char *)dI + o_w);
+  const int32_t *d_byl = (const int32_t *)((char *)dI + o_byl);
+  if ((st = stage_begin(c, ibytes))) return st;
+  size_t used = 0;
+  if ((st = stage_copy(c, dI, ab.data(), sizeof(int2) * ab.size(), s, &used)) ||
+      (st = stage_copy(c, (char *)dI + o_w, w.data(), sizeof(double) * w.size(), s, &used)) ||
+      (st = stage_copy(c, (char *)dI + o_byl, byl.data(), sizeof(int32_t) * byl.size(), s, &used)))
+    return st;
+  if ((st = stage_end(c, s))) return st;
+  // (ab|P) for every canonical pair and auxiliary shell
+  mderi_opts o{};
+  if ((st = mderi_eri3_batch(c, b, aux, npair, pairs.data(), aux->nshell, auxidx.data(), (double *)dB,
+                             (size_t)nrow * ncol, &o, stream)))
+    return st;
+  // the metric (P|Q), class batch by class batch, scattered into M
+  for (int la = 0; la <= kLmax; ++la)
+    for (int lc = 0; lc <= kLmax; ++lc) {
+      const int na = lstart[la + 1] - lstart[la], nc = lstart[lc + 1] - lstart[lc];
+      if (!na || !nc) continue;
+      Side sa{aux, 0, 0, true, {}, {}}, sc{aux, 0, 0, true, {}, {}};
+      if ((st = expand_shells(aux, na, byl.data() + lstart[la], "aux", &sa.la, sa)) ||
+          (st = expand_shells(aux, nc, byl.data() + lstart[lc], "aux", &sc.la, sc)))
+        return st;
+      if ((st = run_class_batch(c, sa, sc, 0, (double *)dT, nullptr, nullptr, s))) return st;
+      HIP_TRY(launch_df_scatter(na, nsph(la), nc, nsph(lc), (const double *)dT, d_byl + lstart[la],
+                                d_byl + lstart[lc], aux->dev.ao_off, (double *)dM, ncol, s));
+    }
+  // fitted charge, Cholesky solve in the Coulomb metric, J
+  HIP_TRY(launch_df_dvec(nrow, d_ab, d_w, D, nao, dvec, s));
+  HIP_TRY(launch_df_gamma(nrow, ncol, (const double *)dB, dvec, gamma, s));
+  if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success)
+    return fail(MDERI_EDEVICE, "mderi_dfj: rocblas_create_handle failed");
+  if (rocblas_set_stream(c->blas, s) != rocblas_status_success ||
+      rocsolver_dpotrf(c->blas, rocblas_fill_lower, ncol, (double *)dM, ncol, info) != rocblas_status_success ||
+      rocsolver_dpotrs(c->blas, rocblas_fill_lower, ncol, 1, (double *)dM, ncol, gamma, ncol) !=
+          rocblas_status_success)
+    return fail(MDERI_EDEVICE, "mderi_dfj: the metric solve could not be enqueued");
+  HIP_TRY(launch_df_j(nrow, ncol, (const double *)dB, gamma, d_ab, J, nao, s));
   return MDERI_OK;
 }

@@ -80,6 +80,8 @@ def load_library():
     L.mderi_eri2.argtypes = [_vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
                              ctypes.POINTER(Opts), _vp]
     L.mderi_eri2.restype = ctypes.c_int
+    L.mderi_dfj.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _vp]
+    L.mderi_dfj.restype = ctypes.c_int
     L.mderi_kbuild.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _vp]
     L.mderi_kbuild.restype = ctypes.c_int
     L.mderi_eri3_batch.argtypes = [_vp, _vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
@@ -236,6 +238,21 @@ class Context:
                                          sc.ctypes.data_as(_ip), _vp(out.data_ptr()), out.numel(), ctypes.byref(opts),
                                          _stream_handle(stream)))
         return out[:n].view(len(sc), nc_, na_, len(sa)).permute(3, 2, 1, 0)
+
+    def dfj(self, basis: "Basis", aux: "Basis", D, out=None, stream=None):
+        """Density-fitted Coulomb matrix J_ab = sum_P (ab|P) [M^-1 gamma]_P with
+        gamma_Q = sum_cd (Q|cd) D_cd and the metric M = (P|Q) of `aux`; D torch
+        float64 [nao, nao] on the device, symmetric -> J (same shape)."""
+        import torch
+        nao = basis.nao()
+        assert D.dtype == torch.float64 and D.is_cuda and D.shape == (nao, nao)
+        D = D.contiguous()
+        if out is None:
+            out = torch.empty((nao, nao), dtype=torch.float64, device=D.device)
+        opts = Opts(0, 0.0)
+        _check(load_library().mderi_dfj(self._h, basis._h, aux._h, _vp(D.data_ptr()), _vp(out.data_ptr()), nao,
+                                        ctypes.byref(opts), _stream_handle(stream)))
+        return out
 
     def eri3_batch(self, basis: "Basis", aux: "Basis", pairs, auxidx, flags=0, out=None, stream=None):
         """(ab|P) over pairs and auxiliary shells of any classes in one task-list
