@@ -298,17 +298,18 @@ def high_l_aux(ctx, steps):
 
 def dfj_leg(ctx, natom=12):
     """Density-fitted J on the cluster recipe with an even-tempered fitting
-    set per atom (s4 p3 d3 f2 g2 h1, exponents geometric 0.1-60), against the
-    4-centre J of the quartet engine: time of one call (after a warm-up) and
-    the relative error of tr(D J)."""
+    set per atom (s12 p8 d6 f4 g3 h2, exponents geometric from 0.16 to twice
+    the largest primary exponent for s, narrower ranges for higher l), against
+    the 4-centre J of the quartet engine: time of one call (after a warm-up)
+    and the relative error of tr(D J)."""
     import torch
     from paper_2405_01834_amd import inputs
     sh, atom, pos, D = inputs.cluster(7, natom)
     b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, atom=atom)
     ls, ex, cen = [], [], []
     for p in pos:
-        for l, n in ((0, 4), (1, 3), (2, 3), (3, 2), (4, 2), (5, 1)):
-            for z in (np.geomspace(0.1, 60.0, n) if n > 1 else [np.sqrt(6.0)]):
+        for l, n, hi in ((0, 12, 4000.0), (1, 8, 500.0), (2, 6, 100.0), (3, 4, 40.0), (4, 3, 25.0), (5, 2, 10.0)):
+            for z in np.geomspace(0.16, hi, n):
                 ls.append(l)
                 ex.append(z)
                 cen.append(p)
@@ -328,8 +329,9 @@ def dfj_leg(ctx, natom=12):
         f"tr(DJ) relative error {abs(edf - e) / abs(e):.2e}")
     return {"ms": tdf * 1e3, "atoms": natom, "nao": b.nao(), "fitting_aos": a.nao(), "pair_rows": nrow,
             "triplets": int(sh.n * (sh.n + 1) // 2 * len(ls)), "energy_rel_err": abs(edf - e) / abs(e),
-            "workload": "cluster recipe, %d atoms; fitting set per atom s4 p3 d3 f2 g2 h1 (K=1, even-tempered "
-                        "0.1-60); one mderi_dfj call (all canonical pairs, no screening) after a warm-up" % natom}
+            "workload": "cluster recipe, %d atoms; fitting set per atom s12 p8 d6 f4 g3 h2 (K=1, even-tempered "
+                        "from 0.16 to 4000/500/100/40/25/10); one mderi_dfj call (all canonical pairs, no "
+                        "screening) after a warm-up" % natom}
 
 
 def count_quartets(ctx, basis, sh):
