@@ -364,6 +364,7 @@ def backward_forward(ctx, natom, warm_atoms=12):
     Dwd = torch.tensor(Dw, device="cuda")
     ctx.kbuild(bw, Dwd, tau=TAU)
     ctx.jkbuild(bw, Dwd, tau=TAU)
+    ctx.jkbuild(bw, Dwd, tau=TAU, deterministic=True)
     ctx.kbuild_grad(bw, Dwd, warm_atoms, tau=TAU)
     torch.cuda.synchronize()
     bw.close()
@@ -386,11 +387,15 @@ def backward_forward(ctx, natom, warm_atoms=12):
     log(f"  K build {tf:.2f} s ({nq / tf:.3e} quartets/s)")
     tb, g = timed(lambda: ctx.kbuild_grad(basis, Dd, natom, tau=TAU))
     log(f"  gradient {tb:.2f} s ({nq / tb:.3e} quartets/s), ratio {tb / tf:.2f}")
-    tjk, _ = timed(lambda: ctx.jkbuild(basis, Dd, tau=TAU))
+    tjk, (Ja, Ka) = timed(lambda: ctx.jkbuild(basis, Dd, tau=TAU))
     log(f"  J+K build {tjk:.2f} s")
+    tdet, (Jd, Kd) = timed(lambda: ctx.jkbuild(basis, Dd, tau=TAU, deterministic=True))
+    det_dev = max(float((Kd - Ka).abs().max() / Ka.abs().max()), float((Jd - Ja).abs().max() / Ja.abs().max()))
+    log(f"  J+K build, deterministic {tdet:.2f} s, max |d| / max |ref| from the atomic build {det_dev:.1e}")
     ctx.progress(False)
     gs = g.cpu().numpy()
     return {"ratio": tb / tf, "forward_ms": tf * 1e3, "backward_ms": tb * 1e3, "jk_build_ms": tjk * 1e3,
+            "jk_build_deterministic_ms": tdet * 1e3, "deterministic_vs_atomic": det_dev,
             "atoms": natom, "shells": int(sh.n), "nao": basis.nao(), "significant_pairs": npair,
             "kbuild_quartets": nq, "ordered_quartets": nord, "kbuild_quartets_per_s": nq / tf,
             "gradient_quartets_per_s": nq / tb,

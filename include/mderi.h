@@ -67,7 +67,8 @@ typedef struct {
   int split_slices;   /* MDERI_SPLIT_BF16: 7-bit slices per operand, 5..7 (0 = default 6) */
   int tile_variant;   /* mderi_eri4, FP64: 0 = the planned (or tuned) work split; v > 0 = the v-th of
                          the splits mderi_eri4_tile_variants counts for the batch */
-  int reserved;
+  int deterministic;  /* mderi_jkbuild / mderi_kbuild: 1 = bitwise repeatable J and K (fixed-point
+                         integer accumulation, see mderi_jkbuild); 0 = FP64 atomics (default) */
 } mderi_opts;
 
 #define MDERI_FLAG_GRAPH 1    /* capture the call's launches in a hipGraph, replay it on identical calls */
@@ -270,8 +271,18 @@ mderi_status mderi_schwarz(mderi_ctx_t ctx, mderi_basis_t basis, int npair, cons
  * class by Q on the host (so the admissible partners of every pair are a
  * prefix of the sorted list); everything after that is enqueued
  * asynchronously.  Work space grows with the number of significant pairs
- * (pair data of every class in both roles).  Sums of the images use FP64
- * atomics, so the last bits of J and K vary from run to run.
+ * (pair data of every class in both roles).  By default the sums of the
+ * images use FP64 atomics, so the last bits of J and K vary from run to run.
+ * With opts->deterministic = 1 every image is scaled by 2^e and added as a
+ * fixed-point number with 32 fraction bits, held in two 64-bit integers
+ * (the floor and the rounded fraction), by integer atomics, whose sums do
+ * not depend on the order of the adds; J and K are then the same bits on
+ * every run with the same inputs on the same device.  e = 62 -
+ * ceil(log2 B), B = 4 Q_max^2 sum|D| (computed on the device), so no sum
+ * of magnitudes reaching one element can overflow; each image is rounded
+ * to B 2^-95, far below FP64 rounding of J and K themselves.  This mode
+ * takes 16 bytes per element of each matrix built as work space and two
+ * integer atomics per image instead of one.
  */
 mderi_status mderi_jkbuild(mderi_ctx_t ctx, mderi_basis_t basis, const double *D_dev, double *J_dev, double *K_dev,
                            int nao, double *energy_dev, const mderi_opts *opts, void *stream);
@@ -331,7 +342,9 @@ mderi_status mderi_progress(mderi_ctx_t ctx, int enable);
  * overwrites it, 1 adds to it.  The exchange energy of mderi_jkbuild,
  * tr(D K[D]), is pattern MDERI_EXCHANGE with Wl = Wr = D and scale 1; its
  * Coulomb energy tr(D J[D]) is MDERI_COULOMB with Wl = Wr = D.
- * Synchronisation and screening as for mderi_jkbuild.
+ * Synchronisation and screening as for mderi_jkbuild.  The gradient sums
+ * use FP64 atomics (last bits vary from run to run); opts->deterministic = 1
+ * is refused with MDERI_EUNSUPPORTED.
  */
 mderi_status mderi_kbuild_grad(mderi_ctx_t ctx, mderi_basis_t basis, int pattern, const double *Wl_dev,
                                const double *Wr_dev, int nao, double scale, double *grad_dev, int natom, int accumulate,

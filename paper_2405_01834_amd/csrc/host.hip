@@ -1145,6 +1145,8 @@ mderi_status check_density(const char *fn, mderi_ctx *c, mderi_basis *b, const d
   if (!D) return fail(MDERI_EINVAL, "%s: NULL density", fn);
   if (nao != b->nao) return fail(MDERI_EINVAL, "%s: nao=%d but the basis has %d AOs", fn, nao, b->nao);
   if (opts && opts->precision != 0) return fail(MDERI_EUNSUPPORTED, "%s: precision %d", fn, opts->precision);
+  if (opts && opts->deterministic != 0 && opts->deterministic != 1)
+    return fail(MDERI_EINVAL, "%s: deterministic %d (0 or 1)", fn, opts->deterministic);
   return MDERI_OK;
 }
 
@@ -1713,6 +1715,7 @@ struct KxJob {
   // digest mode
   const double *dm = nullptr;
   double *kx = nullptr, *jx = nullptr;
+  const double *fscale = nullptr;  // deterministic digest: kx / jx hold fixed-point pairs scaled by *fscale
   // gradient mode
   const double *wl = nullptr, *wr = nullptr;
   int pattern = 0;
@@ -2070,6 +2073,8 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
     ar.dm = job.dm;
     ar.kx = job.kx;
     ar.jx = job.jx;
+    ar.fixed = job.fscale ? 1 : 0;
+    ar.fscale = job.fscale;
     ar.wl = job.wl;
     ar.wr = job.wr;
     ar.pattern = job.pattern;
@@ -2174,21 +2179,36 @@ extern "C" mderi_status mderi_jkbuild(mderi_ctx_t c, mderi_basis_t b, const doub
   PairSets ps;
   if ((st = select_pairs(c, b, tau, s, ps))) return st;
   const size_t nn = (size_t)nao * nao;
+  // deterministic: 2 64-bit words per element and the scale; else one double
+  const bool det = opts && opts->deterministic;
+  const size_t per = det ? 2 * nn : nn, nmat = (J ? 1 : 0) + (K ? 1 : 0);
+  const size_t nwork = std::max(dot2_work_doubles(), det_scale_work_doubles()) + 1;
   void *d_t;
-  if ((st = ws_get(c, WS_KTMP, sizeof(double) * (nn * ((J ? 1 : 0) + (K ? 1 : 0)) + dot2_work_doubles()), &d_t)))
-    return st;
+  if ((st = ws_get(c, WS_KTMP, sizeof(double) * (per * nmat + nwork), &d_t))) return st;
   double *kt = K ? (double *)d_t : nullptr;
-  double *jt = J ? (double *)d_t + (K ? nn : 0) : nullptr;
-  double *work = (double *)d_t + nn * ((J ? 1 : 0) + (K ? 1 : 0));
-  if (kt) HIP_TRY(launch_zero(nn, kt, s));
-  if (jt) HIP_TRY(launch_zero(nn, jt, s));
+  double *jt = J ? (double *)d_t + (K ? per : 0) : nullptr;
+  double *work = (double *)d_t + per * nmat;
+  double *scale = work + nwork - 1;
+  if (kt) HIP_TRY(det ? launch_zero_u64(per, (unsigned long long *)kt, s) : launch_zero(nn, kt, s));
+  if (jt) HIP_TRY(det ? launch_zero_u64(per, (unsigned long long *)jt, s) : launch_zero(nn, jt, s));
+  if (det) {
+    double qmax = 0.0;
+    for (double q : ps.q) qmax = std::max(qmax, q);
+    HIP_TRY(launch_det_scale(nn, D, qmax, work, scale, s));
+  }
   KxJob job;
   job.dm = D;
   job.kx = kt;
   job.jx = jt;
+  job.fscale = det ? scale : nullptr;
   if ((st = run_kx(c, b, ps, tau, job, s))) return st;
-  if (K) HIP_TRY(launch_symmetrize(nao, kt, K, s));
-  if (J) HIP_TRY(launch_symmetrize(nao, jt, J, s));
+  if (det) {
+    if (K) HIP_TRY(launch_symmetrize_fixed(nao, (const unsigned long long *)kt, scale, K, s));
+    if (J) HIP_TRY(launch_symmetrize_fixed(nao, (const unsigned long long *)jt, scale, J, s));
+  } else {
+    if (K) HIP_TRY(launch_symmetrize(nao, kt, K, s));
+    if (J) HIP_TRY(launch_symmetrize(nao, jt, J, s));
+  }
   if (energy) HIP_TRY(launch_dot2(nn, D, J, K, work, energy, s));
   return MDERI_OK;
 }
@@ -2213,6 +2233,8 @@ extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, int pa
                                           int accumulate, const mderi_opts *opts, void *stream) {
   mderi_status st;
   if ((st = check_density("mderi_kbuild_grad", c, b, Wl, nao, opts))) return st;
+  if (opts && opts->deterministic)
+    return fail(MDERI_EUNSUPPORTED, "mderi_kbuild_grad: the deterministic mode covers the J and K builds only");
   if (!Wr) return fail(MDERI_EINVAL, "mderi_kbuild_grad: NULL Wr");
   if (pattern != MDERI_EXCHANGE && pattern != MDERI_COULOMB)
     return fail(MDERI_EINVAL, "mderi_kbuild_grad: pattern %d", pattern);

@@ -191,6 +191,10 @@ struct KxArgs {
   // images (either may be null); K = K' + K'^T, J = J' + J'^T afterwards
   const double *dm;       // density D [nao][nao] (symmetric)
   double *kx, *jx;
+  // deterministic digest: kx / jx then point at [nao][nao][2] 64-bit integer
+  // pairs (floor, fraction 2^32) of the images times *fscale
+  int fixed;
+  const double *fscale;
   // gradient mode: E = sum W_abcd (ab|cd) with W = Wl_ac Wr_bd (pattern 0) or
   // Wl_ab Wr_cd (pattern 1), times scale; dE/dR of the A centres added to
   // grad copy (workgroup % gcopies) at [atom][xyz]
@@ -223,6 +227,16 @@ hipError_t launch_eri4(const Eri4Args &a, hipStream_t s);
 hipError_t launch_schwarz_reduce(int npair, int Nab, const double *D, const int *idx, double *Q, hipStream_t s);
 // K = K' + K'^T (in place would race, so out != in), n x n.
 hipError_t launch_symmetrize(int n, const double *in, double *out, hipStream_t s);
+// Deterministic accumulation (det.hip): scale[0] = 2^(62 - ceil(log2 B)),
+// B = 4 qmax^2 sum_e |D[e]| (1 when B is 0 or not finite), summed in a fixed
+// order over n elements; work holds det_scale_work_doubles().
+size_t det_scale_work_doubles();
+hipError_t launch_det_scale(size_t n, const double *D, double qmax, double *work, double *scale, hipStream_t s);
+// out = K' + K'^T with K' the fixed-point pairs of in[n][n][2] divided by *scale.
+hipError_t launch_symmetrize_fixed(int n, const unsigned long long *in, const double *scale, double *out,
+                                   hipStream_t s);
+// x[0..n) = 0 for 64-bit integers.
+hipError_t launch_zero_u64(size_t n, unsigned long long *x, hipStream_t s);
 // x[0..n) = 0 with a plain kernel (no memset node, capture-safe).
 hipError_t launch_zero(size_t n, double *x, hipStream_t s);
 // out[i] = sum_c in[c n + i] for i < n, c < copies (added to out[i] when accumulate).

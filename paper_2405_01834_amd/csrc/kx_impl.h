@@ -254,6 +254,21 @@ __device__ __forceinline__ void digest_tile(const KxArgs &g, const KxBlock &a, i
   }
 }
 
+// Adds v to element e of a K' / J' matrix: an FP64 atomic, or in the
+// deterministic mode v * sc as the fixed-point pair (floor, rounded fraction
+// 2^32) by two 64-bit integer atomics (pairs that are zero are skipped).
+__device__ __forceinline__ void image_add(double *m, size_t e, double v, bool fixed, double sc) {
+  if (!fixed) {
+    atomicAdd(&m[e], v);
+    return;
+  }
+  const double y = v * sc, h = floor(y);
+  const long long hi = (long long)h, lo = (long long)rint((y - h) * 0x1p32);
+  unsigned long long *p = (unsigned long long *)m + 2 * e;
+  if (hi) atomicAdd(p, (unsigned long long)hi);
+  if (lo) atomicAdd(p + 1, (unsigned long long)lo);
+}
+
 // The images of one quartet into K' / J' (one global atomic per element).
 __device__ __forceinline__ void digest_flush(const KxArgs &g, const KxBlock &a, int i, int k, int si, int sj, int sk,
                                              int sl, const double *img, int lane) {
@@ -262,13 +277,15 @@ __device__ __forceinline__ void digest_flush(const KxArgs &g, const KxBlock &a, 
   const size_t n = (size_t)g.nao;
   const bool same_pair = a.same && i == k;
   const int ko = g.kx ? nab * ncd : 0;
+  const bool fixed = g.fixed != 0;
+  const double sc = fixed ? g.fscale[0] : 1.0;
   if (g.kx) {
     const int neq = (si == sj) + (sk == sl) + (same_pair ? 1 : 0);
     const double w = neq == 0 ? 1.0 : neq == 1 ? 0.5 : neq == 2 ? 0.25 : 0.125;
     for (int o = lane; o < nab * ncd; o += 64) {
       const int r = udiv(o, a.inv_ncd), q = o - r * ncd;
       const int row = r < na ? oi + r : oj + (r - na), col = q < nc ? ok + q : ol + (q - nc);
-      atomicAdd(&g.kx[(size_t)row * n + col], w * img[o]);
+      image_add(g.kx, (size_t)row * n + col, w * img[o], fixed, sc);
     }
   }
   if (g.jx) {
@@ -276,12 +293,12 @@ __device__ __forceinline__ void digest_flush(const KxArgs &g, const KxBlock &a, 
     const double wk = ((si != sj) ? 2.0 : 1.0) * ((sk == sl) ? 0.5 : 1.0);
     for (int ab = lane; ab < NA; ab += 64) {
       const int x = udiv(ab, a.inv_nb);
-      atomicAdd(&g.jx[(size_t)(oi + x) * n + oj + (ab - x * nb)], wb * img[ko + ab]);
+      image_add(g.jx, (size_t)(oi + x) * n + oj + (ab - x * nb), wb * img[ko + ab], fixed, sc);
     }
     if (!same_pair)
       for (int cd = lane; cd < NB; cd += 64) {
         const int x = udiv(cd, a.inv_nd);
-        atomicAdd(&g.jx[(size_t)(ok + x) * n + ol + (cd - x * nd)], wk * img[ko + NA + cd]);
+        image_add(g.jx, (size_t)(ok + x) * n + ol + (cd - x * nd), wk * img[ko + NA + cd], fixed, sc);
       }
   }
 }

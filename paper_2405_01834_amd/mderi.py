@@ -27,7 +27,7 @@ def lib_path() -> str:
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("schwarz_tau", ctypes.c_double), ("flags", ctypes.c_int),
-                ("split_slices", ctypes.c_int), ("tile_variant", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("split_slices", ctypes.c_int), ("tile_variant", ctypes.c_int), ("deterministic", ctypes.c_int)]
 
 
 FLAG_GRAPH = 1
@@ -279,10 +279,12 @@ class Context:
                                                out.numel(), ctypes.byref(opts), _stream_handle(stream)))
         return out[:nrow * ncol].view(ncol, nrow).t()
 
-    def jkbuild(self, basis: "Basis", D, want_j=True, want_k=True, tau=1e-12, energies=False, stream=None):
+    def jkbuild(self, basis: "Basis", D, want_j=True, want_k=True, tau=1e-12, energies=False, stream=None,
+                deterministic=False):
         """Coulomb J_ab = sum_cd (ab|cd) D_cd and exchange K_ac = sum_bd (ab|cd) D_bd
         of a symmetric density D (torch float64 [nao, nao] on the device) ->
-        (J or None, K or None[, energies = float64 tensor [tr(DJ), tr(DK)]])."""
+        (J or None, K or None[, energies = float64 tensor [tr(DJ), tr(DK)]]).
+        deterministic: fixed-point integer accumulation, the same bits on every run."""
         import torch
         nao = basis.nao()
         assert D.dtype == torch.float64 and D.is_cuda and D.shape == (nao, nao)
@@ -290,22 +292,23 @@ class Context:
         J = torch.empty((nao, nao), dtype=torch.float64, device=D.device) if want_j else None
         K = torch.empty((nao, nao), dtype=torch.float64, device=D.device) if want_k else None
         E = torch.empty(2, dtype=torch.float64, device=D.device) if energies else None
-        opts = Opts(0, float(tau))
+        opts = Opts(0, float(tau), 0, 0, 0, int(bool(deterministic)))
         ptr = lambda t: None if t is None else _vp(t.data_ptr())  # noqa: E731
         _check(load_library().mderi_jkbuild(self._h, basis._h, _vp(D.data_ptr()), ptr(J), ptr(K), nao, ptr(E),
                                             ctypes.byref(opts), _stream_handle(stream)))
         return (J, K, E) if energies else (J, K)
 
-    def kbuild(self, basis: "Basis", D, tau=1e-12, out=None, stream=None):
+    def kbuild(self, basis: "Basis", D, tau=1e-12, out=None, stream=None, deterministic=False):
         """Exchange matrix K_ac = sum_bd (ab|cd) D_bd for a symmetric density D
-        (torch float64 [nao, nao] on the device) -> K (same shape)."""
+        (torch float64 [nao, nao] on the device) -> K (same shape).
+        deterministic: fixed-point integer accumulation, the same bits on every run."""
         import torch
         nao = basis.nao()
         assert D.dtype == torch.float64 and D.is_cuda and D.shape == (nao, nao)
         D = D.contiguous()
         if out is None:
             out = torch.empty((nao, nao), dtype=torch.float64, device=D.device)
-        opts = Opts(0, float(tau))
+        opts = Opts(0, float(tau), 0, 0, 0, int(bool(deterministic)))
         _check(load_library().mderi_kbuild(self._h, basis._h, _vp(D.data_ptr()), _vp(out.data_ptr()), nao,
                                            ctypes.byref(opts), _stream_handle(stream)))
         return out
