@@ -88,10 +88,11 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(batches, outs, wall_per_class=2.5):
+def cpu_baseline(batches, outs, wall_per_class=2.5, pp_batch=None):
     """The oracle on a bounded sample of every class batch (all host threads,
     then one thread on a smaller sample); the sample's integrals are also
-    compared element by element with the GPU output of the timed step."""
+    compared element by element with the GPU output of the timed step.  The
+    [pp|pp] 512-quartet batch is computed whole and compared the same way."""
     import oracle
     nthr = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
     total_eris, total_time, total_time1, parts = 0.0, 0.0, 0.0, []
@@ -129,7 +130,23 @@ def cpu_baseline(batches, outs, wall_per_class=2.5):
         log(f"cpu oracle [{NAMES[l]}|{NAMES[l]}] K={K}: {nb * nk} quartets in {dt:.2f}s -> {rate:.1f} quartets/s "
             f"({rate1:.1f} on one thread); parity vs GPU: {int(np.sum(err > 1e-14 + 1e-12 * np.abs(ref)))} of "
             f"{ref.size} outside 1e-12/1e-14")
-    return {"value": total_eris / total_time, "unit": "ERI/s", "cores": nthr, "kind": "oracle",
+    pp = None
+    if pp_batch is not None:
+        sh, bra, ket, out = pp_batch
+        ob = oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, 1)
+        t = time.perf_counter()
+        ref = oracle.eri4(ob, bra, ket, nthreads=nthr)
+        dt = time.perf_counter() - t
+        got = out.view(len(ket), 9, 9, len(bra)).permute(3, 2, 1, 0).cpu().numpy()
+        err = np.abs(got - ref)
+        nbad = int(np.sum(err > 1e-14 + 1e-12 * np.abs(ref)))
+        bad += nbad
+        checked += ref.size
+        worst = max(worst, float(np.max(err / (1e-14 + 1e-12 * np.abs(ref)))))
+        pp = {"ms": dt * 1e3, "eris_per_s": ref.size / dt, "elements": ref.size, "outside_tolerance": nbad}
+        log(f"cpu oracle [pp|pp] K=1: {len(bra) * len(ket)} quartets in {dt * 1e3:.1f} ms; parity vs GPU: {nbad} of "
+            f"{ref.size} outside 1e-12/1e-14")
+    return {"value": total_eris / total_time, "unit": "ERI/s", "cores": nthr, "kind": "oracle", "pp_small": pp,
             "single_core_value": total_eris / total_time1, "cpu_model": cpu_model(),
             "sample": "oracle FP64 on the first " + ", ".join(parts) +
                       " quartets of each class batch (single core: about a tenth of each); full-step time "
@@ -352,6 +369,47 @@ def count_quartets(ctx, basis, sh):
     return (ordered + diag) // 2, ordered, int(keep.sum())
 
 
+def pp_small(ctx, reps=200):
+    """[pp|pp] K=1, 512 shell quartets (16 bra x 32 ket pairs, centres in a
+    10-bohr cube, exponents log-U[0.1,100], no screening): the launch-bound
+    end of the class table.  One call = the pair data of both sides (one
+    launch each) + the fused kernel; the stream time per call from events
+    around `reps` back-to-back calls, the fused kernel's own time from the
+    library's events, the host time per call from the wall clock."""
+    import torch
+    from paper_2405_01834_amd import inputs, model
+    sh, bra, ket = inputs.pp_quartets(0)
+    basis = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    out = torch.empty(len(bra) * len(ket) * 81, dtype=torch.float64, device="cuda")
+    for _ in range(5):
+        ctx.eri4(basis, bra, ket, out=out)
+    torch.cuda.synchronize()
+    ctx.kernel_times()
+    ctx.kernel_timing(True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t = time.perf_counter()
+    start.record()
+    for _ in range(reps):
+        ctx.eri4(basis, bra, ket, out=out)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / reps
+    ctx.kernel_timing(False)
+    kern = float(ctx.kernel_times().mean())
+    ms = start.elapsed_time(stop) / reps
+    nq = len(bra) * len(ket)
+    eris = nq * model.eri4_outputs(1, 1, 1, 1)
+    flops = nq * model.eri4_flops(1, 1, 1, 1, 1, 1)
+    log(f"[pp|pp] K=1, {nq} quartets: {ms * 1e3:.1f} us per call on the stream ({kern * 1e3:.1f} us fused kernel, "
+        f"{wall * 1e6:.1f} us host), {eris / (ms * 1e-3):.3e} ERI/s")
+    return {"quartets": nq, "ms": ms, "kernel_ms": kern, "host_ms_per_call": wall * 1e3,
+            "eris_per_s": eris / (ms * 1e-3), "kernel_eris_per_s": eris / (kern * 1e-3),
+            "model_tflops": flops / (ms * 1e-3) / 1e12,
+            "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / model.FP64_PEAK_TFLOPS,
+            "workload": "[pp|pp] K=1, 16 x 32 pairs (512 quartets), 10-bohr cube, exponents log-U[0.1,100], "
+                        "seed 0, %d back-to-back calls" % reps}, (sh, bra, ket, out)
+
+
 def backward_forward(ctx, natom, warm_atoms=12):
     """Exchange-gradient time over K-build time on the synthetic cluster
     (inputs.cluster): both calls first run on a small cluster of the same
@@ -543,6 +601,7 @@ def main():
                      "traffic": measured_traffic(f"eri4_kernel {dom}"), "traffic_unit": "B"},
         "wall_s": wall,
     }
+    rec["pp_small"], pp_batch = pp_small(ctx)
     if not args.no_split:
         rec["mixed_precision"] = mixed_precision(ctx, max(args.steps, 2))
     if args.eri3 != "off":
@@ -553,7 +612,7 @@ def main():
     if args.cluster_atoms > 0:
         rec["backward_forward"] = backward_forward(ctx, args.cluster_atoms)
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(batches, outs, args.cpu_wall)
+        rec["cpu_baseline"] = cpu_baseline(batches, outs, args.cpu_wall, pp_batch)
     print(json.dumps(rec), flush=True)
 
 

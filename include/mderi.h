@@ -321,6 +321,22 @@ mderi_status mderi_kernel_times(mderi_ctx_t ctx, double *ms_host, int cap, int *
  */
 mderi_status mderi_progress(mderi_ctx_t ctx, int enable);
 
+/*
+ * Caps the device workspace the context may hold (the sum over its work
+ * slots: pair data, intermediate matrices, partial results; not the
+ * constant tables, the pinned staging buffer, the cached task-list plans of
+ * mderi_eri3_batch or the library handle of the density-fitting solve) at
+ * `bytes`; 0 removes the cap.  The call synchronises the device
+ * and releases the workspace held so far.  A later call that would grow it
+ * past the cap returns MDERI_ENOMEM, exactly as when hipMalloc fails; as
+ * with a failed hipMalloc, work of that call enqueued before the failing
+ * request (Schwarz factors, pair data) may already be on the stream, and
+ * its outputs are then undefined.  The context stays usable: after the cap
+ * is raised or removed, the same call succeeds.  Serves callers that share
+ * the GPU with other memory users, and tests of the ENOMEM paths.
+ */
+mderi_status mderi_set_workspace_limit(mderi_ctx_t ctx, size_t bytes);
+
 /* Weight patterns of mderi_kbuild_grad. */
 #define MDERI_EXCHANGE 0 /* W_abcd = Wl_ac Wr_bd: E = tr(Wl^T K[Wr]) */
 #define MDERI_COULOMB 1  /* W_abcd = Wl_ab Wr_cd: E = tr(Wl^T J[Wr]) */

@@ -72,5 +72,46 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+HOSTSAN = os.path.join(HERE, "hostsan")
+CLANGXX = "/opt/rocm/llvm/bin/clang++"
+
+
+def build_hostsan(verbose: bool = False) -> str:
+    """The host-sanitizer variant: host.hip (all host logic of the library:
+    validation, pair selection, plans, workspace) compiled with
+    AddressSanitizer and UndefinedBehaviorSanitizer on its host side only,
+    linked with the regular objects of the other sources (their host code is
+    kernel launchers) into hostsan/libmderi_hostsan.so, and the ABI driver
+    tests/native/abi_sanitizer.cpp built against it with both sanitizers.
+    Needs the regular objects (build() first); returns the driver's path."""
+    os.makedirs(HOSTSAN, exist_ok=True)
+    host_src = os.path.join(CSRC, "host.hip")
+    obj = os.path.join(BUILD, "host.hip.hostsan.o")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all", "-g"]
+    r = subprocess.run([HIPCC, *FLAGS, *san, "-c", host_src, "-o", obj], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for the host-sanitizer object:\n" + r.stderr)
+    others = [os.path.join(BUILD, os.path.basename(x) + ".o") for x in sources() if x != host_src]
+    lib = os.path.join(HOSTSAN, "libmderi_hostsan.so")
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", lib, obj, *others, "-L/opt/rocm/lib",
+           "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("host-sanitizer link failed:\n" + r.stderr)
+    exe = os.path.join(HOSTSAN, "abi_sanitizer")
+    driver_flags = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+    cmd = [CLANGXX, "-std=c++17", "-O1", "-g", *driver_flags, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "native", "abi_sanitizer.cpp"),
+           "-o", exe, "-L", HOSTSAN, "-lmderi_hostsan", "-L/opt/rocm/lib", "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN", "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("driver build failed:\n" + r.stderr)
+    if verbose and r.stderr.strip():
+        print(r.stderr, file=sys.stderr)
+    return exe
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

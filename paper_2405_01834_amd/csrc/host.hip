@@ -214,6 +214,7 @@ struct mderi_ctx {
   Tables tab;
   void *ws[WS_COUNT] = {};
   size_t ws_cap[WS_COUNT] = {};
+  size_t ws_limit = 0;  // cap on the sum of ws_cap (0 = none)
   // pinned staging for per-call host->device uploads, guarded by an event
   char *stage = nullptr;
   size_t stage_cap = 0;
@@ -246,13 +247,27 @@ struct mderi_basis {
 static mderi_status ws_get(mderi_ctx *c, int slot, size_t bytes, void **out) {
   if (bytes == 0) bytes = 16;
   if (c->ws_cap[slot] < bytes) {
+    if (c->ws_limit) {
+      size_t others = 0;
+      for (int i = 0; i < WS_COUNT; ++i)
+        if (i != slot) others += c->ws_cap[i];
+      if (others + bytes > c->ws_limit)
+        return fail(MDERI_ENOMEM, "device workspace of %zu bytes would exceed the limit of %zu bytes (%zu held)",
+                    bytes, c->ws_limit, others);
+    }
     if (c->ws[slot]) {
       HIP_TRY(hipDeviceSynchronize());
       HIP_TRY(hipFree(c->ws[slot]));
       c->ws[slot] = nullptr;
       c->ws_cap[slot] = 0;
     }
-    const size_t cap = bytes + bytes / 4;
+    size_t cap = bytes + bytes / 4;
+    if (c->ws_limit) {
+      size_t others = 0;
+      for (int i = 0; i < WS_COUNT; ++i)
+        if (i != slot) others += c->ws_cap[i];
+      cap = std::min(cap, c->ws_limit - others);
+    }
     if (hipMalloc(&c->ws[slot], cap) != hipSuccess) {
       (void)hipGetLastError();
       return fail(MDERI_ENOMEM, "device workspace of %zu bytes could not be allocated", cap);
@@ -383,6 +398,19 @@ extern "C" void mderi_destroy(mderi_ctx_t c) {
 extern "C" mderi_status mderi_kernel_timing(mderi_ctx_t c, int enable) {
   if (!c) return fail(MDERI_EINVAL, "mderi_kernel_timing: NULL context");
   c->timing = enable != 0;
+  return MDERI_OK;
+}
+
+extern "C" mderi_status mderi_set_workspace_limit(mderi_ctx_t c, size_t bytes) {
+  if (!c) return fail(MDERI_EINVAL, "mderi_set_workspace_limit: NULL context");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipDeviceSynchronize());
+  for (int i = 0; i < WS_COUNT; ++i) {
+    if (c->ws[i]) HIP_TRY(hipFree(c->ws[i]));
+    c->ws[i] = nullptr;
+    c->ws_cap[i] = 0;
+  }
+  c->ws_limit = bytes;
   return MDERI_OK;
 }
 

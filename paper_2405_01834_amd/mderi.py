@@ -91,6 +91,8 @@ def load_library():
     L.mderi_kernel_timing.restype = ctypes.c_int
     L.mderi_progress.argtypes = [_vp, ctypes.c_int]
     L.mderi_progress.restype = ctypes.c_int
+    L.mderi_set_workspace_limit.argtypes = [_vp, ctypes.c_size_t]
+    L.mderi_set_workspace_limit.restype = ctypes.c_int
     L.mderi_kernel_times.argtypes = [_vp, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     L.mderi_kernel_times.restype = ctypes.c_int
     L.mderi_jkbuild.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(Opts), _vp]
@@ -320,6 +322,10 @@ class Context:
     def progress(self, enable: bool):
         """Prints a line to stderr as each launch group of the J/K builds and the gradient finishes."""
         _check(load_library().mderi_progress(self._h, int(bool(enable))))
+
+    def set_workspace_limit(self, nbytes: int):
+        """Caps the context's device workspace (0 = no cap); releases what it holds."""
+        _check(load_library().mderi_set_workspace_limit(self._h, int(nbytes)))
 
     def kernel_times(self):
         """Durations (ms) of the fused-kernel launches recorded since the last read."""

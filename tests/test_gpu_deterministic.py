@@ -8,7 +8,9 @@ on the order in which the waves add them):
     (the fixed-point rounding, B 2^-95 per image, is far below that);
   * on a small molecule they match the oracle's brute force at 1e-12;
   * a density of zeros gives zeros; the gradient refuses the mode and values
-    other than 0 and 1 are rejected."""
+    other than 0 and 1 are rejected.
+Also the workspace cap (mderi_set_workspace_limit), the way to make the
+library's allocation failures (MDERI_ENOMEM) happen on purpose."""
 import ctypes
 
 import numpy as np
@@ -99,3 +101,36 @@ def test_deterministic_refused_where_unsupported(ctx, cluster):
         _check(lib.mderi_kbuild_grad(ctx._h, b._h, 0, vp(D.data_ptr()), vp(D.data_ptr()), nao,
                                      ctypes.c_double(1.0), vp(g.data_ptr()), 12, 0,
                                      ctypes.byref(Opts(0, TAU, 0, 0, 0, 1)), None))
+
+
+def test_workspace_limit_gives_enomem_and_recovers(need_gpu):
+    """A workspace cap below what a call needs: MDERI_ENOMEM (status -2) from
+    the K build, the 4-centre batch and the gradient; after the cap is lifted
+    the same context gives the results of an uncapped one."""
+    import torch
+    from paper_2405_01834_amd import Context
+    from paper_2405_01834_amd.mderi import MderiError
+    rng = np.random.default_rng(43)
+    sh = inputs.random_shells(rng, [0, 1, 2, 1, 0], [2, 1, 1, 2, 1], 3.0, 0.1, 30.0)
+    nao = int(np.sum(2 * sh.l + 1))
+    C = rng.normal(size=(nao, 3))
+    D = torch.tensor(C @ C.T, device="cuda")
+    ref_ctx = Context(0)
+    rb = ref_ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    K_ref = ref_ctx.kbuild(rb, D, tau=TAU)
+    V_ref = ref_ctx.eri4(rb, [[2, 2], [2, 2]], [[3, 1]])
+    ctx = Context(0)
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    ctx.set_workspace_limit(256)
+    for call in (lambda: ctx.kbuild(b, D, tau=TAU), lambda: ctx.eri4(b, [[2, 2], [2, 2]], [[3, 1]]),
+                 lambda: ctx.kbuild_grad(b, D, len(sh.l), tau=TAU)):
+        with pytest.raises(MderiError) as e:
+            call()
+        assert e.value.status == -2 and "limit" in str(e.value)
+    torch.cuda.synchronize()
+    ctx.set_workspace_limit(0)
+    K = ctx.kbuild(b, D, tau=TAU)
+    V = ctx.eri4(b, [[2, 2], [2, 2]], [[3, 1]])
+    torch.cuda.synchronize()
+    assert float((K - K_ref).abs().max()) <= 1e-13 * float(K_ref.abs().max())
+    assert torch.equal(V, V_ref)
