@@ -337,6 +337,23 @@ mderi_status mderi_progress(mderi_ctx_t ctx, int enable);
  */
 mderi_status mderi_set_workspace_limit(mderi_ctx_t ctx, size_t bytes);
 
+/*
+ * Persistent autotune cache.  mderi_tune_save writes the tile choices the
+ * context's autotuner has made (MDERI_FLAG_AUTOTUNE of mderi_eri4,
+ * mderi_eri2 and mderi_eri3_batch, one per class signature: l of the four
+ * centres and the largest primitive-pair counts of the two sides) to the
+ * text file path_host, headed by the device's architecture name;
+ * mderi_tune_load reads such a file into a context, so that later calls use
+ * the stored choices without timing candidates again.  Loading checks the
+ * header and every entry before it changes anything: a file that does not
+ * parse, or that was written on another architecture, gives MDERI_EINVAL
+ * and leaves the context as it was.  Loaded entries replace those of the
+ * same signature; a stored choice that is not among a class's candidates
+ * when the class runs is ignored.  Host-only; nothing is enqueued.
+ */
+mderi_status mderi_tune_save(mderi_ctx_t ctx, const char *path_host);
+mderi_status mderi_tune_load(mderi_ctx_t ctx, const char *path_host);
+
 /* Weight patterns of mderi_kbuild_grad. */
 #define MDERI_EXCHANGE 0 /* W_abcd = Wl_ac Wr_bd: E = tr(Wl^T K[Wr]) */
 #define MDERI_COULOMB 1  /* W_abcd = Wl_ab Wr_cd: E = tr(Wl^T J[Wr]) */

@@ -401,6 +401,71 @@ extern "C" mderi_status mderi_kernel_timing(mderi_ctx_t c, int enable) {
   return MDERI_OK;
 }
 
+// Autotune cache file: a header line "mderi-tune <format> <device arch>", the
+// entry count, then one line per class signature: the six key integers
+// (l_a l_b l_c l_d, -1 for a 1-centre side, and the largest primitive-pair
+// counts of the two sides) and the three tile integers (npt nps dbuf).
+static constexpr int kTuneFormat = 1;
+
+static std::string device_arch(int device) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+  std::string a = p.gcnArchName;
+  for (char &ch : a)
+    if (ch == ' ') ch = '_';
+  return a;
+}
+
+extern "C" mderi_status mderi_tune_save(mderi_ctx_t c, const char *path) {
+  if (!c || !path) return fail(MDERI_EINVAL, "mderi_tune_save: NULL context or path");
+  FILE *f = std::fopen(path, "w");
+  if (!f) return fail(MDERI_EINVAL, "mderi_tune_save: cannot open %s for writing", path);
+  bool ok = std::fprintf(f, "mderi-tune %d %s\n%zu\n", kTuneFormat, device_arch(c->device).c_str(), c->tune.size()) > 0;
+  for (const auto &kv : c->tune) {
+    const auto &k = kv.first;
+    const auto &v = kv.second;
+    ok = ok && std::fprintf(f, "%d %d %d %d %d %d %d %d %d\n", k[0], k[1], k[2], k[3], k[4], k[5], v[0], v[1], v[2]) > 0;
+  }
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(MDERI_EINVAL, "mderi_tune_save: writing %s failed", path);
+  return MDERI_OK;
+}
+
+extern "C" mderi_status mderi_tune_load(mderi_ctx_t c, const char *path) {
+  if (!c || !path) return fail(MDERI_EINVAL, "mderi_tune_load: NULL context or path");
+  FILE *f = std::fopen(path, "r");
+  if (!f) return fail(MDERI_EINVAL, "mderi_tune_load: cannot open %s", path);
+  char arch[256] = {0};
+  int format = 0;
+  long n = -1;
+  if (std::fscanf(f, "mderi-tune %d %255s %ld", &format, arch, &n) != 3 || format != kTuneFormat || n < 0 ||
+      n > 1000000) {
+    std::fclose(f);
+    return fail(MDERI_EINVAL, "mderi_tune_load: %s is not an autotune cache of format %d", path, kTuneFormat);
+  }
+  if (device_arch(c->device) != arch) {
+    std::fclose(f);
+    return fail(MDERI_EINVAL, "mderi_tune_load: %s was written on %s, this device is %s", path, arch,
+                device_arch(c->device).c_str());
+  }
+  std::vector<std::pair<std::array<int, 6>, std::array<int, 3>>> got;
+  for (long e = 0; e < n; ++e) {
+    std::array<int, 6> k;
+    std::array<int, 3> v;
+    if (std::fscanf(f, "%d %d %d %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &v[0], &v[1],
+                    &v[2]) != 9) {
+      std::fclose(f);
+      return fail(MDERI_EINVAL, "mderi_tune_load: %s: entry %ld of %ld is malformed", path, e, n);
+    }
+    got.push_back({k, v});
+  }
+  std::fclose(f);
+  // a choice is only ever used when it is among the class's candidates, so a
+  // stale entry costs nothing; nothing is changed unless the whole file parsed
+  for (const auto &kv : got) c->tune[kv.first] = kv.second;
+  return MDERI_OK;
+}
+
 extern "C" mderi_status mderi_set_workspace_limit(mderi_ctx_t c, size_t bytes) {
   if (!c) return fail(MDERI_EINVAL, "mderi_set_workspace_limit: NULL context");
   HIP_TRY(hipSetDevice(c->device));

@@ -93,6 +93,9 @@ def load_library():
     L.mderi_progress.restype = ctypes.c_int
     L.mderi_set_workspace_limit.argtypes = [_vp, ctypes.c_size_t]
     L.mderi_set_workspace_limit.restype = ctypes.c_int
+    for name in ("mderi_tune_save", "mderi_tune_load"):
+        getattr(L, name).argtypes = [_vp, ctypes.c_char_p]
+        getattr(L, name).restype = ctypes.c_int
     L.mderi_kernel_times.argtypes = [_vp, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     L.mderi_kernel_times.restype = ctypes.c_int
     L.mderi_jkbuild.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(Opts), _vp]
@@ -322,6 +325,14 @@ class Context:
     def progress(self, enable: bool):
         """Prints a line to stderr as each launch group of the J/K builds and the gradient finishes."""
         _check(load_library().mderi_progress(self._h, int(bool(enable))))
+
+    def tune_save(self, path):
+        """Writes the autotuner's tile choices held by the context to `path`."""
+        _check(load_library().mderi_tune_save(self._h, os.fsencode(path)))
+
+    def tune_load(self, path):
+        """Reads tile choices written by tune_save (same GPU architecture)."""
+        _check(load_library().mderi_tune_load(self._h, os.fsencode(path)))
 
     def set_workspace_limit(self, nbytes: int):
         """Caps the context's device workspace (0 = no cap); releases what it holds."""
