@@ -21,7 +21,13 @@
 // transforms are chained without leaving the wave.  The bra step runs one
 // 16-row ab tile at a time and adds it into an LDS copy of V[ab][cd]
 // (FP64 LDS atomics, since the nps row parts share columns), which is written
-// to V[ij,ab,cd,kl] (Sec. 3, ij fastest) at the end.
+// to V[ij,ab,cd,kl] (Sec. 3, ij fastest) at the end; with one row part and
+// single-primitive bra pairs a wave holds complete elements and stores them
+// from registers (vdirect).
+// Quartet runs: when every pair has one primitive pair, a quartet is a single
+// step, so the producer would have nothing to build ahead; a workgroup then
+// takes nrun quartets (ij, kl0 + m) in a row as its steps, and the producer
+// builds quartet m+1's [r] while the consumers transform quartet m.
 #include <algorithm>
 #include <vector>
 
@@ -55,8 +61,10 @@ __device__ __forceinline__ void with_tiles(int n, F &f) {
 // block's nct * nps consumers and its producer (a task-list launch sizes the
 // workgroup for its largest block) only take part in the barriers.
 template <int NPT, int LM, int MODE>
-__device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, int slab, double *smem, uint32_t tk) {
+__device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, int slab, double *smem, uint32_t tk,
+                                             int nq = 1) {
   constexpr bool SPLIT = MODE >= 2;  // split-precision bra transform with S = MODE + 3 slices
+  constexpr bool SINGLE = MODE == 1;  // single-primitive pairs: quartet runs / V from registers
   constexpr int S = MODE + 3;
   const int L = a.L;
   // column slab: this workgroup owns ket columns [c0, c0 + 16 nct); V keeps
@@ -70,8 +78,8 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
   double *cube1 = a.dbuf ? smem + cube_sz : smem;
   double *work = smem + (a.dbuf ? 2 : 1) * cube_sz;  // R-chain work area of the producer
   double *gsh = work + rr_work_size(L);              // G of this quartet's bra then ket primitive pairs
-  double *vsh = gsh + 4 * a.maxpp;                   // V[ab][cd] of this quartet
-  uint32_t *uvsh = (uint32_t *)(vsh + a.Nb * vstride);  // (u, v, y slot) of the pairs u+v <= L, by u+v
+  double *vsh = gsh + 4 * a.maxpp;                   // V[ab][cd] of this quartet (none when vdirect)
+  uint32_t *uvsh = (uint32_t *)(vsh + (SINGLE && a.vdirect ? 0 : a.Nb * vstride));  // (u, v, y slot) of the pairs u+v <= L
   int *offq = (int *)(uvsh + (L + 1) * (L + 2) / 2);
 
   const int tid = threadIdx.x;
@@ -79,13 +87,20 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
   const int g = lane >> 4, c = lane & 15;
   const int ncons = a.nct * a.nps;
 
+  // run: steps n = 0 .. nq-1 are the quartets (ij, kl + n), one primitive
+  // pair each side (the ket index ik of a step is then the quartet)
+  const bool run = SINGLE && a.nrun > 1, vd = SINGLE && a.vdirect != 0;
   const int bp0 = a.bra_off[ij], bp1 = a.bra_off[ij + 1];
   const int kp0 = a.ket_off[kl], kp1 = a.ket_off[kl + 1];
-  const int nbp = bp1 - bp0, nkp = kp1 - kp0;
+  const int nbp = bp1 - bp0, nkp = run ? nq : kp1 - kp0;
   const int nsteps = nbp * nkp;
 
   for (int e = tid; e < 4 * nbp; e += blockDim.x) gsh[e] = a.bra_G[4 * (size_t)bp0 + e];
-  for (int e = tid; e < 4 * nkp; e += blockDim.x) gsh[4 * nbp + e] = a.ket_G[4 * (size_t)kp0 + e];
+  if (run) {
+    for (int e = tid; e < 4 * nq; e += blockDim.x) gsh[4 * nbp + e] = a.ket_G[4 * (size_t)a.ket_off[kl + (e >> 2)] + (e & 3)];
+  } else {
+    for (int e = tid; e < 4 * nkp; e += blockDim.x) gsh[4 * nbp + e] = a.ket_G[4 * (size_t)kp0 + e];
+  }
   for (int e = tid; e < (L + 1) * (L + 2) / 2; e += blockDim.x) {
     // e-th pair in the order s = u+v ascending, u ascending
     int s = 0;
@@ -95,7 +110,8 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     (void)ylayout(L, v, &vb);
     uvsh[e] = (uint32_t)u | ((uint32_t)v << 8) | ((uint32_t)(vb + u) << 16);
   }
-  for (int e = tid; e < a.Nb * vstride; e += blockDim.x) vsh[e] = 0.0;
+  if (!vd)
+    for (int e = tid; e < a.Nb * vstride; e += blockDim.x) vsh[e] = 0.0;
   for (int q = tid; q < a.Nhk_pad; q += blockDim.x) {
     int o = 0;
     const uint32_t h = a.korder ? a.korder[q] : (q < a.Nhk ? a.tab.herm[q] : kPadRow);
@@ -103,6 +119,22 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     offq[q] = o;
   }
   __syncthreads();
+
+  // V of quartet (ij, kl + m) at V[ij + nbra (ab + Nb cd)] from this base
+  auto vbase = [&](int m) -> size_t { return (size_t)ij + (size_t)a.nbra * (size_t)a.Nb * (size_t)a.Nk * (kl + m); };
+  // run with an LDS copy of V: after step m every wave waits for the row
+  // parts' adds, the workgroup writes quartet m out and clears the copy (the
+  // next step's barrier orders the clearing before its adds)
+  const bool flushes = run && !vd;
+  auto flush = [&](int m) {
+    __syncthreads();
+    const size_t base = vbase(m);
+    for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) {
+      const int cl = e / a.Nb, ab = e - cl * a.Nb;
+      a.V[base + (size_t)a.nbra * ((size_t)ab + (size_t)a.Nb * cl)] = vsh[ab * vstride + cl];
+      vsh[ab * vstride + cl] = 0.0;
+    }
+  };
 
   if (wave == ncons) {
     // ---------------- producer: [r] one primitive quartet ahead ----------------
@@ -124,15 +156,23 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     for (int n = 0; n < nsteps; ++n) {
       if (!a.dbuf && n > 0) __syncthreads();  // consumers are done with the single cube
       build(n, (a.dbuf && (n & 1)) ? cube1 : cube0);
+      if (flushes && n > 0) {
+        __builtin_amdgcn_s_setprio(0);
+        flush(n - 1);
+        __builtin_amdgcn_s_setprio(3);
+      }
       __syncthreads();  // [r] of step n published
     }
     __builtin_amdgcn_s_setprio(0);
+    if (flushes) flush(nsteps - 1);
   } else if (wave > ncons) {
     // ---------------- surplus waves: barriers only ----------------
     for (int n = 0; n < nsteps; ++n) {
       if (!a.dbuf && n > 0) __syncthreads();
+      if (flushes && n > 0) flush(n - 1);
       __syncthreads();
     }
+    if (flushes) flush(nsteps - 1);
   } else {
     // ---------------- consumers ----------------
     // this wave's ket column tile ct and bra row tiles [t0, t0 + ntw); the
@@ -154,6 +194,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
     d4 xacc[NPT];
     for (int n = 0; n < nsteps; ++n) {
       if (!a.dbuf && n > 0) __syncthreads();
+      if (flushes && n > 0) flush(n - 1);
       const int ib = n / nkp, ik = n - ib * nkp;
       // ket transform: X[p][cd] += sum_q [p+q] H_ket[q][cd].  Two register
       // sets of LDS gathers ping-pong one k-step ahead of the MFMAs (the
@@ -162,7 +203,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
       // an L2 or last-level-cache round trip hides behind two k-steps of
       // MFMAs.  Prefetch indices are clamped so every load is unconditional;
       // nks is even (Nhk_pad is a multiple of 8).
-      const double *Hk = a.ket_H + (size_t)(kp0 + ik) * a.Nhk_pad * a.Nk_pad;
+      const double *Hk = a.ket_H + (size_t)(run ? a.ket_off[kl + ik] : kp0 + ik) * a.Nhk_pad * a.Nk_pad;
       // H_ket reads as buffer loads: the lane part of the offset sits in a
       // VGPR set once, the k-step part in an SGPR, so the loop spends no
       // vector instructions on addresses (and never rewrites a register an
@@ -178,7 +219,7 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
       const double h2 = hload(min(2, nks - 1)), h3 = hload(min(3, nks - 1));
       __syncthreads();  // [r] of step n published
       const double *cube = (a.dbuf && (n & 1)) ? cube1 : cube0;
-      if (ik == 0) {
+      if (run || ik == 0) {
 #pragma unroll
         for (int pt = 0; pt < NPT; ++pt) xacc[pt] = d4{0.0, 0.0, 0.0, 0.0};
       }
@@ -310,9 +351,16 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
             }
           }
         }
-      } else if (!SPLIT && ik == nkp - 1) {
+      } else if (!SPLIT && (run || ik == nkp - 1)) {
         // bra transform: V[ab][cd] += sum_p H_bra[p][ab] X[p][cd], one ab tile
-        // at a time (two accumulators), summed into the LDS copy of V
+        // at a time (two accumulators), summed into the LDS copy of V or
+        // (vdirect) stored to this step's quartet by buffer stores: the
+        // quartet's base in the resource, the lane's part of the offset
+        // (column cd, row 4 r + g of the tile) in a VGPR, the tile's part in
+        // an SGPR (the host keeps one quartet's nbra Nb Nk doubles below 2 GiB)
+        const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a.V + (vd ? vbase(run ? ik : 0) : 0)), (short)0, a.nbra * a.Nb * a.Nk * 8, kBufferWord3);
+        const int vlane = 8 * a.nbra * (g + a.Nb * col);
         const double *Hb = a.bra_H + (size_t)(bp0 + ib) * a.Hb_rows * a.Nb_pad + (size_t)t0 * 16 * a.Nb_pad;
 #pragma unroll 1
         for (int at = 0; at < nat; ++at) {
@@ -337,14 +385,24 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int ab = at * 16 + 4 * r + g;
-              if (ab < a.Nb) atomicAdd(&vsh[ab * vstride + (col - c0)], acc0[r] + acc1[r]);
+              if (ab < a.Nb) {
+                if (vd) {
+                  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+                  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, acc0[r] + acc1[r]), vrs, vlane,
+                                                        8 * a.nbra * (at * 16 + 4 * r), 0);
+                } else {
+                  atomicAdd(&vsh[ab * vstride + (col - c0)], acc0[r] + acc1[r]);
+                }
+              }
             }
           }
         }
       }
     }
+    if (flushes) flush(nsteps - 1);
   }
   __syncthreads();  // V complete in LDS
+  if (vd || run) return;  // stored from registers, or flushed quartet by quartet
 
   if (a.diag) {
     // (ab|ab) for the ab that fall in this workgroup's column slab
@@ -374,12 +432,13 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
 template <int NPT, int LM, int MODE>
 __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
   extern __shared__ double smem[];
-  const long G = (a.diag ? (long)a.nbra : (long)a.nbra * a.nket) * a.nslab;
+  const int nr = a.nrun > 1 ? a.nrun : 1, nkr = (a.nket + nr - 1) / nr;  // ket runs
+  const long G = (a.diag ? (long)a.nbra : (long)a.nbra * nkr) * a.nslab;
   const long v0 = xcd_remap(blockIdx.x, G);
   const int slab = (int)(v0 % a.nslab);  // slabs of one quartet are neighbours (shared bra data)
   const long v = v0 / a.nslab;
-  const int ij = (int)(v % a.nbra), kl = a.diag ? ij : (int)(v / a.nbra);
-  eri4_quartet<NPT, LM, MODE>(a, ij, kl, slab, smem, a.wtask[threadIdx.x >> 6]);
+  const int ij = (int)(v % a.nbra), kl = a.diag ? ij : (int)(v / a.nbra) * nr;
+  eri4_quartet<NPT, LM, MODE>(a, ij, kl, slab, smem, a.wtask[threadIdx.x >> 6], min(nr, a.nket - kl));
 }
 
 // Persistent task-list kernel: the workgroups stride over tasks (block id,
@@ -416,7 +475,8 @@ template <int NPT, int LM, int MODE>
 hipError_t launch_t(const Eri4Args &a, hipStream_t s) {
   const int waves = a.nct * a.nps + 1;
   const size_t lds = eri4_lds_bytes(a);
-  const long G = (a.diag ? (long)a.nbra : (long)a.nbra * a.nket) * a.nslab;
+  const int nr = a.nrun > 1 ? a.nrun : 1;
+  const long G = (a.diag ? (long)a.nbra : (long)a.nbra * ((a.nket + nr - 1) / nr)) * a.nslab;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)eri4_kernel<NPT, LM, MODE>,
@@ -545,7 +605,7 @@ static size_t side_bytes(int L, int maxpp, int Nhk_pad, int Nb, int Nk) {
 }
 
 size_t eri4_lds_bytes(const Eri4Args &a) {
-  const int vcols = a.nslab > 1 ? a.nct * 16 : a.Nk;
+  const int vcols = a.vdirect ? 0 : a.nslab > 1 ? a.nct * 16 : a.Nk;
   return cube_region(a.cube_sz, a.dbuf ? 2 : 1) + side_bytes(a.L, a.maxpp, a.Nhk_pad, a.Nb, vcols);
 }
 
@@ -704,7 +764,7 @@ hipError_t launch_eri4(const Eri4Args &a0, hipStream_t s) {
       default: return hipErrorInvalidValue;
     }
   }
-  return launch_g<0>(a, s);
+  return (a.nrun > 1 || a.vdirect) ? launch_g<1>(a, s) : launch_g<0>(a, s);
 }
 
 int eri4_lm_bucket(int L) { return rr_lm_bucket(L); }

@@ -799,6 +799,27 @@ std::vector<std::array<int, 3>> block_candidates(int Nhb, int Nb, int Nk, int L,
 // entry point); otherwise regions come from the pooled workspace.
 // tile_variant > 0 forces that work split (see mderi_eri4_tile_variants);
 // count_only stores the number of splits in *count and enqueues nothing.
+#ifndef MDERI_QUARTET_RUN
+#define MDERI_QUARTET_RUN 4
+#endif
+// Quartet runs and V stored from registers (Eri4Args::nrun, vdirect) for one
+// work split of a class batch whose pairs have at most maxb / maxk primitive
+// pairs (maxpp their sum): both need single-primitive bra pairs and plain
+// class-batch output, runs also single-primitive kets and two [r] cubes, V
+// from registers one row part.  Off again if the run's ket data would push
+// the workgroup past the LDS limit.
+void set_run_mode(Eri4Args &a, int maxb, int maxk, int maxpp) {
+  const bool single = maxb == 1 && !a.diag && a.nslab == 1 && !a.bra_Hs && !a.orow;
+  // (buffer stores of V: one quartet's nbra Nb Nk doubles within 2 GiB)
+  a.vdirect = single && a.nps == 1 && (long)a.nbra * a.Nb * a.Nk * 8 < (1L << 31) ? 1 : 0;
+  a.nrun = single && maxk == 1 && a.dbuf ? MDERI_QUARTET_RUN : 0;
+  a.maxpp = std::max(maxpp, a.nrun > 1 ? 1 + a.nrun : 0);
+  if (eri4_lds_bytes(a) > 160 * 1024) {
+    a.nrun = 0;
+    a.maxpp = maxpp;
+  }
+}
+
 mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int diag, double *V,
                              const std::vector<int> *extra_idx, void **d_extra_idx, hipStream_t s, int flags = 0,
                              int precision = 0, int slices = kSplitDefault, bool noalloc = false, int tile_variant = 0,
@@ -985,6 +1006,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
     ea.Hs_rows = Hs_rows;
     ea.split = slices;
   }
+  set_run_mode(ea, maxb, maxk, maxpp);
   if (cands.size() > 1) {
     // autotune: time each variant on this batch (the second of two runs)
     hipEvent_t e0, e1;
@@ -998,6 +1020,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
       t.nps = cd[1];
       t.dbuf = cd[2];
       t.Nhb_pad = 16 * cd[0] * cd[1];
+      set_run_mode(t, maxb, maxk, maxpp);
       float ms = 0.0f;
       for (int rep = 0; rep < 2; ++rep) {
         HIP_TRY(hipEventRecord(e0, s));
@@ -1018,6 +1041,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
     ea.nps = bestc[1];
     ea.dbuf = bestc[2];
     ea.Nhb_pad = 16 * bestc[0] * bestc[1];
+    set_run_mode(ea, maxb, maxk, maxpp);
   }
   if (noalloc) {  // no timing events (creating them could allocate)
     HIP_TRY(launch_eri4(ea, s));

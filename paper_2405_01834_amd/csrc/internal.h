@@ -121,6 +121,15 @@ struct Eri4Args {
   const uint32_t *border;  // bra Hermite row order (Nhb_pad entries, see PairArgs::order)
   const uint32_t *korder;  // ket Hermite row order (Nhk_pad entries), or nullptr for the global order
   int diag;      // Schwarz mode: quartets (ij|ij) only, V receives the diagonal [ij][ab]
+  // quartet runs (single-primitive pairs on both sides, two [r] cubes): a
+  // workgroup takes the nrun ket pairs kl0 .. kl0 + nrun - 1 of one bra pair
+  // as consecutive steps, the producer building the next quartet's [r] while
+  // the consumers transform the current one (0 or 1: one quartet)
+  int nrun;
+  // V leaves the consumer registers straight for global memory (single
+  // primitive bra pairs and one row part, so a wave holds complete
+  // elements): no LDS copy of V
+  int vdirect;
   // matrix output (orow != nullptr): (ab, cd) of quartet (ij, kl) goes to
   // V[orow[ij] + ab + ld * (ocol[kl] + cd)] instead of the class-batch layout
   const long *orow, *ocol;

@@ -63,6 +63,23 @@ def test_class_batch_parity(ctx, cls, K):
     _assert_close(got, ref, f"{cls} K={K}")
 
 
+@pytest.mark.parametrize("cls,Kb,Kk,nbra,nket", [((2, 2, 2, 2), 1, 2, 3, 5), ((2, 1, 2, 2), 2, 1, 3, 5),
+                                                  ((3, 3, 3, 3), 1, 1, 2, 9), ((4, 4, 4, 4), 1, 1, 2, 7),
+                                                  ((1, 1, 1, 0), 1, 1, 7, 13), ((3, 2, 1, 0), 1, 1, 5, 1)])
+def test_single_primitive_paths(ctx, cls, Kb, Kk, nbra, nket):
+    """Single-primitive pairs on both sides go through quartet runs (several
+    ket pairs per workgroup; run counts that do not divide the ket list, and
+    a one-pair ket list); a single-primitive bra with a contracted ket stores
+    V from registers without runs; a contracted bra takes the plain path."""
+    la, lb, lc, ld = cls
+    sh_b, bra = inputs.near_pairs(300 + 7 * sum(cls) + Kb, la, lb, Kb, nbra, box=6.0)
+    sh_k, ket = inputs.near_pairs(400 + 7 * sum(cls) + Kk, lc, ld, Kk, nket, box=6.0)
+    sh = sh_b.concat(sh_k)
+    ket = ket + sh_b.n
+    got, ref = _both(ctx, sh, bra, ket)
+    _assert_close(got, ref, f"{cls} K={Kb},{Kk} {nbra}x{nket}")
+
+
 def test_mixed_contraction_degrees(ctx):
     """Pairs of one class may have different primitive counts."""
     rng = np.random.default_rng(5)
