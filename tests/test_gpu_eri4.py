@@ -64,20 +64,38 @@ def test_class_batch_parity(ctx, cls, K):
 
 
 @pytest.mark.parametrize("cls,Kb,Kk,nbra,nket", [((2, 2, 2, 2), 1, 2, 3, 5), ((2, 1, 2, 2), 2, 1, 3, 5),
-                                                  ((3, 3, 3, 3), 1, 1, 2, 9), ((4, 4, 4, 4), 1, 1, 2, 7),
-                                                  ((1, 1, 1, 0), 1, 1, 7, 13), ((3, 2, 1, 0), 1, 1, 5, 1)])
+                                                  ((3, 3, 3, 3), 1, 1, 64, 131), ((4, 4, 4, 4), 1, 1, 64, 67),
+                                                  ((1, 1, 1, 0), 1, 1, 64, 133), ((2, 2, 2, 2), 1, 1, 7, 13),
+                                                  ((3, 2, 1, 0), 1, 1, 5, 1)])
 def test_single_primitive_paths(ctx, cls, Kb, Kk, nbra, nket):
-    """Single-primitive pairs on both sides go through quartet runs (several
-    ket pairs per workgroup; run counts that do not divide the ket list, and
-    a one-pair ket list); a single-primitive bra with a contracted ket stores
-    V from registers without runs; a contracted bra takes the plain path."""
+    """Single-primitive pairs on both sides go through quartet runs once the
+    batch is large enough to keep 2048 workgroups (runs of 4 from 8192
+    quartets, of 2 from 4096; ket counts that runs do not divide): the first
+    four bra pairs against every ket pair are checked, which covers every
+    position in a run.  Small single-primitive batches, a single-primitive
+    bra with a contracted ket (V stored from registers without runs) and a
+    contracted bra (plain path) are checked whole."""
+    import torch
     la, lb, lc, ld = cls
     sh_b, bra = inputs.near_pairs(300 + 7 * sum(cls) + Kb, la, lb, Kb, nbra, box=6.0)
     sh_k, ket = inputs.near_pairs(400 + 7 * sum(cls) + Kk, lc, ld, Kk, nket, box=6.0)
     sh = sh_b.concat(sh_k)
     ket = ket + sh_b.n
-    got, ref = _both(ctx, sh, bra, ket)
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    V = ctx.eri4(b, bra, ket)
+    torch.cuda.synchronize()
+    nb = min(nbra, 4)
+    got = V[:nb].cpu().numpy()
+    ref = oracle.eri4(oracle.Basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers, 1), bra[:nb], ket)
     _assert_close(got, ref, f"{cls} K={Kb},{Kk} {nbra}x{nket}")
+    if nbra * nket >= 4096:
+        # every work split at run size (one or more row parts, one or two cubes)
+        nv = ctx.eri4_tile_variants(b, bra, ket)
+        for v in range(1, nv + 1):
+            print(f"tile variant {v} of {nv} for {cls} {nbra}x{nket}", flush=True)
+            V = ctx.eri4(b, bra, ket, tile_variant=v)
+            torch.cuda.synchronize()
+            _assert_close(V[:nb].cpu().numpy(), ref, f"{cls} {nbra}x{nket} variant {v}")
 
 
 def test_mixed_contraction_degrees(ctx):
