@@ -445,8 +445,12 @@ __global__ void __launch_bounds__(64 * kMaxWaves) eri4_kernel(Eri4Args a) {
 // quartet index ij + nbra kl), sorted by the host by decreasing cost, of any
 // number of class blocks that share the register tile NPT and the producer
 // length LM; the workgroup holds the largest block's waves and LDS.
-template <int NPT, int LM>
-__global__ void __launch_bounds__(64 * kMaxWaves)
+// OCC: waves per SIMD the kernel is compiled for (4: any workgroup up to
+// kMaxWaves waves, 128 VGPRs; 5 or 6: workgroups of at most 4 waves, 96 or
+// 80 VGPRs, see eri4_tasks_occupancy).
+template <int NPT, int LM, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, OCC == 4 ? 64 * kMaxWaves : 256),
+                               amdgpu_waves_per_eu(OCC == 4 ? 1 : OCC)))
     eri4_tasks_kernel(const Eri4Args *__restrict__ blocks, const int2 *__restrict__ tasks, int ntask) {
   extern __shared__ double smem[];
   for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
@@ -714,17 +718,27 @@ hipError_t launch_lm(const Eri4Args &a, hipStream_t s) {
   }
 }
 
-template <int NPT, int LM>
-hipError_t launch_tasks_t(const Eri4Args *b, const int2 *t, int n, int waves, size_t lds, int grid, hipStream_t s) {
+template <int NPT, int LM, int OCC>
+hipError_t launch_tasks_o(const Eri4Args *b, const int2 *t, int n, int waves, size_t lds, int grid, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)eri4_tasks_kernel<NPT, LM>,
+    hipError_t e = hipFuncSetAttribute((const void *)eri4_tasks_kernel<NPT, LM, OCC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((eri4_tasks_kernel<NPT, LM>), dim3((unsigned)grid), dim3(64 * waves), lds, s, b, t, n);
+  hipLaunchKernelGGL((eri4_tasks_kernel<NPT, LM, OCC>), dim3((unsigned)grid), dim3(64 * waves), lds, s, b, t, n);
   return hipGetLastError();
+}
+
+template <int NPT, int LM>
+hipError_t launch_tasks_t(const Eri4Args *b, const int2 *t, int n, int waves, size_t lds, int grid, hipStream_t s) {
+  const int occ = eri4_tasks_occupancy(NPT, LM, waves);
+  if constexpr (LM <= 10 && NPT == 1)
+    if (occ == 6) return launch_tasks_o<NPT, LM, 6>(b, t, n, waves, lds, grid, s);
+  if constexpr (LM <= 10 && NPT == 2)
+    if (occ == 5) return launch_tasks_o<NPT, LM, 5>(b, t, n, waves, lds, grid, s);
+  return launch_tasks_o<NPT, LM, 4>(b, t, n, waves, lds, grid, s);
 }
 
 template <int LM>
@@ -768,6 +782,15 @@ hipError_t launch_eri4(const Eri4Args &a0, hipStream_t s) {
 }
 
 int eri4_lm_bucket(int L) { return rr_lm_bucket(L); }
+
+// The one- and two-tile shapes with short R chains (L <= 10) fit 80 / 96
+// VGPRs without spilling, so their task-list workgroups (at most 4 waves)
+// can sit 6 / 5 to a SIMD side by side: more producer waves per CU for the
+// 3-centre task lists, whose [r] builds bound them.
+int eri4_tasks_occupancy(int npt, int Lmax, int waves) {
+  if (waves > 4 || rr_lm_bucket(Lmax) > 10) return 4;
+  return npt == 1 ? 6 : npt == 2 ? 5 : 4;
+}
 
 hipError_t launch_eri4_tasks(const Eri4Args *d_blocks, const int2 *d_tasks, int ntask, int npt, int Lmax, int waves,
                              size_t lds, int grid, hipStream_t s) {

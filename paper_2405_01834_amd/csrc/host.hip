@@ -1371,9 +1371,9 @@ std::vector<std::array<int, 3>> block_candidates(int Nhb, int Nb, int Nk, int L,
 
 size_t block_lds(const Eri4Args &a) { return eri4_lds_bytes(a); }
 
-int group_grid(size_t lds, int waves, long ntask) {
+int group_grid(size_t lds, int waves, long ntask, int occ = 4) {
   const long per_cu_lds = lds ? (long)(160 * 1024 / lds) : 16;
-  const long per_cu_waves = 16 / waves;  // 128 VGPRs per lane: 4 waves per SIMD
+  const long per_cu_waves = 4 * occ / waves;  // occ waves per SIMD (128 VGPRs per lane: 4)
   long per_cu = std::max(1L, std::min(per_cu_lds, per_cu_waves));
   long g = 256 * per_cu;
   return (int)std::max(1L, std::min(g, ntask));
@@ -1709,7 +1709,7 @@ extern "C" mderi_status mderi_eri3_batch(mderi_ctx_t c, mderi_basis_t b, mderi_b
         HIP_TRY(hipMemcpyAsync(dev(o_blocks), one.data(), sizeof(Eri4Args), hipMemcpyHostToDevice, s));
         const int waves = one[0].nct * cd[1] + 1;
         const size_t lds = block_lds(one[0]);
-        const int grid = group_grid(lds, waves, nq);
+        const int grid = group_grid(lds, waves, nq, eri4_tasks_occupancy(cd[0], bp.a.L, waves));
         float ms = 0.0f;
         for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches
           HIP_TRY(hipEventRecord(e0, s));
@@ -1777,7 +1777,7 @@ extern "C" mderi_status mderi_eri3_batch(mderi_ctx_t c, mderi_basis_t b, mderi_b
     g.ntask = (int)tl.size();
     g.d_blocks = (const Eri4Args *)dev(o_blocks) + first_block;
     g.d_tasks = (const int2 *)dev(o_tasks) + first_task;
-    g.grid = group_grid(g.lds, g.waves, g.ntask);
+    g.grid = group_grid(g.lds, g.waves, g.ntask, eri4_tasks_occupancy(g.npt, g.Lmax, g.waves));
     plan->groups.push_back(g);
   }
   HIP_TRY(hipMemcpyAsync(dev(o_blocks), dblocks.data(), sizeof(Eri4Args) * dblocks.size(), hipMemcpyHostToDevice, s));

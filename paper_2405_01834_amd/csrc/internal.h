@@ -281,6 +281,8 @@ hipError_t launch_eri4_tasks(const Eri4Args *d_blocks, const int2 *d_tasks, int 
 int eri4_lm_bucket(int L);
 // LDS bytes needed by one 4-centre workgroup.
 size_t eri4_lds_bytes(const Eri4Args &a);
+// Waves per SIMD the task-list kernel of this shape is built for (4, 5 or 6).
+int eri4_tasks_occupancy(int npt, int Lmax, int waves);
 // Fills a.wtask from nct, nps, npt, Nhb and split (see eri4.hip).
 void eri4_fill_wtask(Eri4Args &a);
 
