@@ -39,9 +39,9 @@ TAU = 1e-12
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2) and
 # WRITE_SIZE (x1) counters (profiles/eri4_ggK3_hbm_counters.md), valid only for
 # the kernel sources they were taken with.
-TRAFFIC = {"kernel": "eri4_kernel [gg|gg] K=3", "bytes": 1.1305e11,
-           "sources": {"eri4.hip": "ff26cc5271d31933", "device_common.h": "1d6737b5b2d84adb",
-                       "internal.h": "2c30d7b888ea459f"}}
+TRAFFIC = {"kernel": "eri4_kernel [gg|gg] K=3", "bytes": 1.1303e11,
+           "sources": {"eri4.hip": "43fdd93448f59f27", "device_common.h": "1d6737b5b2d84adb",
+                       "internal.h": "4a481a7c1ef1a30c"}}
 
 
 def measured_traffic(kernel):
