@@ -154,10 +154,10 @@ mderi_status mderi_eri4_tile_variants(mderi_ctx_t ctx, mderi_basis_t basis, int 
  * MDERI_FP64 and opts->flags 0).  Every device region the call needs (pair
  * lists, primitive-pair data and transform matrices of both sides) is a
  * slice of a fixed 64 MiB device array compiled into the library, and its
- * metadata goes through the 4 MiB pinned staging buffer that mderi_create
- * allocates; the call itself calls no allocating routine.  A batch that
- * needs more scratch or staging than that returns MDERI_ESIZE with nothing
- * enqueued.  All calls on one GPU share that GPU's array (contexts
+ * metadata goes through one 4 MiB slot of the pinned staging buffer that
+ * mderi_create allocates (four slots, used by successive calls in turn); the
+ * call itself calls no allocating routine.  A batch that needs more scratch
+ * or staging than that returns MDERI_ESIZE with nothing enqueued.  All calls on one GPU share that GPU's array (contexts
  * included), which keeps the last call's contents: calls that overlap on
  * one GPU (different streams, or different host threads) race and must be
  * serialised by the caller.

@@ -207,7 +207,8 @@ constexpr size_t kScratchBytes = (size_t)64 << 20;
 static __device__ __align__(256) char scratch[kScratchBytes];
 // Pinned host staging allocated when a context is created, so that the
 // allocation-free entry point can upload its metadata without allocating.
-constexpr size_t kStageInitBytes = (size_t)4 << 20;
+constexpr size_t kStageInitBytes = (size_t)4 << 20;  // per slot
+constexpr int kStageSlots = 4;
 
 struct mderi_ctx {
   int device = 0;
@@ -215,11 +216,15 @@ struct mderi_ctx {
   void *ws[WS_COUNT] = {};
   size_t ws_cap[WS_COUNT] = {};
   size_t ws_limit = 0;  // cap on the sum of ws_cap (0 = none)
-  // pinned staging for per-call host->device uploads, guarded by an event
-  char *stage = nullptr;
-  size_t stage_cap = 0;
-  hipEvent_t stage_done = nullptr;
-  bool stage_pending = false;
+  // pinned staging for per-call host->device uploads: kStageSlots slots of
+  // stage_cap bytes used in turn, each guarded by an event, so the host can
+  // prepare the next calls while earlier uploads are still queued
+  char *stage = nullptr;     // kStageSlots * stage_cap bytes
+  size_t stage_cap = 0;      // bytes per slot (the most one call can stage)
+  hipEvent_t stage_done[kStageSlots] = {};
+  bool stage_pending[kStageSlots] = {};
+  int stage_slot = 0;        // slot of the current call
+  char *stage_cur = nullptr;  // its base
   // kernel timing: when on, each fused-kernel launch is bracketed by a pair
   // of events on its stream (pairs are recycled after they are read)
   bool timing = false;
@@ -278,34 +283,47 @@ static mderi_status ws_get(mderi_ctx *c, int slot, size_t bytes, void **out) {
   return MDERI_OK;
 }
 
-// Copies `n` host bytes to device `dst` on `s` through the pinned staging
-// buffer (reused only after the previous copy has completed).
+// Copies `n` host bytes to device `dst` on `s` through the current staging
+// slot (stage_begin .. stage_end).
 static mderi_status stage_copy(mderi_ctx *c, void *dst, const void *src, size_t n, hipStream_t s, size_t *used) {
   if (*used + n > c->stage_cap) return fail(MDERI_EINVAL, "internal: staging overflow");
-  memcpy(c->stage + *used, src, n);
-  HIP_TRY(hipMemcpyAsync(dst, c->stage + *used, n, hipMemcpyHostToDevice, s));
+  memcpy(c->stage_cur + *used, src, n);
+  HIP_TRY(hipMemcpyAsync(dst, c->stage_cur + *used, n, hipMemcpyHostToDevice, s));
   *used += (n + 255) & ~(size_t)255;
   return MDERI_OK;
 }
 
+// Takes the next staging slot for a call that stages `need` bytes: waits for
+// the uploads that last used the slot (kStageSlots calls back), or for all of
+// them when the slots must grow.
 static mderi_status stage_begin(mderi_ctx *c, size_t need) {
-  if (c->stage_pending) {
-    HIP_TRY(hipEventSynchronize(c->stage_done));
-    c->stage_pending = false;
-  }
   if (need > c->stage_cap) {
+    for (int k = 0; k < kStageSlots; ++k)
+      if (c->stage_pending[k]) {
+        HIP_TRY(hipEventSynchronize(c->stage_done[k]));
+        c->stage_pending[k] = false;
+      }
     if (c->stage) HIP_TRY(hipHostFree(c->stage));
     c->stage = nullptr;
-    const size_t cap = need + need / 2 + 4096;
-    HIP_TRY(hipHostMalloc((void **)&c->stage, cap, hipHostMallocDefault));
+    c->stage_cap = 0;
+    const size_t cap = (need + need / 2 + 4096 + 255) & ~(size_t)255;
+    HIP_TRY(hipHostMalloc((void **)&c->stage, cap * kStageSlots, hipHostMallocDefault));
     c->stage_cap = cap;
   }
+  const int k = c->stage_slot;
+  if (c->stage_pending[k]) {
+    HIP_TRY(hipEventSynchronize(c->stage_done[k]));
+    c->stage_pending[k] = false;
+  }
+  c->stage_cur = c->stage + (size_t)k * c->stage_cap;
   return MDERI_OK;
 }
 
 static mderi_status stage_end(mderi_ctx *c, hipStream_t s) {
-  HIP_TRY(hipEventRecord(c->stage_done, s));
-  c->stage_pending = true;
+  const int k = c->stage_slot;
+  HIP_TRY(hipEventRecord(c->stage_done[k], s));
+  c->stage_pending[k] = true;
+  c->stage_slot = (k + 1) % kStageSlots;
   return MDERI_OK;
 }
 
@@ -351,19 +369,21 @@ extern "C" mderi_status mderi_create(int device, mderi_ctx_t *out) {
     mderi_destroy(c);
     return fail(MDERI_EDEVICE, "table upload failed: %s", hipGetErrorString(e));
   }
-  if ((e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming)) != hipSuccess) {
-    mderi_destroy(c);
-    return fail(MDERI_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
-  }
+  for (int k = 0; k < kStageSlots; ++k)
+    if ((e = hipEventCreateWithFlags(&c->stage_done[k], hipEventDisableTiming)) != hipSuccess) {
+      mderi_destroy(c);
+      return fail(MDERI_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    }
   // this device's copy of the scratch array (the device is current here)
   if ((e = hipGetSymbolAddress((void **)&c->scratch, HIP_SYMBOL(scratch))) != hipSuccess || !c->scratch) {
     mderi_destroy(c);
     return fail(MDERI_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
   }
-  if ((e = hipHostMalloc((void **)&c->stage, kStageInitBytes, hipHostMallocDefault)) != hipSuccess) {
+  if ((e = hipHostMalloc((void **)&c->stage, kStageInitBytes * kStageSlots, hipHostMallocDefault)) != hipSuccess) {
     c->stage = nullptr;
     mderi_destroy(c);
-    return fail(MDERI_ENOMEM, "pinned staging of %zu bytes: %s", kStageInitBytes, hipGetErrorString(e));
+    return fail(MDERI_ENOMEM, "pinned staging of %zu bytes: %s", kStageInitBytes * kStageSlots,
+                hipGetErrorString(e));
   }
   c->stage_cap = kStageInitBytes;
   *out = c;
@@ -382,7 +402,8 @@ extern "C" void mderi_destroy(mderi_ctx_t c) {
   (void)hipFree(c->tab.solid_cart);
   for (int i = 0; i < WS_COUNT; ++i) (void)hipFree(c->ws[i]);
   if (c->stage) (void)hipHostFree(c->stage);
-  if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  for (hipEvent_t e : c->stage_done)
+    if (e) (void)hipEventDestroy(e);
   for (TaskPlan *p : c->plans) free_plan(p);
   if (c->blas) (void)rocblas_destroy_handle(c->blas);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
