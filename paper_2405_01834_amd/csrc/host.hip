@@ -911,43 +911,48 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
     *out = c->scratch + off;
     return MDERI_OK;
   };
-  void *d_ppb, *d_ppk, *d_offb, *d_offk, *d_Gb, *d_Gk, *d_Hb, *d_Hk, *d_border, *d_korder = nullptr;
-  if ((st = region(WS_ORDER, sizeof(uint32_t) * border.size(), &d_border)) ||
-      (st = region(WS_PP_BRA, sizeof(PrimPair) * ppb.size(), &d_ppb)) ||
-      (st = region(WS_PP_KET, sizeof(PrimPair) * ppk.size(), &d_ppk)) ||
-      (st = region(WS_OFF_BRA, sizeof(int) * offb.size(), &d_offb)) ||
-      (st = region(WS_OFF_KET, sizeof(int) * offk.size(), &d_offk)) ||
+  // the call's metadata (primitive-pair lists, pair offsets, row orders and
+  // the Schwarz index list) in one device region, uploaded by one copy
+  struct Part {
+    const void *src;
+    size_t bytes, off;
+  };
+  Part parts[7] = {{ppb.data(), sizeof(PrimPair) * ppb.size(), 0},
+                   {ppk.data(), sizeof(PrimPair) * ppk.size(), 0},
+                   {offb.data(), sizeof(int) * offb.size(), 0},
+                   {offk.data(), sizeof(int) * offk.size(), 0},
+                   {border.data(), sizeof(uint32_t) * border.size(), 0},
+                   {korder.data(), sizeof(uint32_t) * korder.size(), 0},
+                   {extra_idx ? extra_idx->data() : nullptr, extra_idx ? sizeof(int) * extra_idx->size() : 0, 0}};
+  size_t meta_bytes = 0;
+  for (Part &pt : parts) {
+    pt.off = meta_bytes;
+    meta_bytes += (pt.bytes + 255) & ~(size_t)255;
+  }
+  void *d_meta, *d_Gb, *d_Gk, *d_Hb, *d_Hk;
+  if ((st = region(WS_PP_BRA, meta_bytes, &d_meta)) ||
       (st = region(WS_G_BRA, sizeof(double) * 4 * ppb.size(), &d_Gb)) ||
       (st = region(WS_G_KET, sizeof(double) * 4 * ppk.size(), &d_Gk)) ||
       (st = region(WS_H_BRA, sizeof(double) * (size_t)Hb_rows * Nb_pad * ppb.size(), &d_Hb)) ||
       (st = region(WS_H_KET, sizeof(double) * (size_t)Nhk_pad * Nk_pad * ppk.size(), &d_Hk)))
     return st;
-  if (!korder.empty() && (st = region(WS_KORDER, sizeof(uint32_t) * korder.size(), &d_korder))) return st;
+  char *meta = (char *)d_meta;
+  void *d_ppb = meta + parts[0].off, *d_ppk = meta + parts[1].off, *d_offb = meta + parts[2].off;
+  void *d_offk = meta + parts[3].off, *d_border = meta + parts[4].off;
+  void *d_korder = korder.empty() ? nullptr : meta + parts[5].off;
+  if (extra_idx) *d_extra_idx = meta + parts[6].off;
   void *d_Hs = nullptr, *d_Hexp = nullptr, *d_Hrow = nullptr;
   if (split && ((st = region(WS_HS, sizeof(uint16_t) * slices * (size_t)Nb_pad * Hs_rows * ppb.size(), &d_Hs)) ||
                 (st = region(WS_HEXP, sizeof(int) * (size_t)Nb_pad * ppb.size(), &d_Hexp)) ||
                 (st = region(WS_HROW, sizeof(int) * (size_t)Hs_rows * ppb.size(), &d_Hrow))))
     return st;
-  if (extra_idx && (st = region(WS_IDX, sizeof(int) * extra_idx->size(), d_extra_idx))) return st;
-  const size_t stage_need = sizeof(PrimPair) * (ppb.size() + ppk.size()) + sizeof(int) * (offb.size() + offk.size()) +
-                            (extra_idx ? sizeof(int) * extra_idx->size() : 0) + sizeof(uint32_t) * border.size() +
-                            sizeof(uint32_t) * korder.size() + 12 * 256;
-  if (noalloc && stage_need > c->stage_cap)
+  if (noalloc && meta_bytes > c->stage_cap)
     return fail(MDERI_ESIZE, "class batch metadata of %zu bytes exceeds the %zu-byte staging buffer of the "
-                "allocation-free entry point", stage_need, c->stage_cap);
-  if ((st = stage_begin(c, stage_need))) return st;
-  size_t used = 0;
-  if ((st = stage_copy(c, d_ppb, ppb.data(), sizeof(PrimPair) * ppb.size(), s, &used)) ||
-      (st = stage_copy(c, d_ppk, ppk.data(), sizeof(PrimPair) * ppk.size(), s, &used)) ||
-      (st = stage_copy(c, d_offb, offb.data(), sizeof(int) * offb.size(), s, &used)) ||
-      (st = stage_copy(c, d_offk, offk.data(), sizeof(int) * offk.size(), s, &used)) ||
-      (st = stage_copy(c, d_border, border.data(), sizeof(uint32_t) * border.size(), s, &used)))
-    return st;
-  if (!korder.empty() &&
-      (st = stage_copy(c, d_korder, korder.data(), sizeof(uint32_t) * korder.size(), s, &used)))
-    return st;
-  if (extra_idx && (st = stage_copy(c, *d_extra_idx, extra_idx->data(), sizeof(int) * extra_idx->size(), s, &used)))
-    return st;
+                "allocation-free entry point", meta_bytes, c->stage_cap);
+  if ((st = stage_begin(c, meta_bytes))) return st;
+  for (const Part &pt : parts)
+    if (pt.bytes) memcpy(c->stage_cur + pt.off, pt.src, pt.bytes);
+  HIP_TRY(hipMemcpyAsync(d_meta, c->stage_cur, meta_bytes, hipMemcpyHostToDevice, s));
   if ((st = stage_end(c, s))) return st;
 
   PairArgs pa{};
