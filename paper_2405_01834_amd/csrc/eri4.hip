@@ -129,9 +129,9 @@ __device__ __forceinline__ void eri4_quartet(const Eri4Args &a, int ij, int kl, 
   auto flush = [&](int m) {
     __syncthreads();
     const size_t base = vbase(m);
-    for (int e = tid; e < a.Nb * a.Nk; e += blockDim.x) {
-      const int cl = e / a.Nb, ab = e - cl * a.Nb;
-      a.V[base + (size_t)a.nbra * ((size_t)ab + (size_t)a.Nb * cl)] = vsh[ab * vstride + cl];
+    for (int e = tid; e < a.Nb * vcols; e += blockDim.x) {
+      const int cl = e / a.Nb, ab = e - cl * a.Nb;  // column c0 + cl of this workgroup's slab
+      a.V[base + (size_t)a.nbra * ((size_t)ab + (size_t)a.Nb * (c0 + cl))] = vsh[ab * vstride + cl];
       vsh[ab * vstride + cl] = 0.0;
     }
   };

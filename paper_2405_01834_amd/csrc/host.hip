@@ -827,7 +827,8 @@ std::vector<std::array<int, 3>> block_candidates(int Nhb, int Nb, int Nk, int L,
 // work split of a class batch whose pairs have at most maxb / maxk primitive
 // pairs (maxpp their sum): both need single-primitive bra pairs and plain
 // class-batch output, runs also single-primitive kets and two [r] cubes, V
-// from registers one row part.  Off again if the run's ket data would push
+// from registers one row part.  Column-slab classes are left out: their
+// [r] cube is too large for two copies (L >= 20), so runs would not overlap.  Off again if the run's ket data would push
 // the workgroup past the LDS limit.  Measured on the 65,536-quartet K=1
 // batches, runs of 4 against none: [dd|dd] 1.32x, [ff|ff] 1.24x, [gg|gg]
 // 1.12x (runs of 8 within 2% of 4).

@@ -152,6 +152,32 @@ HIGH_L = [((5, 5, 5, 5), 1, 3, 2), ((6, 6, 6, 6), 1, 2, 2), ((6, 5, 4, 4), 1, 2,
           ((7, 0, 7, 0), 1, 3, 2), ((8, 1, 2, 0), 2, 2, 2), ((8, 8, 4, 2), 1, 1, 2), ((7, 7, 6, 0), 1, 1, 2)]
 
 
+@pytest.mark.parametrize("cls", [(5, 5, 5, 5), (6, 6, 6, 6)])
+def test_high_l_single_primitive_at_size(ctx, cls):
+    """Column-slab classes with single-primitive pairs at a size where the
+    smaller classes take quartet runs (64 x 67 pairs; these keep one quartet
+    per workgroup, their [r] cube being too large for two copies): sampled
+    quartets (both ends of the bra list, neighbouring ket pairs, the tail)
+    against the matrix-form reference."""
+    import torch
+    from tests.ref import md_matrix
+    la, lb, lc, ld = cls
+    nbra, nket = 64, 67
+    rng = np.random.default_rng(1300 + la)
+    ls = [la, lb] * nbra + [lc, ld] * nket
+    sh = inputs.random_shells(rng, ls, 1, 4.0, 0.1, 30.0)
+    pairs = np.arange(2 * (nbra + nket), dtype=np.int32).reshape(-1, 2)
+    bra, ket = pairs[:nbra], pairs[nbra:]
+    b = ctx.basis(sh.l, sh.nprim, sh.exps, sh.coefs, sh.centers)
+    V = ctx.eri4(b, bra, ket)
+    torch.cuda.synchronize()
+    for i in (0, 37, 63):
+        for k in (0, 1, 2, 33, 65, 66):
+            got = V[i, :, :, k].cpu().numpy()
+            ref = md_matrix.shellset(sh, *bra[i], *ket[k])
+            _assert_close(got, ref.reshape(got.shape), f"{cls} runs, quartet ({i},{k})")
+
+
 @pytest.mark.parametrize("cls,K,nbra,nket", HIGH_L)
 def test_high_l_parity(ctx, cls, K, nbra, nket):
     """[hh|hh] and [ii|ii]-type classes, whose quartets the kernel splits into
