@@ -44,8 +44,9 @@ def test_deterministic_repeats_bitwise(ctx, cluster):
     J1, K1 = ctx.jkbuild(b, D, tau=TAU, deterministic=True)
     J2, K2 = ctx.jkbuild(b, D, tau=TAU, deterministic=True)
     K3 = ctx.kbuild(b, D, tau=TAU, deterministic=True)
+    J3, _ = ctx.jkbuild(b, D, want_k=False, tau=TAU, deterministic=True)  # J alone: its own buffer layout
     torch.cuda.synchronize()
-    assert torch.equal(K1, K2) and torch.equal(J1, J2) and torch.equal(K1, K3)
+    assert torch.equal(K1, K2) and torch.equal(J1, J2) and torch.equal(K1, K3) and torch.equal(J1, J3)
     assert torch.equal(K1, K1.T) and torch.equal(J1, J1.T)
 
 
