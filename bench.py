@@ -20,6 +20,7 @@ the CPU oracle's rate on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -265,12 +266,14 @@ def eri2_metric(ctx, steps):
             flops += len(A) * len(C) * model.eri3_flops(la, 0, lc, 1, 1)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    gc.disable()  # host-bound loop: no cyclic-GC pause inside the timed region
     e0.record()
     for _ in range(steps):
         for (la, lc), V in outs.items():
             ctx.eri2(a, by_l[la], by_l[lc], out=V)
     e1.record()
     torch.cuda.synchronize()
+    gc.enable()
     ms = e0.elapsed_time(e1) / steps
     nao = int(np.sum(2 * aux.l + 1))
     log(f"eri2 metric: {len(aux.l)} shells, {nao}x{nao} elements, {ms:.3f} ms ({nao * nao / (ms * 1e-3):.3e} "
@@ -390,6 +393,7 @@ def pp_small(ctx, reps=200):
     ctx.kernel_times()
     ctx.kernel_timing(True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    gc.disable()  # host-bound loop: no cyclic-GC pause inside the timed region
     t = time.perf_counter()
     start.record()
     for _ in range(reps):
@@ -397,6 +401,7 @@ def pp_small(ctx, reps=200):
     stop.record()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t) / reps
+    gc.enable()
     ctx.kernel_timing(False)
     kern = float(ctx.kernel_times().mean())
     ms = start.elapsed_time(stop) / reps
