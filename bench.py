@@ -41,7 +41,7 @@ TAU = 1e-12
 # WRITE_SIZE (x1) counters (profiles/eri4_ggK3_hbm_counters.md), valid only for
 # the kernel sources they were taken with.
 TRAFFIC = {"kernel": "eri4_kernel [gg|gg] K=3", "bytes": 1.1303e11,
-           "sources": {"eri4.hip": "43fdd93448f59f27", "device_common.h": "1d6737b5b2d84adb",
+           "sources": {"eri4.hip": "03af330b91b2ba0e", "device_common.h": "1d6737b5b2d84adb",
                        "internal.h": "4a481a7c1ef1a30c"}}
 
 
