@@ -57,6 +57,10 @@ typedef struct mderi_basis *mderi_basis_t;
 #define MDERI_FP64 0       /* everything in FP64 */
 #define MDERI_SPLIT_BF16 1 /* bra transform on the BF16 matrix cores with operands split into 7-bit
                               integer slices (see mderi_eri4); all else FP64 */
+#define MDERI_SPLIT_FP32 2 /* not built: every call returns MDERI_EUNSUPPORTED.  The FP32 matrix
+                              rate of MI355X (157.3 TFLOP/s) is twice the FP64 rate, and an FP32
+                              split with exact sums needs 12-bit slices, three per 35-bit operand,
+                              so at least six slice products: more matrix work than FP64 itself */
 
 /* Options shared by the compute calls; NULL means defaults. */
 typedef struct {

@@ -35,6 +35,7 @@ FLAG_AUTOTUNE = 2
 FLAG_SYMMETRIC = 4
 FP64 = 0
 SPLIT_BF16 = 1
+SPLIT_FP32 = 2  # declared by the ABI, not built (MDERI_EUNSUPPORTED)
 EXCHANGE = 0
 COULOMB = 1
 

@@ -130,6 +130,9 @@ def test_validation_errors(ctx):
         ctx.basis([0], [1], [-1.0], [1.0], [[0, 0, 0]])
     with pytest.raises(MderiError):  # l beyond the built maximum
         ctx.basis([9], [1], [1.0], [1.0], [[0, 0, 0]])
+    with pytest.raises(MderiError) as e:  # the FP32 split is declared but not built
+        ctx.eri4(b, bra, ket, precision=2)
+    assert e.value.status == -3
 
 
 def test_schwarz_factors_mixed_classes(ctx):
