@@ -311,6 +311,19 @@ def dfj(basis: Basis, aux: Basis, D, nthreads=0) -> np.ndarray:
     return T @ c
 
 
+def dfk(basis: Basis, aux: Basis, D, nthreads=0) -> np.ndarray:
+    """Density-fitted exchange matrix: every pair product is fitted in the
+    Coulomb metric, (ab|cd) ~ sum_PQ (ab|P) [M^{-1}]_PQ (Q|cd) with
+    M_PQ = (P|Q), and K_ac = sum_bd (ab|cd)_fit D_bd (the exchange operator of
+    Sec. 6 over the fitted integrals).  Dense assembly; numpy solves."""
+    assert basis.normalize == aux.normalize
+    T = three_index(basis, aux, nthreads)
+    M = metric(aux, nthreads)
+    nao, naux = T.shape[0], T.shape[2]
+    F = np.linalg.solve(M, T.reshape(nao * nao, naux).T).T.reshape(T.shape)  # sum_P [M^-1]_QP (P|cd)
+    return np.einsum("abQ,cdQ,bd->ac", T, F, np.asarray(D, dtype=np.float64), optimize=True)
+
+
 def fock_blocks(basis: Basis, D, blocks, which="K", tau=1e-12, nthreads=0):
     """Shell blocks of K (which="K", block (s0, s1) = K[AOs of s0, AOs of s1])
     or J (which="J") by the brute force restricted to the quartets feeding

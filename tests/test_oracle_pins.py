@@ -704,3 +704,48 @@ def test_dfj_energy_is_variational():
     Jdf = oracle.dfj(b, aux, D)
     E, Edf = float(np.sum(D * J)), float(np.sum(D * Jdf))
     assert 0.0 < Edf <= E * (1 + 1e-12)
+
+
+def test_dfk_exact_when_products_are_in_the_fitting_set():
+    """With the pair products of single-primitive s shells as the fitting set
+    every (ab| lies in its span, the fitted integrals are exact and the
+    density-fitted K equals the exact K (the oracle's brute force)."""
+    rng = np.random.default_rng(33)
+    n = 3
+    ex = np.exp(rng.uniform(np.log(0.3), np.log(3.0), n))
+    cen = rng.uniform(-1.0, 1.0, (n, 3))
+    b = oracle.Basis([0] * n, [1] * n, ex, np.ones(n), cen, 1)
+    pe, pc = [], []
+    for i in range(n):
+        for j in range(i, n):
+            pe.append(ex[i] + ex[j])
+            pc.append((ex[i] * cen[i] + ex[j] * cen[j]) / (ex[i] + ex[j]))
+    aux = oracle.Basis([0] * len(pe), [1] * len(pe), np.array(pe), np.ones(len(pe)), np.array(pc), 1)
+    C = rng.normal(size=(n, n))
+    D = C @ C.T
+    K = oracle.kbuild(b, D)
+    Kdf = oracle.dfk(b, aux, D)
+    assert np.max(np.abs(Kdf - K)) <= 1e-10 * np.max(np.abs(K))
+
+
+def test_dfk_exchange_energy_is_variational():
+    """For D = sum_k c_k c_k^T, tr(D K) = sum_kl (phi_k phi_l | phi_k phi_l) is a
+    sum of Coulomb self-energies of pair densities, and fitting each in the
+    Coulomb metric can only lower it: 0 < tr(D K_df) <= tr(D K) (mixed l,
+    incomplete fitting set); K_df is symmetric."""
+    rng = np.random.default_rng(34)
+    ls = [0, 1, 0, 2]
+    b = oracle.Basis(ls, [1] * 4, np.exp(rng.uniform(np.log(0.3), np.log(3), 4)), np.ones(4),
+                     rng.uniform(-1, 1, (4, 3)), 1)
+    aux = oracle.Basis([0, 1, 2, 0, 1, 3], [1] * 6, np.exp(rng.uniform(np.log(0.2), np.log(4), 6)), np.ones(6),
+                       rng.uniform(-1, 1, (6, 3)), 1)
+    nao = b.nao()
+    C = rng.normal(size=(nao, 3))
+    D = C @ C.T
+    K = oracle.kbuild(b, D)
+    Kdf = oracle.dfk(b, aux, D)
+    E, Edf = float(np.sum(D * K)), float(np.sum(D * Kdf))
+    assert 0.0 < Edf <= E * (1 + 1e-12)
+    assert Edf < 0.999 * E  # the set is incomplete: the fit loses something
+    assert np.max(np.abs(Kdf - Kdf.T)) <= 1e-13 * np.max(np.abs(Kdf))
+
