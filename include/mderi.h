@@ -207,6 +207,25 @@ mderi_status mderi_dfj(mderi_ctx_t ctx, mderi_basis_t basis, mderi_basis_t aux, 
                        int nao, const mderi_opts *opts, void *stream);
 
 /*
+ * Density-fitted exchange matrix (the exchange operator of Sec. 6 over
+ * integrals fitted with the 3-centre integrals Sec. 1 motivates): every pair
+ * product is fitted in the Coulomb metric of `aux`,
+ *     (ab|cd)_fit = sum_PQ (ab|P) [M^{-1}]_PQ (Q|cd) = sum_Q B'_ab,Q B'_cd,Q,
+ *     B' = B L^{-T},  M = (P|Q) = L L^T,
+ *     K_ac = sum_bd (ab|cd)_fit D_bd = sum_Q (B'_Q D B'_Q^T)_ac,
+ * with B the (ab|P) matrix of mderi_dfj, the Cholesky factor and the
+ * triangular solve by rocSOLVER / rocBLAS, B'_Q spread over all AO pairs and
+ * the two contractions as two rocBLAS GEMMs (2 nao^3 naux FLOPs each), all on
+ * the stream.  D_dev, K_dev: [nao][nao] row-major FP64 on the device, D
+ * symmetric; K is written in full and exactly symmetric.  Any D is allowed
+ * (no orbital factorisation is assumed), so the work space holds two
+ * nao x nao x naux arrays besides those of mderi_dfj: MDERI_ENOMEM when they
+ * do not fit.  Metric and synchronisation as for mderi_dfj.
+ */
+mderi_status mderi_dfk(mderi_ctx_t ctx, mderi_basis_t basis, mderi_basis_t aux, const double *D_dev, double *K_dev,
+                       int nao, const mderi_opts *opts, void *stream);
+
+/*
  * Class batch of 3-centre integrals (ab|P) (Sec. 2: the 1-centre Hermite
  * expansion of Eqs. (E1rr)-(E1-aa); the paper writes them [P|ab]).
  *

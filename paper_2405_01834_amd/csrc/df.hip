@@ -5,6 +5,8 @@
 //   gamma_Q = sum_rows B[row][Q] w_row D[a_row][b_row]      (the fitted charge)
 //   c = M^{-1} gamma                                        (library Cholesky)
 //   J[a][b] = J[b][a] = sum_Q B[row][Q] c_Q                 (every pair row)
+// and for density-fitted exchange the solved B' = B L^{-T} (M = L L^T)
+// spread over all AO pairs (df_expand) for the two GEMMs of the K build.
 // w_row = 2 for rows of a pair of two different shells (the pair stands for
 // both orders), 1 on a diagonal shell pair.
 #include <algorithm>
@@ -79,7 +81,32 @@ __global__ void __launch_bounds__(kDfThreads) df_scatter_kernel(int na, int Na, 
   }
 }
 
+// The solved (ab|P) matrix B' (column-major, rows = AO pairs of the
+// canonical shell pairs) spread over all AO pairs: Bt[(a naux + Q) nao + b] =
+// B'[row of (a, b)][Q], and the transposed element too for the rows of a pair
+// of two shells (w = 2; a diagonal shell pair holds both orders as rows).
+__global__ void __launch_bounds__(kDfThreads) df_expand_kernel(int nrow, int ncol, const double *B, const int2 *ab,
+                                                              const double *w, int nao, double *Bt) {
+  const size_t total = (size_t)nrow * ncol;
+  for (size_t e = (size_t)blockIdx.x * kDfThreads + threadIdx.x; e < total; e += (size_t)gridDim.x * kDfThreads) {
+    const int r = (int)(e % nrow), q = (int)(e / nrow);
+    const int2 x = ab[r];
+    const double v = B[e];
+    Bt[((size_t)x.x * ncol + q) * nao + x.y] = v;
+    if (w[r] > 1.0) Bt[((size_t)x.y * ncol + q) * nao + x.x] = v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_df_expand(int nrow, int ncol, const double *B, const int2 *ab, const double *w, int nao, double *Bt,
+                            hipStream_t s) {
+  const size_t total = (size_t)nrow * ncol;
+  if (!total) return hipSuccess;
+  const int grid = (int)std::min<size_t>(65536, (total + kDfThreads - 1) / kDfThreads);
+  hipLaunchKernelGGL(df_expand_kernel, dim3(grid), dim3(kDfThreads), 0, s, nrow, ncol, B, ab, w, nao, Bt);
+  return hipGetLastError();
+}
 
 hipError_t launch_df_dvec(int nrow, const int2 *ab, const double *w, const double *D, int nao, double *dvec,
                           hipStream_t s) {

@@ -190,6 +190,7 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 enum WsSlot {
   WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_ORDER,
   WS_KORDER, WS_KTMP, WS_QALL, WS_PAIRS, WS_HS, WS_HEXP, WS_HROW, WS_GPART, WS_DFB, WS_DFM, WS_DFT, WS_DFV, WS_DFI,
+  WS_DFK1, WS_DFK2, WS_DFK3,
   WS_COUNT
 };
 
@@ -2422,16 +2423,21 @@ extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, int pa
 // ---------------------------------------------------------------------------
 // density-fitted Coulomb matrix
 // ---------------------------------------------------------------------------
-extern "C" mderi_status mderi_dfj(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t aux, const double *D, double *J,
-                                  int nao, const mderi_opts *opts, void *stream) {
-  if (!c || !b || !aux) return fail(MDERI_EINVAL, "mderi_dfj: NULL context or basis");
-  if (b->ctx != c || aux->ctx != c) return fail(MDERI_EINVAL, "mderi_dfj: basis belongs to another context");
-  if (!D || !J) return fail(MDERI_EINVAL, "mderi_dfj: NULL density or output");
-  if (nao != b->nao) return fail(MDERI_EINVAL, "mderi_dfj: nao %d but the basis has %d AOs", nao, b->nao);
-  if (opts && opts->precision != 0) return fail(MDERI_EUNSUPPORTED, "mderi_dfj: precision %d", opts->precision);
-  HIP_TRY(hipSetDevice(c->device));
-  hipStream_t s = (hipStream_t)stream;
-  // canonical shell pairs (i >= j) and their AO rows in the (ab|P) matrix
+namespace {
+
+// The shared part of the density-fitted builds: the (ab|P) matrix B over the
+// canonical shell pairs (rows = AO pairs, w = 2 for pairs of two shells, 1 on
+// a diagonal shell pair) and every auxiliary AO (columns), the metric M =
+// (P|Q) from its class batches, and M's Cholesky factor L (lower, in place of
+// M), all enqueued on s.
+struct DfSetup {
+  int nrow = 0, ncol = 0;
+  double *B = nullptr, *M = nullptr, *vec = nullptr;  // vec: nrow + ncol doubles of work
+  const int2 *ab = nullptr;
+  const double *w = nullptr;
+};
+
+mderi_status df_setup(mderi_ctx *c, mderi_basis *b, mderi_basis *aux, const char *fn, hipStream_t s, DfSetup &df) {
   std::vector<int32_t> pairs;
   std::vector<int2> ab;
   std::vector<double> w;
@@ -2471,10 +2477,13 @@ extern "C" mderi_status mderi_dfj(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t 
       (st = ws_get(c, WS_DFV, sizeof(double) * ((size_t)nrow + ncol) + 64, &dV)) ||
       (st = ws_get(c, WS_DFI, ibytes, &dI)))
     return st;
-  double *dvec = (double *)dV, *gamma = dvec + nrow;
-  rocblas_int *info = (rocblas_int *)(gamma + ncol);
-  const int2 *d_ab = (const int2 *)dI;
-  const double *d_w = (const double *)((char *)dI + o_w);
+  df.nrow = nrow;
+  df.ncol = ncol;
+  df.B = (double *)dB;
+  df.M = (double *)dM;
+  df.vec = (double *)dV;
+  df.ab = (const int2 *)dI;
+  df.w = (const double *)((char *)dI + o_w);
   const int32_t *d_byl = (const int32_t *)((char *)dI + o_byl);
   if ((st = stage_begin(c, ibytes))) return st;
   size_t used = 0;
@@ -2485,8 +2494,8 @@ extern "C" mderi_status mderi_dfj(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t 
   if ((st = stage_end(c, s))) return st;
   // (ab|P) for every canonical pair and auxiliary shell
   mderi_opts o{};
-  if ((st = mderi_eri3_batch(c, b, aux, npair, pairs.data(), aux->nshell, auxidx.data(), (double *)dB,
-                             (size_t)nrow * ncol, &o, stream)))
+  if ((st = mderi_eri3_batch(c, b, aux, npair, pairs.data(), aux->nshell, auxidx.data(), df.B, (size_t)nrow * ncol,
+                             &o, s)))
     return st;
   // the metric (P|Q), class batch by class batch, scattered into M
   for (int la = 0; la <= kLmax; ++la)
@@ -2499,18 +2508,82 @@ extern "C" mderi_status mderi_dfj(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t 
         return st;
       if ((st = run_class_batch(c, sa, sc, 0, (double *)dT, nullptr, nullptr, s))) return st;
       HIP_TRY(launch_df_scatter(na, nsph(la), nc, nsph(lc), (const double *)dT, d_byl + lstart[la],
-                                d_byl + lstart[lc], aux->dev.ao_off, (double *)dM, ncol, s));
+                                d_byl + lstart[lc], aux->dev.ao_off, df.M, ncol, s));
     }
-  // fitted charge, Cholesky solve in the Coulomb metric, J
-  HIP_TRY(launch_df_dvec(nrow, d_ab, d_w, D, nao, dvec, s));
-  HIP_TRY(launch_df_gamma(nrow, ncol, (const double *)dB, dvec, gamma, s));
+  // Cholesky factor of the metric, in place
   if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success)
-    return fail(MDERI_EDEVICE, "mderi_dfj: rocblas_create_handle failed");
+    return fail(MDERI_EDEVICE, "%s: rocblas_create_handle failed", fn);
+  rocblas_int *info = (rocblas_int *)(df.vec + nrow + ncol);
   if (rocblas_set_stream(c->blas, s) != rocblas_status_success ||
-      rocsolver_dpotrf(c->blas, rocblas_fill_lower, ncol, (double *)dM, ncol, info) != rocblas_status_success ||
-      rocsolver_dpotrs(c->blas, rocblas_fill_lower, ncol, 1, (double *)dM, ncol, gamma, ncol) !=
-          rocblas_status_success)
+      rocsolver_dpotrf(c->blas, rocblas_fill_lower, ncol, df.M, ncol, info) != rocblas_status_success)
+    return fail(MDERI_EDEVICE, "%s: the metric factorisation could not be enqueued", fn);
+  return MDERI_OK;
+}
+
+mderi_status df_check(mderi_ctx *c, mderi_basis *b, mderi_basis *aux, const double *D, const double *out, int nao,
+                      const mderi_opts *opts, const char *fn) {
+  if (!c || !b || !aux) return fail(MDERI_EINVAL, "%s: NULL context or basis", fn);
+  if (b->ctx != c || aux->ctx != c) return fail(MDERI_EINVAL, "%s: basis belongs to another context", fn);
+  if (!D || !out) return fail(MDERI_EINVAL, "%s: NULL density or output", fn);
+  if (nao != b->nao) return fail(MDERI_EINVAL, "%s: nao %d but the basis has %d AOs", fn, nao, b->nao);
+  if (opts && opts->precision != 0) return fail(MDERI_EUNSUPPORTED, "%s: precision %d", fn, opts->precision);
+  return MDERI_OK;
+}
+
+}  // namespace
+
+extern "C" mderi_status mderi_dfj(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t aux, const double *D, double *J,
+                                  int nao, const mderi_opts *opts, void *stream) {
+  mderi_status st;
+  if ((st = df_check(c, b, aux, D, J, nao, opts, "mderi_dfj"))) return st;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  DfSetup df;
+  if ((st = df_setup(c, b, aux, "mderi_dfj", s, df))) return st;
+  // fitted charge gamma_Q = sum w (Q|ab) D_ab, c = M^{-1} gamma, J
+  double *dvec = df.vec, *gamma = dvec + df.nrow;
+  HIP_TRY(launch_df_dvec(df.nrow, df.ab, df.w, D, nao, dvec, s));
+  HIP_TRY(launch_df_gamma(df.nrow, df.ncol, df.B, dvec, gamma, s));
+  if (rocsolver_dpotrs(c->blas, rocblas_fill_lower, df.ncol, 1, df.M, df.ncol, gamma, df.ncol) !=
+      rocblas_status_success)
     return fail(MDERI_EDEVICE, "mderi_dfj: the metric solve could not be enqueued");
-  HIP_TRY(launch_df_j(nrow, ncol, (const double *)dB, gamma, d_ab, J, nao, s));
+  HIP_TRY(launch_df_j(df.nrow, df.ncol, df.B, gamma, df.ab, J, nao, s));
+  return MDERI_OK;
+}
+
+extern "C" mderi_status mderi_dfk(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t aux, const double *D, double *K,
+                                  int nao, const mderi_opts *opts, void *stream) {
+  mderi_status st;
+  if ((st = df_check(c, b, aux, D, K, nao, opts, "mderi_dfk"))) return st;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const size_t naux = (size_t)aux->nao, n3 = (size_t)nao * nao * naux;
+  if (naux * nao > 0x7fffffffu)
+    return fail(MDERI_EUNSUPPORTED, "mderi_dfk: %zu x %d exceeds a GEMM dimension", naux, nao);
+  DfSetup df;
+  if ((st = df_setup(c, b, aux, "mderi_dfk", s, df))) return st;
+  void *dBt, *dX, *dK;
+  if ((st = ws_get(c, WS_DFK1, sizeof(double) * n3, &dBt)) || (st = ws_get(c, WS_DFK2, sizeof(double) * n3, &dX)) ||
+      (st = ws_get(c, WS_DFK3, sizeof(double) * (size_t)nao * nao, &dK)))
+    return st;
+  double *Bt = (double *)dBt, *X = (double *)dX, *Kt = (double *)dK;
+  const double one = 1.0, half = 0.5, zero = 0.0;
+  const rocblas_int m = nao, k2 = (rocblas_int)(naux * nao);
+  // B' = B L^{-T}: the fitted integrals are (ab|cd)_fit = sum_Q B'[ab][Q] B'[cd][Q]
+  if (rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                    rocblas_diagonal_non_unit, df.nrow, df.ncol, &one, df.M, df.ncol, df.B, df.nrow) !=
+      rocblas_status_success)
+    return fail(MDERI_EDEVICE, "mderi_dfk: the triangular solve could not be enqueued");
+  // Bt[(a naux + Q) nao + b] = B'_Q[a][b] over all AO pairs, then
+  // X[(a naux + Q) nao + d] = sum_b D[d][b] B'_Q[a][b]  (one GEMM, k = nao)
+  // K~[c + nao a] = 1/2 sum_{Q,d} B'_Q[c][d] X_Q[a][d]  (one GEMM, k = naux nao)
+  // and K = K~ + K~^T = sum_Q B'_Q D B'_Q^T, exactly symmetric
+  HIP_TRY(launch_df_expand(df.nrow, df.ncol, df.B, df.ab, df.w, nao, Bt, s));
+  if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, m, k2, m, &one, D, m, Bt, m, &zero, X,
+                    m) != rocblas_status_success ||
+      rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, m, m, k2, &half, Bt, k2, X, k2,
+                    &zero, Kt, m) != rocblas_status_success)
+    return fail(MDERI_EDEVICE, "mderi_dfk: the contractions could not be enqueued");
+  HIP_TRY(launch_symmetrize(nao, Kt, K, s));
   return MDERI_OK;
 }

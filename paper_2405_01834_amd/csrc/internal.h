@@ -228,6 +228,8 @@ hipError_t launch_df_dvec(int nrow, const int2 *ab, const double *w, const doubl
 hipError_t launch_df_gamma(int nrow, int ncol, const double *B, const double *dvec, double *gamma, hipStream_t s);
 hipError_t launch_df_j(int nrow, int ncol, const double *B, const double *c, const int2 *ab, double *J, int nao,
                        hipStream_t s);
+hipError_t launch_df_expand(int nrow, int ncol, const double *B, const int2 *ab, const double *w, int nao, double *Bt,
+                            hipStream_t s);
 hipError_t launch_df_scatter(int na, int Na, int nc, int Nc, const double *V, const int *shells_a, const int *shells_c,
                              const int *ao_off, double *M, int n, hipStream_t s);
 hipError_t launch_pairs(const PairArgs &a, hipStream_t s);

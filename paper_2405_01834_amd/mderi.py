@@ -83,6 +83,8 @@ def load_library():
     L.mderi_eri2.restype = ctypes.c_int
     L.mderi_dfj.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _vp]
     L.mderi_dfj.restype = ctypes.c_int
+    L.mderi_dfk.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _vp]
+    L.mderi_dfk.restype = ctypes.c_int
     L.mderi_kbuild.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _vp]
     L.mderi_kbuild.restype = ctypes.c_int
     L.mderi_eri3_batch.argtypes = [_vp, _vp, _vp, ctypes.c_int, _ip, ctypes.c_int, _ip, _vp, ctypes.c_size_t,
@@ -257,6 +259,21 @@ class Context:
             out = torch.empty((nao, nao), dtype=torch.float64, device=D.device)
         opts = Opts(0, 0.0)
         _check(load_library().mderi_dfj(self._h, basis._h, aux._h, _vp(D.data_ptr()), _vp(out.data_ptr()), nao,
+                                        ctypes.byref(opts), _stream_handle(stream)))
+        return out
+
+    def dfk(self, basis: "Basis", aux: "Basis", D, out=None, stream=None):
+        """Density-fitted exchange matrix K_ac = sum_bd sum_PQ (ab|P) [M^-1]_PQ (Q|cd)
+        D_bd with the metric M = (P|Q) of `aux`; D torch float64 [nao, nao] on the
+        device, symmetric -> K (same shape)."""
+        import torch
+        nao = basis.nao()
+        assert D.dtype == torch.float64 and D.is_cuda and D.shape == (nao, nao)
+        D = D.contiguous()
+        if out is None:
+            out = torch.empty((nao, nao), dtype=torch.float64, device=D.device)
+        opts = Opts(0, 0.0)
+        _check(load_library().mderi_dfk(self._h, basis._h, aux._h, _vp(D.data_ptr()), _vp(out.data_ptr()), nao,
                                         ctypes.byref(opts), _stream_handle(stream)))
         return out
 
