@@ -262,6 +262,9 @@ int main() {
   expect(mderi_kbuild_grad(c, b, 7, D, D, nao, 1.0, G, nsh, 0, nullptr, nullptr) == MDERI_EINVAL, "bad pattern");
   expect(mderi_dfj(c, b, a, D, J, nao, nullptr, nullptr) == MDERI_OK, "dfj");
   expect(all_finite(host(J, nn)) && symmetric(host(J, nn), nao), "dfj finite and symmetric");
+  expect(mderi_dfk(c, b, a, D, K, nao, nullptr, nullptr) == MDERI_OK, "dfk");
+  expect(all_finite(host(K, nn)) && symmetric(host(K, nn), nao), "dfk finite and symmetric");
+  expect(mderi_dfk(c, b, a, D, K, nao + 1, nullptr, nullptr) == MDERI_EINVAL, "dfk wrong nao");
 
   // moved centres, timing, progress
   {
