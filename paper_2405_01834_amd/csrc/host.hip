@@ -188,9 +188,8 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 // context
 // ---------------------------------------------------------------------------
 enum WsSlot {
-  WS_PP_BRA, WS_PP_KET, WS_OFF_BRA, WS_OFF_KET, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_IDX, WS_ORDER,
-  WS_KORDER, WS_KTMP, WS_QALL, WS_PAIRS, WS_HS, WS_HEXP, WS_HROW, WS_GPART, WS_DFB, WS_DFM, WS_DFT, WS_DFV, WS_DFI,
-  WS_DFK1, WS_DFK2, WS_DFK3,
+  WS_META, WS_G_BRA, WS_G_KET, WS_H_BRA, WS_H_KET, WS_DIAG, WS_KTMP, WS_QALL, WS_PAIRS, WS_HS, WS_HEXP, WS_HROW,
+  WS_GPART, WS_DFB, WS_DFM, WS_DFT, WS_DFV, WS_DFI, WS_DFK1, WS_DFK2, WS_DFK3,
   WS_COUNT
 };
 
@@ -932,7 +931,7 @@ mderi_status run_class_batch(mderi_ctx *c, const Side &bra, const Side &ket, int
     meta_bytes += (pt.bytes + 255) & ~(size_t)255;
   }
   void *d_meta, *d_Gb, *d_Gk, *d_Hb, *d_Hk;
-  if ((st = region(WS_PP_BRA, meta_bytes, &d_meta)) ||
+  if ((st = region(WS_META, meta_bytes, &d_meta)) ||
       (st = region(WS_G_BRA, sizeof(double) * 4 * ppb.size(), &d_Gb)) ||
       (st = region(WS_G_KET, sizeof(double) * 4 * ppk.size(), &d_Gk)) ||
       (st = region(WS_H_BRA, sizeof(double) * (size_t)Hb_rows * Nb_pad * ppb.size(), &d_Hb)) ||
