@@ -40,9 +40,9 @@ TAU = 1e-12
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2) and
 # WRITE_SIZE (x1) counters (profiles/eri4_ggK3_hbm_counters.md), valid only for
 # the kernel sources they were taken with.
-TRAFFIC = {"kernel": "eri4_kernel [gg|gg] K=3", "bytes": 1.1303e11,
+TRAFFIC = {"kernel": "eri4_kernel [gg|gg] K=3", "bytes": 1.1301e11,
            "sources": {"eri4.hip": "03af330b91b2ba0e", "device_common.h": "1d6737b5b2d84adb",
-                       "internal.h": "4a481a7c1ef1a30c"}}
+                       "internal.h": "c8762f57546faf41"}}
 
 
 def measured_traffic(kernel):
