@@ -71,8 +71,9 @@ typedef struct {
   int split_slices;   /* MDERI_SPLIT_BF16: 7-bit slices per operand, 5..7 (0 = default 6) */
   int tile_variant;   /* mderi_eri4, FP64: 0 = the planned (or tuned) work split; v > 0 = the v-th of
                          the splits mderi_eri4_tile_variants counts for the batch */
-  int deterministic;  /* mderi_jkbuild / mderi_kbuild: 1 = bitwise repeatable J and K (fixed-point
-                         integer accumulation, see mderi_jkbuild); 0 = FP64 atomics (default) */
+  int deterministic;  /* mderi_jkbuild / mderi_kbuild / mderi_kbuild_grad: 1 = bitwise repeatable
+                         results (fixed-point integer accumulation, see those calls); 0 = FP64
+                         atomics (default) */
 } mderi_opts;
 
 #define MDERI_FLAG_GRAPH 1    /* capture the call's launches in a hipGraph, replay it on identical calls */
@@ -398,9 +399,13 @@ mderi_status mderi_tune_load(mderi_ctx_t ctx, const char *path_host);
  * overwrites it, 1 adds to it.  The exchange energy of mderi_jkbuild,
  * tr(D K[D]), is pattern MDERI_EXCHANGE with Wl = Wr = D and scale 1; its
  * Coulomb energy tr(D J[D]) is MDERI_COULOMB with Wl = Wr = D.
- * Synchronisation and screening as for mderi_jkbuild.  The gradient sums
- * use FP64 atomics (last bits vary from run to run); opts->deterministic = 1
- * is refused with MDERI_EUNSUPPORTED.
+ * Synchronisation and screening as for mderi_jkbuild.  By default the
+ * gradient sums use FP64 atomics (last bits vary from run to run).  With
+ * opts->deterministic = 1 every contribution v is added as |v| 2^80 in four
+ * 32-bit digits (weights 2^(32k-80), so |v| < 2^47 in steps of 2^-80), each
+ * with v's sign into its own 64-bit word by integer atomics; the words are
+ * summed over the partial copies as integers and the total rounded once, so
+ * the result is the same bits on every run (work space four times larger).
  */
 mderi_status mderi_kbuild_grad(mderi_ctx_t ctx, mderi_basis_t basis, int pattern, const double *Wl_dev,
                                const double *Wr_dev, int nao, double scale, double *grad_dev, int natom, int accumulate,

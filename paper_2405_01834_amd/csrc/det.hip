@@ -1,4 +1,5 @@
-// det.hip -- the order-independent accumulation of the J and K builds.
+// det.hip -- the order-independent accumulation of the J and K builds and
+// of the gradient.
 // Every image v reaching an element of K' or J' is scaled by a power of two
 // s and held as the fixed-point number floor(v s) + f 2^-32, f = the rounded
 // fraction, in two 64-bit integer words that integer atomics add; integer
@@ -76,6 +77,40 @@ __global__ void __launch_bounds__(256) symmetrize_fixed_kernel(int n, const unsi
   out[e] = (fixed_value(in + 2 * e) + fixed_value(in + 2 * (c * n + r))) * inv;
 }
 
+// Gradient copies in four-digit fixed point (digit k of weight 2^(32 k - 80),
+// each word the signed sum of that digit over the adds): the copies are
+// summed word by word as integers, the carries moved up (arithmetic shifts),
+// a negative total negated digit-wise so its magnitude is a sum of
+// non-negative terms, and the magnitude rounded once to double.
+__global__ void __launch_bounds__(256) sum_copies_fixed_kernel(int n, int copies,
+                                                               const unsigned long long *__restrict__ in,
+                                                               double *__restrict__ out, int accumulate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  long long w[4] = {0, 0, 0, 0};
+  for (int c = 0; c < copies; ++c)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] += (long long)in[4 * ((size_t)c * n + i) + k];
+  const long long m32 = 0xffffffffll;
+  auto carry = [&]() {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      w[k + 1] += w[k] >> 32;
+      w[k] &= m32;
+    }
+  };
+  carry();  // w[0..2] in [0, 2^32), w[3] signed
+  const bool neg = w[3] < 0;
+  if (neg) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = -w[k];
+    carry();
+  }
+  const double mag = (double)w[3] * 0x1p16 + (double)w[2] * 0x1p-16 + (double)w[1] * 0x1p-48 + (double)w[0] * 0x1p-80;
+  const double v = neg ? -mag : mag;
+  out[i] = accumulate ? out[i] + v : v;
+}
+
 __global__ void zero_u64_kernel(size_t n, unsigned long long *__restrict__ x) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
     x[e] = 0ull;
@@ -97,6 +132,13 @@ hipError_t launch_symmetrize_fixed(int n, const unsigned long long *in, const do
   if (!tot) return hipSuccess;
   hipLaunchKernelGGL(symmetrize_fixed_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, in, scale,
                      out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_copies_fixed(int n, int copies, const unsigned long long *in, double *out, int accumulate,
+                                   hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sum_copies_fixed_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, copies, in, out, accumulate);
   return hipGetLastError();
 }
 

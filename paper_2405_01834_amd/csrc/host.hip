@@ -1871,6 +1871,7 @@ struct KxJob {
   double scale = 1.0;
   double *gpart = nullptr;
   int gcopies = 1, gstride = 0;
+  int gfixed = 0;  // deterministic: gpart holds four-digit fixed-point words
 };
 
 // Per class: its significant pairs (sorted by decreasing Q), sizes, and the
@@ -2231,6 +2232,7 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
     ar.grad = job.gpart;
     ar.gcopies = job.gcopies;
     ar.gstride = job.gstride;
+    ar.gfixed = job.gfixed;
     ar.atom = b->dev.atom;
     ar.exps = b->dev.exps;
     memcpy(img.bytes.data() + g.o_blocks, g.blks.data(), sizeof(KxBlock) * g.blks.size());
@@ -2381,8 +2383,6 @@ extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, int pa
                                           int accumulate, const mderi_opts *opts, void *stream) {
   mderi_status st;
   if ((st = check_density("mderi_kbuild_grad", c, b, Wl, nao, opts))) return st;
-  if (opts && opts->deterministic)
-    return fail(MDERI_EUNSUPPORTED, "mderi_kbuild_grad: the deterministic mode covers the J and K builds only");
   if (!Wr) return fail(MDERI_EINVAL, "mderi_kbuild_grad: NULL Wr");
   if (pattern != MDERI_EXCHANGE && pattern != MDERI_COULOMB)
     return fail(MDERI_EINVAL, "mderi_kbuild_grad: pattern %d", pattern);
@@ -2401,9 +2401,12 @@ extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, int pa
   // into grad at the end, so the atomics of many short flushes do not queue
   // on the same 3 natom addresses
   constexpr int kGradCopies = 512;
+  // deterministic: four 64-bit digit words per element instead of one double
+  const bool det = opts && opts->deterministic;
+  const size_t nwords = (size_t)kGradCopies * 3 * natom * (det ? 4 : 1);
   void *d_gpart = nullptr;
-  if ((st = ws_get(c, WS_GPART, sizeof(double) * (size_t)kGradCopies * 3 * natom, &d_gpart))) return st;
-  HIP_TRY(launch_zero((size_t)kGradCopies * 3 * natom, (double *)d_gpart, s));
+  if ((st = ws_get(c, WS_GPART, sizeof(double) * nwords, &d_gpart))) return st;
+  HIP_TRY(det ? launch_zero_u64(nwords, (unsigned long long *)d_gpart, s) : launch_zero(nwords, (double *)d_gpart, s));
   KxJob job;
   job.grad = true;
   job.wl = Wl;
@@ -2414,8 +2417,13 @@ extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, int pa
   job.gpart = (double *)d_gpart;
   job.gcopies = kGradCopies;
   job.gstride = 3 * natom;
+  job.gfixed = det ? 1 : 0;
   if ((st = run_kx(c, b, ps, tau, job, s))) return st;
-  HIP_TRY(launch_sum_copies(3 * natom, kGradCopies, (const double *)d_gpart, grad, s, accumulate ? 1 : 0));
+  if (det)
+    HIP_TRY(launch_sum_copies_fixed(3 * natom, kGradCopies, (const unsigned long long *)d_gpart, grad,
+                                    accumulate ? 1 : 0, s));
+  else
+    HIP_TRY(launch_sum_copies(3 * natom, kGradCopies, (const double *)d_gpart, grad, s, accumulate ? 1 : 0));
   return MDERI_OK;
 }
 

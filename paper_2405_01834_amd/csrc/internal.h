@@ -213,6 +213,7 @@ struct KxArgs {
   double scale;
   double *grad;
   int gcopies, gstride;
+  int gfixed;             // deterministic: grad holds four 64-bit digit words per element (see grad_add)
   const int *atom;
   const double *exps;     // basis exponents
   // per-wave LDS layout (offsets in doubles from the wave's base)
@@ -248,6 +249,10 @@ hipError_t launch_symmetrize_fixed(int n, const unsigned long long *in, const do
                                    hipStream_t s);
 // x[0..n) = 0 for 64-bit integers.
 hipError_t launch_zero_u64(size_t n, unsigned long long *x, hipStream_t s);
+// out[i] (+)= the sum over c < copies of the fixed-point values in[c n + i]
+// (four digit words each, value = sum_k W_k 2^(32 k - 80)), summed as integers.
+hipError_t launch_sum_copies_fixed(int n, int copies, const unsigned long long *in, double *out, int accumulate,
+                                   hipStream_t s);
 // x[0..n) = 0 with a plain kernel (no memset node, capture-safe).
 hipError_t launch_zero(size_t n, double *x, hipStream_t s);
 // out[i] = sum_c in[c n + i] for i < n, c < copies (added to out[i] when accumulate).

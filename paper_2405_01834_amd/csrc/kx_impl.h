@@ -269,6 +269,32 @@ __device__ __forceinline__ void image_add(double *m, size_t e, double v, bool fi
   if (lo) atomicAdd(p + 1, (unsigned long long)lo);
 }
 
+// Adds v to element e of the wave's gradient copy: an FP64 atomic, or in the
+// deterministic mode |v| 2^80 as four 32-bit digits (weights 2^(32 k - 80),
+// k = 0..3: |v| < 2^47 in steps of 2^-80), each added with v's sign to its
+// own 64-bit word by an integer atomic; integer sums do not depend on the
+// order of the adds (digits that are zero are skipped).
+__device__ __forceinline__ void grad_add(const KxArgs &g, size_t e, double v) {
+  if (!g.gfixed) {
+    atomicAdd(&g.grad[e], v);
+    return;
+  }
+  unsigned long long *p = (unsigned long long *)g.grad + 4 * e;
+  const double t = fabs(v) * 0x1p-16;
+  const double d3 = floor(t);
+  double r = (t - d3) * 0x1p32;  // exact: 0 <= t - d3 < 1
+  const double d2 = floor(r);
+  r = (r - d2) * 0x1p32;
+  const double d1 = floor(r);
+  r = (r - d1) * 0x1p32;
+  const double d0 = rint(r);
+  const long long sg = v < 0.0 ? -1 : 1;
+  if (d3 != 0.0) atomicAdd(p + 3, (unsigned long long)(sg * (long long)d3));
+  if (d2 != 0.0) atomicAdd(p + 2, (unsigned long long)(sg * (long long)d2));
+  if (d1 != 0.0) atomicAdd(p + 1, (unsigned long long)(sg * (long long)d1));
+  if (d0 != 0.0) atomicAdd(p, (unsigned long long)(sg * (long long)d0));
+}
+
 // The images of one quartet into K' / J' (one global atomic per element).
 __device__ __forceinline__ void digest_flush(const KxArgs &g, const KxBlock &a, int i, int k, int si, int sj, int sk,
                                              int sl, const double *img, int lane) {
@@ -625,7 +651,7 @@ __device__ __forceinline__ void quartet(const KxArgs &g, const KxBlock &a, int i
       const PrimPair pr = a.B_pp[bp0];
       const double zc = g.exps[pr.pa], zd = g.exps[pr.pb], dq = -P;
       const double val = lane < 3 ? fma(zc / (zc + zd), dq, r) : fma(zd / (zc + zd), dq, -r);
-      atomicAdd(&g.grad[(size_t)(blockIdx.x % g.gcopies) * g.gstride + 3 * g.atom[lane < 3 ? sk : sl] + x], val);
+      grad_add(g, (size_t)(blockIdx.x % g.gcopies) * g.gstride + 3 * g.atom[lane < 3 ? sk : sl] + x, val);
     }
   }
   lds_wave_sync();  // the next quartet may overwrite the wave's LDS
@@ -649,7 +675,7 @@ __device__ __forceinline__ void flush_grad(const KxArgs &g, int si, int sj, doub
     for (int m = 1; m < 6; ++m)
       if (lane == m) val = tot[m];
     const int at = g.atom[lane < 3 ? si : sj];
-    atomicAdd(&g.grad[(size_t)(blockIdx.x % g.gcopies) * g.gstride + 3 * at + (lane % 3)], val);
+    grad_add(g, (size_t)(blockIdx.x % g.gcopies) * g.gstride + 3 * at + (lane % 3), val);
   }
 }
 
@@ -710,7 +736,7 @@ __device__ __forceinline__ void flush_run(const KxArgs &g, const KxBlock &a, int
     const PrimPair pr = a.A_pp[a.A_off[i]];
     const double za = g.exps[pr.pa], zb = g.exps[pr.pb];
     const double val = lane < 3 ? fma(za / (za + zb), P, r) : fma(zb / (za + zb), P, -r);
-    atomicAdd(&g.grad[(size_t)(blockIdx.x % g.gcopies) * g.gstride + 3 * g.atom[lane < 3 ? si : sj] + x], val);
+    grad_add(g, (size_t)(blockIdx.x % g.gcopies) * g.gstride + 3 * g.atom[lane < 3 ? si : sj] + x, val);
   }
 #pragma unroll
   for (int m = 0; m < 6; ++m) gpart[m] = 0.0;

@@ -365,12 +365,13 @@ class Context:
         return buf[:n.value].copy()
 
     def kbuild_grad(self, basis: "Basis", Wl, natom, Wr=None, pattern=EXCHANGE, scale=1.0, tau=1e-12, out=None,
-                    accumulate=False, symmetric=None, stream=None):
+                    accumulate=False, symmetric=None, stream=None, deterministic=False):
         """dE/dR of E = scale sum W_abcd (ab|cd) with W = Wl_ac Wr_bd (pattern
         EXCHANGE; Wl = Wr = D gives tr(D K[D])) or Wl_ab Wr_cd (COULOMB), W
         held fixed -> torch float64 [natom, 3] (atoms as mapped by the basis'
         atom list).  Wr defaults to Wl; symmetric (default: Wr is None, the
-        density case) declares Wl = Wr symmetric (MDERI_FLAG_SYMMETRIC)."""
+        density case) declares Wl = Wr symmetric (MDERI_FLAG_SYMMETRIC).
+        deterministic: fixed-point integer accumulation, the same bits on every run."""
         import torch
         nao = basis.nao()
         if symmetric is None:
@@ -381,7 +382,7 @@ class Context:
         Wl, Wr = Wl.contiguous(), Wr.contiguous()
         if out is None:
             out = torch.zeros((natom, 3), dtype=torch.float64, device=Wl.device)
-        opts = Opts(0, float(tau), FLAG_SYMMETRIC if (symmetric and Wr is Wl) else 0)
+        opts = Opts(0, float(tau), FLAG_SYMMETRIC if (symmetric and Wr is Wl) else 0, 0, 0, int(bool(deterministic)))
         _check(load_library().mderi_kbuild_grad(self._h, basis._h, int(pattern), _vp(Wl.data_ptr()),
                                                 _vp(Wr.data_ptr()), nao, float(scale), _vp(out.data_ptr()),
                                                 int(natom), int(bool(accumulate)), ctypes.byref(opts),

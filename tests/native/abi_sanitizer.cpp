@@ -259,6 +259,16 @@ int main() {
   expect(mderi_kbuild_grad(c, b, MDERI_COULOMB, D, K, nao, 0.5, G, nsh, 1, nullptr, nullptr) == MDERI_OK,
          "kbuild_grad coulomb, unsymmetric weights, accumulate");
   expect(all_finite(host(G, 3 * (size_t)nsh)), "gradient finite");
+  {
+    mderi_opts o{};
+    o.deterministic = 1;
+    double *G2 = dev(3 * (size_t)nsh);
+    expect(mderi_kbuild_grad(c, b, MDERI_EXCHANGE, D, D, nao, 1.0, G, nsh, 0, &o, nullptr) == MDERI_OK &&
+               mderi_kbuild_grad(c, b, MDERI_EXCHANGE, D, D, nao, 1.0, G2, nsh, 0, &o, nullptr) == MDERI_OK,
+           "kbuild_grad deterministic");
+    expect(host(G, 3 * (size_t)nsh) == host(G2, 3 * (size_t)nsh), "deterministic gradient repeats bitwise");
+    (void)hipFree(G2);
+  }
   expect(mderi_kbuild_grad(c, b, 7, D, D, nao, 1.0, G, nsh, 0, nullptr, nullptr) == MDERI_EINVAL, "bad pattern");
   expect(mderi_dfj(c, b, a, D, J, nao, nullptr, nullptr) == MDERI_OK, "dfj");
   expect(all_finite(host(J, nn)) && symmetric(host(J, nn), nao), "dfj finite and symmetric");

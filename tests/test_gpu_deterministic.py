@@ -7,8 +7,9 @@ on the order in which the waves add them):
   * they agree with the FP64-atomic path within 1e-13 of max |K| / max |J|
     (the fixed-point rounding, B 2^-95 per image, is far below that);
   * on a small molecule they match the oracle's brute force at 1e-12;
-  * a density of zeros gives zeros; the gradient refuses the mode and values
-    other than 0 and 1 are rejected.
+  * a density of zeros gives zeros; values other than 0 and 1 are rejected;
+  * the gradient in the same mode (four-digit fixed point): bitwise
+    repeatable and within 1e-12 of the FP64-atomic gradient.
 Also the workspace cap (mderi_set_workspace_limit), the way to make the
 library's allocation failures (MDERI_ENOMEM) happen on purpose."""
 import ctypes
@@ -101,7 +102,34 @@ def test_deterministic_refused_where_unsupported(ctx, cluster):
     with pytest.raises(MderiError):
         _check(lib.mderi_kbuild_grad(ctx._h, b._h, 0, vp(D.data_ptr()), vp(D.data_ptr()), nao,
                                      ctypes.c_double(1.0), vp(g.data_ptr()), 12, 0,
-                                     ctypes.byref(Opts(0, TAU, 0, 0, 0, 1)), None))
+                                     ctypes.byref(Opts(0, TAU, 0, 0, 0, 5)), None))
+
+
+def test_deterministic_gradient(ctx, cluster):
+    """The exchange gradient in the deterministic mode: two runs give the
+    same bits; it agrees with the FP64-atomic gradient within 1e-12 of max |g|
+    (the 2^-80 steps of the fixed point are far below that), and a Coulomb
+    pattern with unsymmetric weights and accumulate as well."""
+    import torch
+    b, D = cluster
+    g1 = ctx.kbuild_grad(b, D, 12, tau=TAU, deterministic=True)
+    g2 = ctx.kbuild_grad(b, D, 12, tau=TAU, deterministic=True)
+    ga = ctx.kbuild_grad(b, D, 12, tau=TAU)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+    assert float((g1 - ga).abs().max()) <= 1e-12 * float(ga.abs().max())
+    rng = np.random.default_rng(44)
+    W = torch.tensor(rng.normal(size=tuple(D.shape)), device="cuda")
+    base = torch.tensor(rng.normal(size=(12, 3)), device="cuda")
+    outs = []
+    for det in (True, True, False):
+        o = base.clone()
+        ctx.kbuild_grad(b, D, 12, Wr=W, pattern=1, scale=0.5, tau=TAU, out=o, accumulate=True, deterministic=det)
+        outs.append(o)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+    scale = float((outs[2] - base).abs().max())
+    assert float((outs[0] - outs[2]).abs().max()) <= 1e-12 * scale
 
 
 def test_workspace_limit_gives_enomem_and_recovers(need_gpu):
