@@ -40,9 +40,9 @@ TAU = 1e-12
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2) and
 # WRITE_SIZE (x1) counters (profiles/eri4_ggK3_hbm_counters.md), valid only for
 # the kernel sources they were taken with.
-TRAFFIC = {"kernel": "eri4_kernel [gg|gg] K=3", "bytes": 1.1301e11,
+TRAFFIC = {"kernel": "eri4_kernel [gg|gg] K=3", "bytes": 1.1302e11,
            "sources": {"eri4.hip": "03af330b91b2ba0e", "device_common.h": "1d6737b5b2d84adb",
-                       "internal.h": "c8762f57546faf41"}}
+                       "internal.h": "1f28521e37d5a89b"}}
 
 
 def measured_traffic(kernel):
