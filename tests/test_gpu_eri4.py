@@ -98,6 +98,28 @@ def test_single_primitive_paths(ctx, cls, Kb, Kk, nbra, nket):
             _assert_close(V[:nb].cpu().numpy(), ref, f"{cls} {nbra}x{nket} variant {v}")
 
 
+@pytest.mark.parametrize("seed", range(24))
+def test_random_class_batches(ctx, seed):
+    """Seeded random class batches: l of each centre 0..3, 1..3 primitives
+    per shell drawn per pair, 1..9 bra and ket pairs, near and far pairs in
+    an 8-bohr cube, normalised or bare primitives; every element against the
+    oracle.  Covers the plain, single-primitive and V-from-registers paths on
+    shapes the fixed cases do not pick."""
+    rng = np.random.default_rng(5000 + seed)
+    la, lb, lc, ld = (int(x) for x in rng.integers(0, 4, 4))
+    nbra, nket = (int(x) for x in rng.integers(1, 10, 2))
+    Kb = int(rng.integers(1, 4)) if seed % 3 else 1
+    Kk = int(rng.integers(1, 4)) if seed % 4 else 1
+    ls = [la, lb] * nbra + [lc, ld] * nket
+    Ks = [Kb] * (2 * nbra) + [Kk] * (2 * nket)
+    if seed % 5 == 0:  # contraction degrees that differ from pair to pair
+        Ks = [int(x) for x in rng.integers(1, 4, len(ls))]
+    sh = inputs.random_shells(rng, ls, Ks, 8.0, 0.1, 50.0)
+    pairs = np.arange(2 * (nbra + nket), dtype=np.int32).reshape(-1, 2)
+    got, ref = _both(ctx, sh, pairs[:nbra], pairs[nbra:], normalize=int(seed % 7 != 0))
+    _assert_close(got, ref, f"seed {seed}: ({la}{lb}|{lc}{ld}) {nbra}x{nket}")
+
+
 def test_mixed_contraction_degrees(ctx):
     """Pairs of one class may have different primitive counts."""
     rng = np.random.default_rng(5)
