@@ -290,11 +290,15 @@ mderi_status mderi_schwarz(mderi_ctx_t ctx, mderi_basis_t basis, int npair, cons
  * J_dev or K_dev may be NULL (that matrix is not built), not both; the
  * matrices built are overwritten.  energy_dev (device, may be NULL)
  * receives {tr(D J), tr(D K)} (a NULL matrix gives 0).
- * The call computes the Schwarz factors of all canonical shell pairs on the
- * stream and synchronises it once, to sort the significant pairs of each
- * class by Q on the host (so the admissible partners of every pair are a
- * prefix of the sorted list); everything after that is enqueued
- * asynchronously.  Work space grows with the number of significant pairs
+ * The first call for a basis, geometry and tau computes the Schwarz
+ * factors of all canonical shell pairs on the stream and synchronises it
+ * once, to sort the significant pairs of each class by Q on the host (so
+ * the admissible partners of every pair are a prefix of the sorted list);
+ * the context keeps that selection for the two most recent (basis,
+ * geometry, tau) keys, so later calls on an unchanged basis (the rounds of
+ * an SCF) do not synchronise at all.  Everything after the selection is
+ * enqueued asynchronously.  mderi_basis_set_centers starts a new geometry
+ * (the next call selects again).  Work space grows with the number of significant pairs
  * (pair data of every class in both roles).  By default the sums of the
  * images use FP64 atomics, so the last bits of J and K vary from run to run.
  * With opts->deterministic = 1 every image is scaled by 2^e and added as a
@@ -319,7 +323,8 @@ mderi_status mderi_kbuild(mderi_ctx_t ctx, mderi_basis_t basis, const double *D_
  * bohr), copied on `stream` (asynchronous, the caller keeps centers_dev
  * alive until the stream reaches the copy).  Later calls on that stream
  * see the new geometry; shells, exponents, coefficients and the atom map
- * stay. */
+ * stay.  The pair selections the context cached for this basis are
+ * dropped. */
 mderi_status mderi_basis_set_centers(mderi_basis_t basis, const double *centers_dev, void *stream);
 
 /*

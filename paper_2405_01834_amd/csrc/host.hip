@@ -13,6 +13,7 @@
 #include <map>
 #include <array>
 #include <numeric>
+#include <memory>
 #include <mutex>
 
 #include <rocblas/rocblas.h>
@@ -209,6 +210,11 @@ static __device__ __align__(256) char scratch[kScratchBytes];
 // allocation-free entry point can upload its metadata without allocating.
 constexpr size_t kStageInitBytes = (size_t)4 << 20;  // per slot
 constexpr int kStageSlots = 4;
+constexpr size_t kPairCacheKeys = 2;  // pair selections a context keeps
+
+namespace {
+struct PairSets;  // a Schwarz pair selection (defined with select_pairs)
+}  // namespace
 
 struct mderi_ctx {
   int device = 0;
@@ -239,11 +245,24 @@ struct mderi_ctx {
   uint64_t next_serial = 1;
   char *scratch = nullptr;  // device address of `scratch` on this context's device
   rocblas_handle blas = nullptr;  // library handle of the density-fitting solve (created on first use)
+  // Schwarz pair selections of the last kPairCacheKeys (basis upload,
+  // geometry, tau) keys, most recent last: a J/K or gradient call on a basis
+  // whose centres have not moved since reuses its selection without the
+  // device-to-host copy and the wait it needs.  Upload serials are never
+  // reused, so an entry of a freed basis matches nothing; it stays (host
+  // memory only) until newer keys push it out or the context is destroyed.
+  struct PairCacheEntry {
+    uint64_t serial, geom;
+    double tau;
+    std::shared_ptr<const PairSets> ps;
+  };
+  std::vector<PairCacheEntry> pair_cache;
 };
 
 struct mderi_basis {
   mderi_ctx *ctx = nullptr;
   uint64_t serial = 0;  // unique per upload (keys cached task plans)
+  uint64_t geom = 0;    // bumped whenever the centres change (keys cached pair selections)
   int nshell = 0, nao = 0;
   std::vector<int> l, K, poff, atom, ao_off;
   DevBasis dev;
@@ -1238,8 +1257,9 @@ namespace {
 
 // Canonical shell pairs (l_i > l_j, or l_i == l_j and i >= j) whose Schwarz
 // factor passes Q_ij Q_max >= tau, grouped by class (l_i, l_j) and expanded
-// into primitive pairs.  Synchronises the stream once (the selection runs on
-// the host).
+// into primitive pairs.  The selection runs on the host: the first call for a
+// (basis upload, geometry, tau) key synchronises the stream once; later calls
+// with the same key take the context's cached copy and do not wait.
 struct PairSets {
   std::vector<int32_t> pairs;          // all canonical pairs [np][2]
   std::vector<double> q;               // their Schwarz factors
@@ -1247,7 +1267,7 @@ struct PairSets {
   std::vector<Side> sides;             // their primitive expansion
 };
 
-mderi_status select_pairs(mderi_ctx *c, mderi_basis *b, double tau, hipStream_t s, PairSets &ps) {
+mderi_status select_pairs_uncached(mderi_ctx *c, mderi_basis *b, double tau, hipStream_t s, PairSets &ps) {
   for (int i = 0; i < b->nshell; ++i)
     for (int j = 0; j < b->nshell; ++j)
       if (b->l[i] > b->l[j] || (b->l[i] == b->l[j] && i >= j)) {
@@ -1284,6 +1304,30 @@ mderi_status select_pairs(mderi_ctx *c, mderi_basis *b, double tau, hipStream_t 
     if ((st = expand_pairs(b, (int)ps.cls[ci].size(), sub.data(), "pairs", &sd.la, &sd.lb, sd.pp, sd.off))) return st;
   }
   return MDERI_OK;
+}
+
+mderi_status select_pairs(mderi_ctx *c, mderi_basis *b, double tau, hipStream_t s,
+                          std::shared_ptr<const PairSets> &out) {
+  auto &pc = c->pair_cache;
+  for (size_t i = 0; i < pc.size(); ++i)
+    if (pc[i].serial == b->serial && pc[i].geom == b->geom && pc[i].tau == tau) {
+      out = pc[i].ps;
+      if (i + 1 != pc.size()) std::rotate(pc.begin() + i, pc.begin() + i + 1, pc.end());
+      return MDERI_OK;
+    }
+  auto ps = std::make_shared<PairSets>();
+  mderi_status st;
+  if ((st = select_pairs_uncached(c, b, tau, s, *ps))) return st;
+  if (pc.size() >= kPairCacheKeys) pc.erase(pc.begin());
+  pc.push_back({b->serial, b->geom, tau, ps});
+  out = ps;
+  return MDERI_OK;
+}
+
+void drop_pair_selections(mderi_basis *b) {
+  auto &pc = b->ctx->pair_cache;
+  pc.erase(std::remove_if(pc.begin(), pc.end(), [&](const mderi_ctx::PairCacheEntry &e) { return e.serial == b->serial; }),
+           pc.end());
 }
 
 mderi_status check_density(const char *fn, mderi_ctx *c, mderi_basis *b, const double *D, int nao,
@@ -2330,8 +2374,9 @@ extern "C" mderi_status mderi_jkbuild(mderi_ctx_t c, mderi_basis_t b, const doub
   const double tau = opt_tau(opts);
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
-  PairSets ps;
-  if ((st = select_pairs(c, b, tau, s, ps))) return st;
+  std::shared_ptr<const PairSets> psel;
+  if ((st = select_pairs(c, b, tau, s, psel))) return st;
+  const PairSets &ps = *psel;
   const size_t nn = (size_t)nao * nao;
   // deterministic: 2 64-bit words per element and the scale; else one double
   const bool det = opts && opts->deterministic;
@@ -2377,6 +2422,9 @@ extern "C" mderi_status mderi_basis_set_centers(mderi_basis_t b, const double *c
   if (!b) return fail(MDERI_EINVAL, "mderi_basis_set_centers: NULL basis");
   if (!centers) return fail(MDERI_EINVAL, "mderi_basis_set_centers: NULL centres");
   HIP_TRY(hipSetDevice(b->ctx->device));
+  // the cached pair selections of the old geometry no longer hold
+  ++b->geom;
+  drop_pair_selections(b);
   HIP_TRY(hipMemcpyAsync(b->dev.centers, centers, sizeof(double) * 3 * (size_t)b->nshell, hipMemcpyDeviceToDevice,
                          (hipStream_t)stream));
   return MDERI_OK;
@@ -2399,8 +2447,9 @@ extern "C" mderi_status mderi_kbuild_grad(mderi_ctx_t c, mderi_basis_t b, int pa
   const double tau = opt_tau(opts);
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
-  PairSets ps;
-  if ((st = select_pairs(c, b, tau, s, ps))) return st;
+  std::shared_ptr<const PairSets> psel;
+  if ((st = select_pairs(c, b, tau, s, psel))) return st;
+  const PairSets &ps = *psel;
   // the waves add into kGradCopies partial gradients (by workgroup), summed
   // into grad at the end, so the atomics of many short flushes do not queue
   // on the same 3 natom addresses
