@@ -203,6 +203,13 @@ mderi_status mderi_eri2(mderi_ctx_t ctx, mderi_basis_t basis, int na, const int3
  * caller's to prune; the solve does not report it and J is then undefined).
  * Device workspace grows to hold the npairrow x naux (ab|P) matrix and the
  * naux x naux metric.  The (ab|P) plan's first call synchronises the stream.
+ * The context keeps these factors for the next mderi_dfj / mderi_dfk call:
+ * when it has the same two bases and neither was moved since
+ * (mderi_basis_set_centers), the 3-centre integrals, the metric and its
+ * factorisation are not recomputed, so the calls of an SCF's later rounds
+ * are a few matrix-vector products (after a mderi_dfk they use the B L^-T
+ * that call left in place of B, which gives the same J without the solve).
+ * Another basis pair or mderi_set_workspace_limit drops them.
  */
 mderi_status mderi_dfj(mderi_ctx_t ctx, mderi_basis_t basis, mderi_basis_t aux, const double *D_dev, double *J_dev,
                        int nao, const mderi_opts *opts, void *stream);
@@ -221,7 +228,9 @@ mderi_status mderi_dfj(mderi_ctx_t ctx, mderi_basis_t basis, mderi_basis_t aux, 
  * symmetric; K is written in full and exactly symmetric.  Any D is allowed
  * (no orbital factorisation is assumed), so the work space holds two
  * nao x nao x naux arrays besides those of mderi_dfj: MDERI_ENOMEM when they
- * do not fit.  Metric and synchronisation as for mderi_dfj.
+ * do not fit.  Metric, synchronisation and the kept factors as for
+ * mderi_dfj; a repeated call on the same bases also keeps B' spread over
+ * the AO pairs, so it is the two GEMMs and the symmetrisation alone.
  */
 mderi_status mderi_dfk(mderi_ctx_t ctx, mderi_basis_t basis, mderi_basis_t aux, const double *D_dev, double *K_dev,
                        int nao, const mderi_opts *opts, void *stream);

@@ -29,15 +29,25 @@ __global__ void __launch_bounds__(kDfThreads) df_dvec_kernel(int nrow, const int
 }
 
 // gamma[col] = sum_row B[row + nrow col] dvec[row]: one workgroup per column,
-// consecutive rows across the workgroup's threads, tree reduction in LDS.
+// consecutive rows across the workgroup's threads (each wave reads 512
+// contiguous bytes per step), four independent partial sums per thread so
+// that four loads are in flight, then a fixed-order tree in LDS.
 __global__ void __launch_bounds__(kDfThreads) df_gamma_kernel(int nrow, const double *B, const double *dvec,
                                                              double *gamma) {
   __shared__ double part[kDfThreads];
   const int col = blockIdx.x;
   const double *Bc = B + (size_t)nrow * col;
-  double s = 0.0;
-  for (int r = threadIdx.x; r < nrow; r += kDfThreads) s = fma(Bc[r], dvec[r], s);
-  part[threadIdx.x] = s;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  constexpr int step = 4 * kDfThreads;
+  int r = threadIdx.x;
+  for (; r + 3 * kDfThreads < nrow; r += step) {
+    s0 = fma(Bc[r], dvec[r], s0);
+    s1 = fma(Bc[r + kDfThreads], dvec[r + kDfThreads], s1);
+    s2 = fma(Bc[r + 2 * kDfThreads], dvec[r + 2 * kDfThreads], s2);
+    s3 = fma(Bc[r + 3 * kDfThreads], dvec[r + 3 * kDfThreads], s3);
+  }
+  for (; r < nrow; r += kDfThreads) s0 = fma(Bc[r], dvec[r], s0);
+  part[threadIdx.x] = (s0 + s1) + (s2 + s3);
   __syncthreads();
   for (int h = kDfThreads / 2; h > 0; h >>= 1) {
     if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
@@ -49,15 +59,34 @@ __global__ void __launch_bounds__(kDfThreads) df_gamma_kernel(int nrow, const do
 // J rows: jr = sum_col B[row + nrow col] c[col], then J[a][b] = J[b][a] = jr
 // from the rows with a >= b (a diagonal shell pair holds both (a, b) and
 // (b, a), equal up to rounding; the other pairs have a > b throughout), so
-// every element has one writer and J is exactly symmetric
+// every element has one writer and J is exactly symmetric.  A workgroup takes
+// kJRows consecutive rows; its kJParts waves split the columns (wave w takes
+// col = w mod kJParts, two partial sums each) and the parts are added in a
+// fixed order.
+constexpr int kJRows = 64, kJParts = kDfThreads / kJRows;
+
 __global__ void __launch_bounds__(kDfThreads) df_j_kernel(int nrow, int ncol, const double *B, const double *c,
                                                          const int2 *ab, double *J, int nao) {
-  const int r = blockIdx.x * kDfThreads + threadIdx.x;
-  if (r >= nrow) return;
+  __shared__ double part[kJParts][kJRows];
+  const int lane = threadIdx.x % kJRows, w = threadIdx.x / kJRows;
+  const int r = blockIdx.x * kJRows + lane;
+  double s0 = 0.0, s1 = 0.0;
+  if (r < nrow) {
+    const double *Br = B + r;
+    int k = w;
+    for (; k + kJParts < ncol; k += 2 * kJParts) {
+      s0 = fma(Br[(size_t)nrow * k], c[k], s0);
+      s1 = fma(Br[(size_t)nrow * (k + kJParts)], c[k + kJParts], s1);
+    }
+    if (k < ncol) s0 = fma(Br[(size_t)nrow * k], c[k], s0);
+  }
+  part[w][lane] = s0 + s1;
+  __syncthreads();
+  if (w != 0 || r >= nrow) return;
+  double s = part[0][lane];
+  for (int q = 1; q < kJParts; ++q) s += part[q][lane];
   const int2 x = ab[r];
   if (x.x < x.y) return;
-  double s = 0.0;
-  for (int k = 0; k < ncol; ++k) s = fma(B[r + (size_t)nrow * k], c[k], s);
   J[(size_t)x.x * nao + x.y] = s;
   J[(size_t)x.y * nao + x.x] = s;
 }
@@ -125,8 +154,8 @@ hipError_t launch_df_gamma(int nrow, int ncol, const double *B, const double *dv
 hipError_t launch_df_j(int nrow, int ncol, const double *B, const double *c, const int2 *ab, double *J, int nao,
                        hipStream_t s) {
   if (nrow <= 0) return hipSuccess;
-  hipLaunchKernelGGL(df_j_kernel, dim3((nrow + kDfThreads - 1) / kDfThreads), dim3(kDfThreads), 0, s, nrow, ncol, B,
-                     c, ab, J, nao);
+  hipLaunchKernelGGL(df_j_kernel, dim3((nrow + kJRows - 1) / kJRows), dim3(kDfThreads), 0, s, nrow, ncol, B, c, ab, J,
+                     nao);
   return hipGetLastError();
 }
 

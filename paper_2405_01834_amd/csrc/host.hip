@@ -257,6 +257,13 @@ struct mderi_ctx {
     std::shared_ptr<const PairSets> ps;
   };
   std::vector<PairCacheEntry> pair_cache;
+  // density-fitting factors of the last (basis, fitting basis) pair, kept in
+  // the DF work space slots for the next mderi_dfj / mderi_dfk call on the
+  // same pair and geometries: df_stage 0 = none, 1 = the (ab|P) matrix B and
+  // the Cholesky factor L of the metric, 2 = B' = B L^-T in place of B,
+  // 3 = B' also spread over all AO pairs for the exchange contractions
+  uint64_t df_key[4] = {};  // basis serial and geometry, fitting basis serial and geometry
+  int df_stage = 0, df_nrow = 0;
 };
 
 struct mderi_basis {
@@ -510,6 +517,7 @@ extern "C" mderi_status mderi_set_workspace_limit(mderi_ctx_t c, size_t bytes) {
   if (!c) return fail(MDERI_EINVAL, "mderi_set_workspace_limit: NULL context");
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(hipDeviceSynchronize());
+  c->df_stage = 0;  // the kept density-fitting factors go with the work space
   for (int i = 0; i < WS_COUNT; ++i) {
     if (c->ws[i]) HIP_TRY(hipFree(c->ws[i]));
     c->ws[i] = nullptr;
@@ -2497,7 +2505,24 @@ struct DfSetup {
   const double *w = nullptr;
 };
 
+// The factors of the fit for (b, aux): taken from the context when its last
+// density-fitting call had the same bases at the same geometries (df_stage
+// says how far they were carried), else computed (df_stage 1).
 mderi_status df_setup(mderi_ctx *c, mderi_basis *b, mderi_basis *aux, const char *fn, hipStream_t s, DfSetup &df) {
+  const uint64_t key[4] = {b->serial, b->geom, aux->serial, aux->geom};
+  if (c->df_stage && std::equal(key, key + 4, c->df_key)) {
+    if (rocblas_set_stream(c->blas, s) != rocblas_status_success)
+      return fail(MDERI_EDEVICE, "%s: rocblas_set_stream failed", fn);
+    df.nrow = c->df_nrow;
+    df.ncol = aux->nao;
+    df.B = (double *)c->ws[WS_DFB];
+    df.M = (double *)c->ws[WS_DFM];
+    df.vec = (double *)c->ws[WS_DFV];
+    df.ab = (const int2 *)c->ws[WS_DFI];
+    df.w = (const double *)((char *)c->ws[WS_DFI] + sizeof(int2) * (size_t)df.nrow);
+    return MDERI_OK;
+  }
+  c->df_stage = 0;
   std::vector<int32_t> pairs;
   std::vector<int2> ab;
   std::vector<double> w;
@@ -2577,6 +2602,9 @@ mderi_status df_setup(mderi_ctx *c, mderi_basis *b, mderi_basis *aux, const char
   if (rocblas_set_stream(c->blas, s) != rocblas_status_success ||
       rocsolver_dpotrf(c->blas, rocblas_fill_lower, ncol, df.M, ncol, info) != rocblas_status_success)
     return fail(MDERI_EDEVICE, "%s: the metric factorisation could not be enqueued", fn);
+  std::copy(key, key + 4, c->df_key);
+  c->df_nrow = nrow;
+  c->df_stage = 1;
   return MDERI_OK;
 }
 
@@ -2600,12 +2628,14 @@ extern "C" mderi_status mderi_dfj(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t 
   hipStream_t s = (hipStream_t)stream;
   DfSetup df;
   if ((st = df_setup(c, b, aux, "mderi_dfj", s, df))) return st;
-  // fitted charge gamma_Q = sum w (Q|ab) D_ab, c = M^{-1} gamma, J
+  // fitted charge gamma_Q = sum w (Q|ab) D_ab, c = M^{-1} gamma, J; when a
+  // K build left B' = B L^-T in place of B, gamma' = B'^T d = L^-1 gamma
+  // and J = B' gamma' = B M^-1 gamma with no solve
   double *dvec = df.vec, *gamma = dvec + df.nrow;
   HIP_TRY(launch_df_dvec(df.nrow, df.ab, df.w, D, nao, dvec, s));
   HIP_TRY(launch_df_gamma(df.nrow, df.ncol, df.B, dvec, gamma, s));
-  if (rocsolver_dpotrs(c->blas, rocblas_fill_lower, df.ncol, 1, df.M, df.ncol, gamma, df.ncol) !=
-      rocblas_status_success)
+  if (c->df_stage < 2 && rocsolver_dpotrs(c->blas, rocblas_fill_lower, df.ncol, 1, df.M, df.ncol, gamma,
+                                          df.ncol) != rocblas_status_success)
     return fail(MDERI_EDEVICE, "mderi_dfj: the metric solve could not be enqueued");
   HIP_TRY(launch_df_j(df.nrow, df.ncol, df.B, gamma, df.ab, J, nao, s));
   return MDERI_OK;
@@ -2630,15 +2660,23 @@ extern "C" mderi_status mderi_dfk(mderi_ctx_t c, mderi_basis_t b, mderi_basis_t 
   const double one = 1.0, half = 0.5, zero = 0.0;
   const rocblas_int m = nao, k2 = (rocblas_int)(naux * nao);
   // B' = B L^{-T}: the fitted integrals are (ab|cd)_fit = sum_Q B'[ab][Q] B'[cd][Q]
-  if (rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
-                    rocblas_diagonal_non_unit, df.nrow, df.ncol, &one, df.M, df.ncol, df.B, df.nrow) !=
-      rocblas_status_success)
-    return fail(MDERI_EDEVICE, "mderi_dfk: the triangular solve could not be enqueued");
+  if (c->df_stage < 2) {
+    if (rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                      rocblas_diagonal_non_unit, df.nrow, df.ncol, &one, df.M, df.ncol, df.B, df.nrow) !=
+        rocblas_status_success) {
+      c->df_stage = 0;  // B may be half transformed
+      return fail(MDERI_EDEVICE, "mderi_dfk: the triangular solve could not be enqueued");
+    }
+    c->df_stage = 2;
+  }
   // Bt[(a naux + Q) nao + b] = B'_Q[a][b] over all AO pairs, then
   // X[(a naux + Q) nao + d] = sum_b D[d][b] B'_Q[a][b]  (one GEMM, k = nao)
   // K~[c + nao a] = 1/2 sum_{Q,d} B'_Q[c][d] X_Q[a][d]  (one GEMM, k = naux nao)
   // and K = K~ + K~^T = sum_Q B'_Q D B'_Q^T, exactly symmetric
-  HIP_TRY(launch_df_expand(df.nrow, df.ncol, df.B, df.ab, df.w, nao, Bt, s));
+  if (c->df_stage < 3) {
+    HIP_TRY(launch_df_expand(df.nrow, df.ncol, df.B, df.ab, df.w, nao, Bt, s));
+    c->df_stage = 3;
+  }
   if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, m, k2, m, &one, D, m, Bt, m, &zero, X,
                     m) != rocblas_status_success ||
       rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, m, m, k2, &half, Bt, k2, X, k2,
