@@ -2248,11 +2248,27 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
     ar.wave_doubles = ar.o_tab + (ar.uv_max + ar.oq_max + 2 * ar.op_max + 1) / 2 + 1;
     ar.wave_doubles = even(ar.wave_doubles);
     const size_t wave_bytes = sizeof(double) * (size_t)ar.wave_doubles;
-    g.waves = (int)std::min<size_t>(4, (160 * 1024) / wave_bytes);
-    if (g.waves < 1)
+    if (wave_bytes > 160 * 1024)
       return fail(MDERI_EUNSUPPORTED, "quartet engine: a wave needs %zu bytes of LDS (over 160 KiB)", wave_bytes);
+    // waves are independent (each has its own LDS region and takes its own
+    // chunks), so the workgroup size only decides how many waves the CU's
+    // LDS holds: 4 per workgroup leaves up to 3 waves' worth unused.  Take
+    // the size that holds the most waves, counting at most the waves the
+    // registers allow (the digest's 72-104 VGPRs: 32 per CU are counted, as
+    // the grid always did; the gradient's up to 256: 8), ties going to the
+    // larger workgroup.
+    const size_t wave_cap = job.grad ? 8 : 32;
+    g.waves = 1;
+    size_t best = 0;
+    for (int w = 4; w >= 1; --w) {
+      const size_t tot = std::min<size_t>(wave_cap, w * ((160 * 1024) / (wave_bytes * w)));
+      if (tot > best) {
+        best = tot;
+        g.waves = w;
+      }
+    }
     g.lds = wave_bytes * g.waves;
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / g.lds));
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(wave_cap / g.waves, (160 * 1024) / g.lds));
     // chunks: at least ~6e5 cycles each (the per-chunk search and table
     // set-up stay small), and larger where the group's work allows about 16
     // chunks per resident wave (longer runs of one A pair); blocks run
