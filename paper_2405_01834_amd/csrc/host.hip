@@ -2269,11 +2269,13 @@ mderi_status run_kx(mderi_ctx *c, mderi_basis *b, const PairSets &ps, double tau
     }
     g.lds = wave_bytes * g.waves;
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(wave_cap / g.waves, (160 * 1024) / g.lds));
-    // chunks: at least ~6e5 cycles each (the per-chunk search and table
-    // set-up stay small), and larger where the group's work allows about 16
-    // chunks per resident wave (longer runs of one A pair); blocks run
-    // heaviest first, so the tail is made of the cheapest block's chunks
-    const double per_chunk = std::max(6e5, work / (16.0 * 256.0 * per_cu * g.waves));
+    // chunks: at least ~7.5e4 cycles each (the per-chunk search and table
+    // set-up stay small), and larger where the group's work allows about
+    // 128 chunks per resident wave (measured on the 40-atom cluster: 16
+    // and 32 per wave were 1-3% slower for the K build and the gradient);
+    // blocks run heaviest first, so the tail is made of the cheapest
+    // block's chunks
+    const double per_chunk = std::max(7.5e4, work / (128.0 * 256.0 * per_cu * g.waves));
     long chunk0 = 0;
     for (size_t j = 0; j < gr.second.size(); ++j) {
       const KxPlanBlock &pb = blocks[gr.second[j]];
